@@ -1,0 +1,85 @@
+// Internal declarations shared by the lupp HIP sources (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lupp.h"
+
+namespace lupp {
+
+// ---------------------------------------------------------------- MFMA traits
+// v_mfma_*_16x16x4: operand "a" lane l holds X[l%16][l/16] (16x4), operand "b"
+// lane l holds Y[l/16][l%16] (4x16).  The GEMM feeds a = B-fragment and
+// b = A-fragment, so the 16x16 result is C^T: lane l then holds C rows l%16
+// (16 consecutive rows: coalesced column segments) and the column given by
+// col(l, r) -- the FP64 and FP32 instructions place their four result
+// registers differently (measured on gfx950).
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int col(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int col(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+// ---------------------------------------------------------------- workspace
+// Device-resident state of the cooperative panel kernel: one slot per
+// workgroup with its pivot candidate and the candidate's row, a copy of the
+// current diagonal row, per-workgroup progress flags and an error flag.
+constexpr int kLeafMaxGroups = 128;
+constexpr int kLeafMaxWidth = 32;
+
+struct LeafSlots {
+  uint32_t flags[kLeafMaxGroups];                  // progress flag per workgroup
+  int32_t err;                                     // set when a bounded wait expires
+  int32_t pad_[31];
+  double cand_val[2][kLeafMaxGroups];              // |candidate|, double-buffered by column parity
+  int64_t cand_idx[2][kLeafMaxGroups];             // candidate row (panel-local)
+  double cand_row[2][kLeafMaxGroups][kLeafMaxWidth];  // candidate row values (T stored as double)
+  double rowj[2][kLeafMaxWidth];                   // the diagonal row before the interchange
+};
+
+// ---------------------------------------------------------------- launchers
+// C[M x N] -= A[M x K] * B[K x N], column-major (A, B and C must not overlap).
+template <typename T>
+hipError_t gemm_sub(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda,
+                    const T* B, int64_t ldb, T* C, int64_t ldc);
+
+// Factor the r x w column block P (leading dimension ld) whose first row and
+// column are the global row/column k: partial pivoting column by column, the
+// interchanges applied across the w columns of the block.  Writes
+// ipiv[k + j] = k + piv + 1 and, on the first exactly zero pivot, *info.
+template <typename T>
+hipError_t panel_leaf(hipStream_t s, int64_t r, int w, T* P, int64_t ld, int32_t* ipiv, int64_t k,
+                      int32_t* info, LeafSlots* ws, uint32_t epoch);
+
+// Apply interchanges k1..k2-1 (ipiv, 1-based rows of the m-row matrix A) to
+// columns [c0, c1) of A except the columns [skip0, skip1).
+template <typename T>
+hipError_t laswp(hipStream_t s, T* A, int64_t lda, int64_t m, int64_t c0, int64_t c1, int64_t skip0, int64_t skip1,
+                 const int32_t* ipiv, int64_t k1, int64_t k2);
+
+// Triangular solve on a w x ncols block (w <= 64): lower=true solves with a
+// unit lower triangle (forward), lower=false with a non-unit upper triangle.
+template <typename T>
+hipError_t trsm_leaf(hipStream_t s, bool lower, int64_t w, int64_t ncols, const T* L, int64_t ldl, T* B,
+                     int64_t ldb);
+
+hipError_t set_int(hipStream_t s, int32_t* p, int32_t v);
+hipError_t reset_flags(hipStream_t s, LeafSlots* ws);
+
+}  // namespace lupp

@@ -1,0 +1,265 @@
+// C ABI and host-side drivers of the blocked right-looking LU with partial
+// pivoting (declarations and conventions: include/lupp.h).
+//
+// The loop is the paper's FLAME loop (Section 4.3: partition A into
+// A_TL, A_TR, A_BL, A_BR with A_TL empty; while A_TL does not cover A,
+// repartition with a b x b block A11, b = min(nb, n(A_BR)); update; continue
+// with the boundaries moved past A11), instantiated for LU:
+//   [A11; A21], p1 := LUPP([A11; A21])        column block (recursive)
+//   apply p1 to [A10; A20] and [A12; A22]      laswp
+//   A12 := inv(L11) * A12                       trsm (recursive, GEMM inside)
+//   A22 := A22 - A21 * A12                      GEMM on MFMA
+// Loop invariant after a step with A_TL of order k: the top k rows and left k
+// columns hold L_TL\U_TL, U_TR and L_BL of P_k*A, and A_BR holds its Schur
+// complement P_k*A_BR - L_BL*U_TR.
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <new>
+
+#include "common.h"
+
+struct lupp_handle_st {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t nb = 256;
+  int leaf = 32;
+  lupp::LeafSlots* slots = nullptr;
+  uint32_t epoch = 0;
+};
+
+namespace lupp {
+namespace {
+
+inline int hip_status(hipError_t e) { return e == hipSuccess ? LUPP_OK : LUPP_ERR_HIP + (int)e; }
+
+#define LUPP_TRY(expr)                       \
+  do {                                       \
+    hipError_t e_ = (expr);                  \
+    if (e_ != hipSuccess) return e_;         \
+  } while (0)
+
+// Epoch of the panel kernel's progress flags: every launch uses flag values
+// above all values written before; the flags are cleared before wrap-around.
+inline hipError_t next_epoch(lupp_handle_t h, int w, uint32_t* out) {
+  if (h->epoch > 0xF0000000u) {
+    LUPP_TRY(reset_flags(h->stream, h->slots));
+    h->epoch = 0;
+  }
+  *out = h->epoch;
+  h->epoch += (uint32_t)w + 1u;
+  return hipSuccess;
+}
+
+// B (w x ncols) := inv(L) * B with L unit lower triangular (w x w).
+template <typename T>
+hipError_t trsm_lower_unit(hipStream_t s, int64_t w, int64_t ncols, const T* L, int64_t ldl, T* B, int64_t ldb) {
+  if (w <= 64) return trsm_leaf<T>(s, true, w, ncols, L, ldl, B, ldb);
+  const int64_t w1 = w / 2;
+  LUPP_TRY(trsm_lower_unit<T>(s, w1, ncols, L, ldl, B, ldb));
+  LUPP_TRY(gemm_sub<T>(s, w - w1, ncols, w1, L + w1, ldl, B, ldb, B + w1, ldb));
+  return trsm_lower_unit<T>(s, w - w1, ncols, L + w1 + w1 * ldl, ldl, B + w1, ldb);
+}
+
+// B (w x ncols) := inv(U) * B with U upper triangular, non-unit (w x w).
+template <typename T>
+hipError_t trsm_upper(hipStream_t s, int64_t w, int64_t ncols, const T* U, int64_t ldu, T* B, int64_t ldb) {
+  if (w <= 64) return trsm_leaf<T>(s, false, w, ncols, U, ldu, B, ldb);
+  const int64_t w1 = w / 2;
+  LUPP_TRY(trsm_upper<T>(s, w - w1, ncols, U + w1 + w1 * ldu, ldu, B + w1, ldb));
+  LUPP_TRY(gemm_sub<T>(s, w1, ncols, w - w1, U + w1 * ldu, ldu, B + w1, ldb, B, ldb));
+  return trsm_upper<T>(s, w1, ncols, U, ldu, B, ldb);
+}
+
+// Recursive column-block factorization of columns [k, k+w), rows [k, m).
+template <typename T>
+hipError_t panel(lupp_handle_t h, int64_t m, int64_t k, int64_t w, T* A, int64_t lda, int32_t* ipiv, int32_t* info) {
+  hipStream_t s = h->stream;
+  if (w <= h->leaf) {
+    uint32_t ep;
+    LUPP_TRY(next_epoch(h, (int)w, &ep));
+    return panel_leaf<T>(s, m - k, (int)w, A + k + k * lda, lda, ipiv, k, info, h->slots, ep);
+  }
+  int64_t w1 = w / 2;
+  if (w1 > 8) w1 = (w1 / 8) * 8;
+  const int64_t w2 = w - w1;
+  LUPP_TRY(panel<T>(h, m, k, w1, A, lda, ipiv, info));
+  LUPP_TRY(laswp<T>(s, A, lda, m, k + w1, k + w, 0, 0, ipiv, k, k + w1));
+  LUPP_TRY(trsm_lower_unit<T>(s, w1, w2, A + k + k * lda, lda, A + k + (k + w1) * lda, lda));
+  LUPP_TRY(gemm_sub<T>(s, m - k - w1, w2, w1, A + (k + w1) + k * lda, lda, A + k + (k + w1) * lda, lda,
+                       A + (k + w1) + (k + w1) * lda, lda));
+  LUPP_TRY(panel<T>(h, m, k + w1, w2, A, lda, ipiv, info));
+  return laswp<T>(s, A, lda, m, k, k + w1, 0, 0, ipiv, k + w1, k + w);
+}
+
+template <typename T>
+hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32_t* ipiv, int32_t* info) {
+  hipStream_t s = h->stream;
+  LUPP_TRY(set_int(s, info, 0));
+  const int64_t p = m < n ? m : n;
+  for (int64_t k = 0; k < p; k += h->nb) {
+    const int64_t b = (p - k < h->nb) ? (p - k) : h->nb;
+    LUPP_TRY(panel<T>(h, m, k, b, A, lda, ipiv, info));
+    // interchanges of this block on every column outside it
+    LUPP_TRY(laswp<T>(s, A, lda, m, 0, n, k, k + b, ipiv, k, k + b));
+    if (k + b < n) {
+      LUPP_TRY(trsm_lower_unit<T>(s, b, n - k - b, A + k + k * lda, lda, A + k + (k + b) * lda, lda));
+      if (k + b < m)
+        LUPP_TRY(gemm_sub<T>(s, m - k - b, n - k - b, b, A + (k + b) + k * lda, lda, A + k + (k + b) * lda, lda,
+                             A + (k + b) + (k + b) * lda, lda));
+    }
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t getrs(lupp_handle_t h, int64_t n, int64_t nrhs, const T* LU, int64_t lda, const int32_t* ipiv, T* B,
+                 int64_t ldb) {
+  hipStream_t s = h->stream;
+  LUPP_TRY(laswp<T>(s, B, ldb, n, 0, nrhs, 0, 0, ipiv, 0, n));
+  LUPP_TRY(trsm_lower_unit<T>(s, n, nrhs, LU, lda, B, ldb));
+  return trsm_upper<T>(s, n, nrhs, LU, lda, B, ldb);
+}
+
+hipError_t ensure_workspace(lupp_handle_t h) {
+  if (h->slots) return hipSuccess;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, sizeof(LeafSlots));
+  if (e != hipSuccess) return e;
+  e = hipMemset(p, 0, sizeof(LeafSlots));
+  if (e != hipSuccess) {
+    (void)hipFree(p);
+    return e;
+  }
+  h->slots = (LeafSlots*)p;
+  h->epoch = 0;
+  return hipSuccess;
+}
+
+template <typename T>
+int getrf_entry(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32_t* ipiv, int32_t* info) {
+  if (!h) return -1;
+  if (m < 0 || m >= ((int64_t)1 << 31)) return -2;
+  if (n < 0) return -3;
+  if (!A && m > 0 && n > 0) return -4;
+  if (lda < (m > 1 ? m : 1)) return -5;
+  if (!ipiv && m > 0 && n > 0) return -6;
+  if (!info) return -7;
+  if (m - 0 > (int64_t)kLeafMaxGroups * 256 * 4) return LUPP_ERR_UNSUPPORTED;
+  hipError_t e = ensure_workspace(h);
+  if (e != hipSuccess) return LUPP_ERR_ALLOC;
+  return hip_status(getrf<T>(h, m, n, A, lda, ipiv, info));
+}
+
+template <typename T>
+int getrs_entry(lupp_handle_t h, char trans, int64_t n, int64_t nrhs, const T* LU, int64_t lda, const int32_t* ipiv,
+                T* B, int64_t ldb) {
+  if (!h) return -1;
+  if (trans != 'N' && trans != 'n') return -2;
+  if (n < 0 || n >= ((int64_t)1 << 31)) return -3;
+  if (nrhs < 0) return -4;
+  if (!LU && n > 0) return -5;
+  if (lda < (n > 1 ? n : 1)) return -6;
+  if (!ipiv && n > 0) return -7;
+  if (!B && n > 0 && nrhs > 0) return -8;
+  if (ldb < (n > 1 ? n : 1)) return -9;
+  if (n == 0 || nrhs == 0) return LUPP_OK;
+  return hip_status(getrs<T>(h, n, nrhs, LU, lda, ipiv, B, ldb));
+}
+
+}  // namespace
+}  // namespace lupp
+
+extern "C" {
+
+int lupp_create(lupp_handle_t* h) {
+  if (!h) return -1;
+  lupp_handle_st* p = new (std::nothrow) lupp_handle_st();
+  if (!p) return LUPP_ERR_ALLOC;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return lupp::hip_status(e);
+  }
+  *h = p;
+  return LUPP_OK;
+}
+
+int lupp_destroy(lupp_handle_t h) {
+  if (!h) return -1;
+  int rc = LUPP_OK;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) rc = lupp::hip_status(e);
+  if (h->slots) (void)hipFree(h->slots);
+  delete h;
+  return rc;
+}
+
+int lupp_set_stream(lupp_handle_t h, void* stream) {
+  if (!h) return -1;
+  h->stream = (hipStream_t)stream;
+  return LUPP_OK;
+}
+
+int lupp_set_option(lupp_handle_t h, int option, int64_t value) {
+  if (!h) return -1;
+  switch (option) {
+    case LUPP_OPT_NB:
+      if (value < 1 || value > 4096) return -3;
+      h->nb = value;
+      return LUPP_OK;
+    case LUPP_OPT_PANEL_LEAF:
+      if (value != 8 && value != 16 && value != 32) return -3;
+      h->leaf = (int)value;
+      return LUPP_OK;
+    default:
+      return -2;
+  }
+}
+
+int lupp_sync(lupp_handle_t h) {
+  if (!h) return -1;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return lupp::hip_status(e);
+  if (h->slots) {
+    int32_t err = 0;
+    e = hipMemcpy(&err, &h->slots->err, sizeof(err), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return lupp::hip_status(e);
+    if (err) {
+      const int32_t zero = 0;
+      (void)hipMemcpy(&h->slots->err, &zero, sizeof(zero), hipMemcpyHostToDevice);
+      return LUPP_ERR_INTERNAL;
+    }
+  }
+  return LUPP_OK;
+}
+
+const char* lupp_status_string(int status) {
+  if (status == LUPP_OK) return "success";
+  if (status < 0) return "invalid argument";
+  if (status == LUPP_ERR_ALLOC) return "workspace allocation failed";
+  if (status == LUPP_ERR_INTERNAL) return "device-side wait expired";
+  if (status == LUPP_ERR_UNSUPPORTED) return "unsupported size or option";
+  if (status > LUPP_ERR_HIP && status < LUPP_ERR_ALLOC) return hipGetErrorString((hipError_t)(status - LUPP_ERR_HIP));
+  return "unknown status";
+}
+
+int lupp_dgetrf(lupp_handle_t h, int64_t m, int64_t n, double* dA, int64_t lda, int32_t* dipiv, int32_t* dinfo) {
+  return lupp::getrf_entry<double>(h, m, n, dA, lda, dipiv, dinfo);
+}
+
+int lupp_sgetrf(lupp_handle_t h, int64_t m, int64_t n, float* dA, int64_t lda, int32_t* dipiv, int32_t* dinfo) {
+  return lupp::getrf_entry<float>(h, m, n, dA, lda, dipiv, dinfo);
+}
+
+int lupp_dgetrs(lupp_handle_t h, char trans, int64_t n, int64_t nrhs, const double* dLU, int64_t lda,
+                const int32_t* dipiv, double* dB, int64_t ldb) {
+  return lupp::getrs_entry<double>(h, trans, n, nrhs, dLU, lda, dipiv, dB, ldb);
+}
+
+int lupp_sgetrs(lupp_handle_t h, char trans, int64_t n, int64_t nrhs, const float* dLU, int64_t lda,
+                const int32_t* dipiv, float* dB, int64_t ldb) {
+  return lupp::getrs_entry<float>(h, trans, n, nrhs, dLU, lda, dipiv, dB, ldb);
+}
+
+}  // extern "C"

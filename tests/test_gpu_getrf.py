@@ -1,0 +1,189 @@
+"""GPU parity of the HIP LU path against the CPU oracle (through the C ABI).
+
+Bars (floating point decides integers here, so pivots are compared where the
+oracle's pivot column is separated by a relative gap >= tau, on every step up
+to the first non-separated one):
+  * ipiv identical to the oracle's on the separated prefix;
+  * scaled residual ||PA - LU||_1 / (n eps ||A||_1) < 10 for the GPU factors
+    (eps = 2^-53 FP64, 2^-24 FP32), |L| <= 1;
+  * closed forms bit-exact at any size (Pi*D pivots; exactly factorable
+    dyadic matrices: ipiv, L and U bit for bit);
+  * solve: normwise backward error <= 8 n u.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import checks
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - GPU machine only
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2104_05782_amd as lupp  # noqa: E402
+from gpu_util import announce, to_dev, to_host  # noqa: E402
+
+TAU = 1e-9
+
+
+def _oracle():
+    import oracle
+    return oracle
+
+
+def _gpu_factor(A, nb=None, leaf=None):
+    h = lupp.Handle()
+    if nb:
+        h.set_option(1, nb)
+    if leaf:
+        h.set_option(2, leaf)
+    dA = to_dev(A)
+    ipiv, info = lupp.getrf(dA, handle=h)
+    h.sync()
+    torch.cuda.synchronize()
+    out = to_host(dA), ipiv.cpu().numpy(), int(info.item())
+    h.close()
+    return out
+
+
+def _check_against_oracle(A, LU, ipiv, info, eps, tau=TAU, nthreads=8):
+    o = _oracle()
+    LUo, ipo, info_o, gap = o.getrf(A, with_gap=True, nthreads=nthreads)
+    assert info == info_o
+    ok, cmp, first = checks.pivot_prefix_match(ipiv, ipo, gap, tau)
+    assert ok, "pivot mismatch at step %d (compared %d, min gap %.3g)" % (first, cmp, float(np.min(gap, initial=1)))
+    L, U = checks.unpack(LU)
+    assert np.abs(L).max(initial=0.0) <= 1.0
+    res = checks.scaled_residual(A, LU, ipiv, eps)
+    assert res < 10, res
+    return cmp
+
+
+def test_config1_n512_fp64():
+    """n = 512, A and b iid U(-1,1): pivots bit-exact, residual, solve."""
+    n = 512
+    announce("config1 n=512 fp64")
+    A = synth.uniform(synth.DEFAULT_SEED, 0, n, n)
+    b = synth.uniform(synth.DEFAULT_SEED, 1, n, 1)[:, 0]
+    LU, ipiv, info = _gpu_factor(A)
+    cmp = _check_against_oracle(A, LU, ipiv, info, checks.U64)
+    assert cmp == n
+    dLU = to_dev(LU)
+    dip = torch.from_numpy(ipiv).cuda()
+    db = torch.from_numpy(b.copy()).cuda()
+    lupp.getrs(dLU, dip, db)
+    x = db.cpu().numpy()
+    assert checks.backward_error(A, x, b) <= 8 * n * checks.U64
+    LUo, ipo, _ = _oracle().getrf(A)
+    xo, _ = _oracle().getrs(LUo, ipo, b)
+    kappa = np.linalg.cond(A, 1)
+    assert np.abs(x - xo).max() / np.abs(xo).max() <= 16 * n * kappa * checks.U64
+
+
+SHAPES = [(1, 1), (2, 2), (3, 7), (7, 3), (33, 33), (64, 64), (100, 100), (257, 257), (300, 200), (200, 300),
+          (1000, 1000), (1025, 1025), (1500, 700), (700, 1500)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_ragged_shapes(shape, dtype):
+    m, n = shape
+    announce("ragged %dx%d %s" % (m, n, dtype))
+    A = synth.uniform(7, 3, m, n)
+    if dtype == "f32":
+        A = A.astype(np.float32)
+    for nb, leaf in ((None, None), (64, 16), (96, 8)):
+        LU, ipiv, info = _gpu_factor(A, nb, leaf)
+        _check_against_oracle(A, LU, ipiv, info, checks.U64 if dtype == "f64" else checks.U32,
+                              tau=TAU if dtype == "f64" else 1e-4)
+
+
+@pytest.mark.parametrize("n", [2048, 4096])
+def test_multi_group_panels(n):
+    """r > 1024 rows: the panel leaf runs with several cooperating workgroups."""
+    announce("multi-group n=%d" % n)
+    A = synth.uniform(11, 0, n, n)
+    LU, ipiv, info = _gpu_factor(A)
+    cmp = _check_against_oracle(A, LU, ipiv, info, checks.U64, nthreads=16)
+    assert cmp >= n - 4
+
+
+def test_empty():
+    announce("empty")
+    for (m, n) in ((0, 0), (0, 5), (5, 0)):
+        dA = torch.zeros((max(n, 1), max(m, 1)), dtype=torch.float64, device="cuda").t()[:m, :n]
+        ipiv = torch.zeros(1, dtype=torch.int32, device="cuda")
+        info = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+        lupp.lupp_dgetrf(dA, ipiv, info)
+        torch.cuda.synchronize()
+        assert int(info.item()) == 0
+
+
+def test_zero_column_info():
+    announce("zero column")
+    A = synth.uniform(4, 1, 300, 300)
+    A[:, 77] = 0.0
+    A[:, 200] = 0.0
+    LU, ipiv, info = _gpu_factor(A)
+    assert info == 78
+    LUo, ipo, info_o = _oracle().getrf(A)
+    assert info_o == 78
+
+
+def test_zero_matrix():
+    announce("zero matrix")
+    LU, ipiv, info = _gpu_factor(np.zeros((70, 70)))
+    assert info == 1 and np.array_equal(ipiv, np.arange(1, 71)) and not np.any(LU)
+
+
+@pytest.mark.parametrize("n", [100, 1000, 3000])
+def test_exact_factorable_bit_exact(n):
+    """A = Pi^T L U with dyadic factors: every value is exact, so the GPU must
+    return the constructed ipiv, L and U bit for bit (FP64 and FP32)."""
+    announce("exact-factorable n=%d" % n)
+    A, L, U, perm = synth.exact_lu_product(8, 30, n)
+    for dt in (np.float64, np.float32):
+        LU, ipiv, info = _gpu_factor(A.astype(dt))
+        assert info == 0
+        assert np.array_equal(ipiv, checks.closed_form_ipiv(perm))
+        Lg, Ug = checks.unpack(LU)
+        assert np.array_equal(Lg, L) and np.array_equal(Ug, U)
+
+
+@pytest.mark.parametrize("n", [500, 4096])
+def test_pi_d_closed_form(n):
+    announce("Pi*D n=%d" % n)
+    A, perm = synth.pi_times_coldom(21, 4, n)
+    LU, ipiv, info = _gpu_factor(A)
+    assert info == 0
+    assert np.array_equal(ipiv, checks.closed_form_ipiv(perm))
+    assert checks.scaled_residual(A, LU, ipiv) < 10
+
+
+def test_deterministic():
+    announce("determinism n=1500")
+    A = synth.uniform(3, 3, 1500, 1500)
+    a1, p1, _ = _gpu_factor(A)
+    a2, p2, _ = _gpu_factor(A)
+    assert np.array_equal(p1, p2) and np.array_equal(a1.view(np.int64), a2.view(np.int64))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_getrs_multi_rhs(dtype):
+    n, nrhs = 777, 5
+    announce("getrs n=%d nrhs=%d %s" % (n, nrhs, dtype))
+    npdt = np.float64 if dtype == "f64" else np.float32
+    A = synth.uniform(5, 0, n, n).astype(npdt)
+    B = synth.uniform(5, 1, n, nrhs).astype(npdt)
+    dA = to_dev(A)
+    ipiv, info = lupp.getrf(dA)
+    dB = to_dev(B)
+    lupp.getrs(dA, ipiv, dB)
+    torch.cuda.synchronize()
+    X = to_host(dB)
+    u = checks.U64 if dtype == "f64" else checks.U32
+    for j in range(nrhs):
+        assert checks.backward_error(A.astype(np.float64), X[:, j].astype(np.float64),
+                                     B[:, j].astype(np.float64)) <= 8 * n * u
