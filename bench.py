@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark: LU with partial pivoting, FP64, n = 32768, on one MI355X.
+
+One step = one blocked right-looking factorization P*A = L*U of the whole
+n x n matrix (column-block factorization, interchanges, triangular solve and
+trailing update for every block of columns) through the C ABI.  The input is
+the seeded synthetic matrix A with iid U(-1,1) entries (the paper evaluates on
+randomly generated dense matrices); it is resident in HBM before timing, and
+each step first restores it with a device-to-device copy (inside the step, so
+the reported rate is slightly pessimistic).
+
+The JSON line carries:
+  value       2/3 n^3 / (mean step time), TFLOP/s
+  roofline    the trailing-update GEMM (128x128-tile kernel): its algorithmic
+              flops 2*M*N*K summed over its launches in the timed steps,
+              divided by the summed launch durations from HIP events recorded
+              on the library's stream, against MI355X's FP64 MFMA peak
+  cpu_baseline  the CPU oracle (unblocked FP64 LUPP, all host cores) on a
+              bounded sample: its first S elimination steps on the same matrix
+  check       info, pivot-closed-form and residual checks of the last step
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def probe_residual(torch, A0, LU, ipiv, nprobe=8, seed=5):
+    """||P A X - L (U X)||_1 / (n u ||A||_1 ||X||_1) with an FP64 random probe
+    X (n x nprobe); products formed with torch.matmul (rocBLAS), independent
+    of the library."""
+    n = A0.shape[0]
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    X = torch.rand((n, nprobe), generator=g, dtype=torch.float64, device="cuda") * 2 - 1
+    perm = torch.arange(n, device="cuda")
+    piv = (ipiv.long() - 1).cpu().numpy()
+    p = np.arange(n)
+    for k, v in enumerate(piv):
+        if v != k:
+            p[k], p[v] = p[v], p[k]
+    perm = torch.from_numpy(p).cuda()
+    PAX = A0[perm, :] @ X
+    U = torch.triu(LU)
+    UX = U @ X
+    del U
+    L = torch.tril(LU, -1)
+    L.diagonal().fill_(1.0)
+    LUX = L @ UX
+    del L
+    r = (PAX - LUX).abs().sum(0).max().item()
+    na = A0.abs().sum(0).max().item()
+    nx = X.abs().sum(0).max().item()
+    return r / (n * 2.0 ** -53 * na * nx)
+
+
+def cpu_baseline(A_host, budget_s=15.0):
+    """Oracle (unblocked, threaded over trailing columns) on the first S steps
+    of the same factorization; rate in TFLOP/s of the steps done."""
+    import oracle
+    n = A_host.shape[0]
+    cores = oracle.host_cores()
+    # one step to size the sample (oracle.getrf factors a private copy)
+    t = time.perf_counter()
+    oracle.getrf(A_host, ksteps=1, nthreads=cores)
+    t1 = time.perf_counter() - t
+    steps = int(max(2, min(512, budget_s / max(t1, 1e-3))))
+    t = time.perf_counter()
+    oracle.getrf(A_host, ksteps=steps, nthreads=cores)
+    dt = time.perf_counter() - t
+    flops = sum(2.0 * (n - k - 1) ** 2 + (n - k - 1) for k in range(steps))
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": "first %d elimination steps of the same n=%d FP64 factorization (%.1f s, %.3g flop)"
+            % (steps, n, dt, flops)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=32768)
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--nb", type=int, default=0)
+    ap.add_argument("--seed", type=int, default=20210513)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2104_05782_amd as lupp
+
+    n = args.n
+    npdt = np.float64 if args.dtype == "f64" else np.float32
+    tdt = torch.float64 if args.dtype == "f64" else torch.float32
+    log("generating A (n=%d, seed=%d)" % (n, args.seed))
+    t = time.time()
+    A_host = synth.uniform(args.seed, 0, n, n)
+    if npdt != np.float64:
+        A_host = np.asfortranarray(A_host.astype(npdt))
+    log("generated in %.1f s; uploading" % (time.time() - t))
+    A0 = torch.from_numpy(np.ascontiguousarray(A_host.T)).cuda().t()  # column-major, pristine
+    A = torch.empty_like(A0.t()).t()
+    ipiv = torch.empty(n, dtype=torch.int32, device="cuda")
+    info = torch.empty(1, dtype=torch.int32, device="cuda")
+    h = lupp.Handle()
+    if args.nb:
+        h.set_option(1, args.nb)
+    fn = lupp.lupp_dgetrf if args.dtype == "f64" else lupp.lupp_sgetrf
+
+    def step():
+        A.copy_(A0)
+        fn(A, ipiv, info, handle=h)
+
+    for w in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log("warmup %d done" % w)
+    h.set_option(3, 1)  # record phase events during the timed steps
+    h.timing_summary("panel", reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    h.sync()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    flops = 2.0 / 3.0 * float(n) ** 3
+    value = flops / (ms_per_step * 1e-3) / 1e12
+    log("timed %d steps: %.2f ms/step, %.2f TFLOP/s" % (args.steps, ms_per_step, value))
+    phases = {}
+    for ph in ("panel", "laswp", "trsm", "update", "update_big"):
+        c, ms, fl = h.timing_summary(ph)
+        phases[ph] = {"launches": c, "ms_per_step": ms / args.steps, "flops": fl / args.steps}
+    c, ms, fl = h.timing_summary("update_big", reset=True)
+    peak = FP64_PEAK_TFLOPS if args.dtype == "f64" else FP32_PEAK_TFLOPS
+    achieved = (fl / (ms * 1e-3) / 1e12) if ms > 0 else 0.0
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": "k_gemm_sub<%s,128,128,16,2,2>" % ("double" if args.dtype == "f64" else "float"),
+                "launches_per_step": c // max(1, args.steps),
+                "avg_launch_ms": round(ms / max(1, c), 4),
+                "flops_per_launch": fl / max(1, c)}
+    h.set_option(3, 0)
+
+    check = None
+    if not args.no_check:
+        inf = int(info.item())
+        res = probe_residual(torch, A0.double(), A.double(), ipiv) if n <= 32768 else None
+        check = {"info": inf, "probe_scaled_residual": res}
+        log("check: %s" % check)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        cpu = cpu_baseline(A_host)
+        log("cpu baseline: %s" % cpu)
+
+    out = {
+        "metric": "LU TFLOP/s @n=32768: FP64 vs mixed+IR at FP64 backward err; batched LUs/s",
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.dtype == "f64" else "f32",
+        "data": "synthetic: A iid U(-1,1) from seed %d (Philox-4x64-10)" % args.seed,
+        "config": {"workload": "plain blocked LUPP FP64 n=%d" % n if args.dtype == "f64"
+                   else "plain blocked LUPP FP32 n=%d" % n,
+                   "n": n, "nb": args.nb or 256, "flops_per_step": flops, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "phases": phases,
+        "check": check,
+    }
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
+if __name__ == "__main__":
+    main()

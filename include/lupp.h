@@ -52,8 +52,18 @@ enum {
 
 /* Options for lupp_set_option. */
 enum {
-  LUPP_OPT_NB = 1,        /* outer block size b of the right-looking loop (default 256) */
-  LUPP_OPT_PANEL_LEAF = 2 /* column width at which the recursive panel stops (8/16/32)   */
+  LUPP_OPT_NB = 1,         /* outer block size b of the right-looking loop (default 256)  */
+  LUPP_OPT_PANEL_LEAF = 2, /* column width at which the recursive panel stops (8/16/32)    */
+  LUPP_OPT_TIMING = 3      /* 1: record HIP events around every phase of xGETRF (below)    */
+};
+
+/* Phases reported by lupp_timing_summary. */
+enum {
+  LUPP_PHASE_PANEL = 0,     /* recursive column-block factorization          */
+  LUPP_PHASE_LASWP = 1,     /* interchanges applied outside the column block */
+  LUPP_PHASE_TRSM = 2,      /* U12 := inv(L11) * A12                         */
+  LUPP_PHASE_UPDATE = 3,    /* A22 := A22 - A21 * U12, every launch          */
+  LUPP_PHASE_UPDATE_BIG = 4 /* the same, launches of the 128x128-tile kernel */
 };
 
 /* Create a handle on the current HIP device.  The handle owns its workspace
@@ -73,6 +83,15 @@ int lupp_set_option(lupp_handle_t h, int option, int64_t value);
 /* Wait for all work on the handle's stream.  Returns LUPP_ERR_INTERNAL once if
  * a device-side wait of an earlier call expired, else 0 or LUPP_ERR_HIP+e. */
 int lupp_sync(lupp_handle_t h);
+
+/* Instrumentation (test and benchmark use).  With LUPP_OPT_TIMING set, every
+ * xGETRF phase launched on the handle's stream is bracketed by HIP events on
+ * that stream.  This call synchronizes the stream and returns, for one phase,
+ * the number of recorded intervals, their summed duration (ms) and their
+ * summed algorithmic flop count (2*M*N*K for the update, M*N*M for the
+ * triangular solve, 0 otherwise); reset != 0 then clears all records.
+ * Errors: -2 unknown phase, -3/-4/-5 NULL output. */
+int lupp_timing_summary(lupp_handle_t h, int phase, int64_t* count, double* ms, double* flops, int reset);
 
 /* Human-readable text for a return code (static storage). */
 const char* lupp_status_string(int status);

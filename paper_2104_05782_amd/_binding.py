@@ -18,6 +18,8 @@ _lib.lupp_destroy.argtypes = [_vp]
 _lib.lupp_set_stream.argtypes = [_vp, _vp]
 _lib.lupp_set_option.argtypes = [_vp, _i32, _i64]
 _lib.lupp_sync.argtypes = [_vp]
+_lib.lupp_timing_summary.argtypes = [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double), _i32]
 _lib.lupp_status_string.argtypes = [_i32]
 _lib.lupp_status_string.restype = ctypes.c_char_p
 for _name in ("lupp_dgetrf", "lupp_sgetrf"):
@@ -27,6 +29,8 @@ for _name in ("lupp_dgetrs", "lupp_sgetrs"):
 
 OPT_NB = 1
 OPT_PANEL_LEAF = 2
+OPT_TIMING = 3
+PHASES = {"panel": 0, "laswp": 1, "trsm": 2, "update": 3, "update_big": 4}
 
 
 class LuppError(RuntimeError):
@@ -66,6 +70,13 @@ class Handle:
 
     def sync(self):
         _check(_lib.lupp_sync(self._p), "lupp_sync")
+
+    def timing_summary(self, phase: str, reset: bool = False):
+        """(count, ms, flops) recorded for a phase (see lupp_timing_summary)."""
+        c, ms, fl = _i64(), ctypes.c_double(), ctypes.c_double()
+        _check(_lib.lupp_timing_summary(self._p, PHASES[phase], ctypes.byref(c), ctypes.byref(ms), ctypes.byref(fl),
+                                        int(reset)), "lupp_timing_summary")
+        return c.value, ms.value, fl.value
 
     def close(self):
         if getattr(self, "_p", None):

@@ -154,17 +154,27 @@ hipError_t launch(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, in
 
 template <typename T>
 hipError_t gemm_sub(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B,
-                    int64_t ldb, T* C, int64_t ldc) {
+                    int64_t ldb, T* C, int64_t ldc, int* tile_out) {
+  int dummy;
+  int& tile = tile_out ? *tile_out : dummy;
+  tile = -1;
   if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
-  if (N <= 32) return launch<T, 128, 32, 16, 4, 1>(s, M, N, K, A, lda, B, ldb, C, ldc);
+  if (N <= 32) {
+    tile = 0;
+    return launch<T, 128, 32, 16, 4, 1>(s, M, N, K, A, lda, B, ldb, C, ldc);
+  }
   const int64_t big_tiles = ((M + 127) / 128) * ((N + 127) / 128);
-  if (big_tiles >= 512) return launch<T, 128, 128, 16, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
+  if (big_tiles >= 512) {
+    tile = 1;
+    return launch<T, 128, 128, 16, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
+  }
+  tile = 2;
   return launch<T, 64, 64, 16, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
 }
 
 template hipError_t gemm_sub<double>(hipStream_t, int64_t, int64_t, int64_t, const double*, int64_t,
-                                     const double*, int64_t, double*, int64_t);
+                                     const double*, int64_t, double*, int64_t, int*);
 template hipError_t gemm_sub<float>(hipStream_t, int64_t, int64_t, int64_t, const float*, int64_t,
-                                    const float*, int64_t, float*, int64_t);
+                                    const float*, int64_t, float*, int64_t, int*);
 
 }  // namespace lupp

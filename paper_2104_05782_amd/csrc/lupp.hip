@@ -16,8 +16,18 @@
 #include <stdlib.h>
 
 #include <new>
+#include <vector>
 
 #include "common.h"
+
+namespace lupp {
+struct TimingRecord {
+  hipEvent_t start = nullptr, stop = nullptr;
+  int phase = 0;
+  bool big = false;
+  double flops = 0.0;
+};
+}  // namespace lupp
 
 struct lupp_handle_st {
   int device = 0;
@@ -26,6 +36,9 @@ struct lupp_handle_st {
   int leaf = 32;
   lupp::LeafSlots* slots = nullptr;
   uint32_t epoch = 0;
+  bool timing = false;
+  std::vector<lupp::TimingRecord> records;  // events are created once and reused
+  size_t nrecords = 0;
 };
 
 namespace lupp {
@@ -49,6 +62,34 @@ inline hipError_t next_epoch(lupp_handle_t h, int w, uint32_t* out) {
   *out = h->epoch;
   h->epoch += (uint32_t)w + 1u;
   return hipSuccess;
+}
+
+// Phase timing: HIP events on the handle's stream around a phase's launches.
+int timer_begin(lupp_handle_t h, int phase) {
+  if (!h->timing) return -1;
+  if (h->nrecords == h->records.size()) {
+    TimingRecord r;
+    if (hipEventCreate(&r.start) != hipSuccess) return -1;
+    if (hipEventCreate(&r.stop) != hipSuccess) {
+      (void)hipEventDestroy(r.start);
+      return -1;
+    }
+    h->records.push_back(r);
+  }
+  TimingRecord& r = h->records[h->nrecords];
+  if (hipEventRecord(r.start, h->stream) != hipSuccess) return -1;
+  r.phase = phase;
+  r.big = false;
+  r.flops = 0.0;
+  return (int)h->nrecords++;
+}
+
+void timer_end(lupp_handle_t h, int idx, double flops, bool big = false) {
+  if (idx < 0) return;
+  TimingRecord& r = h->records[idx];
+  r.flops = flops;
+  r.big = big;
+  (void)hipEventRecord(r.stop, h->stream);
 }
 
 // B (w x ncols) := inv(L) * B with L unit lower triangular (w x w).
@@ -99,14 +140,26 @@ hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32
   const int64_t p = m < n ? m : n;
   for (int64_t k = 0; k < p; k += h->nb) {
     const int64_t b = (p - k < h->nb) ? (p - k) : h->nb;
+    int t = timer_begin(h, LUPP_PHASE_PANEL);
     LUPP_TRY(panel<T>(h, m, k, b, A, lda, ipiv, info));
+    timer_end(h, t, 0.0);
     // interchanges of this block on every column outside it
+    t = timer_begin(h, LUPP_PHASE_LASWP);
     LUPP_TRY(laswp<T>(s, A, lda, m, 0, n, k, k + b, ipiv, k, k + b));
+    timer_end(h, t, 0.0);
     if (k + b < n) {
-      LUPP_TRY(trsm_lower_unit<T>(s, b, n - k - b, A + k + k * lda, lda, A + k + (k + b) * lda, lda));
-      if (k + b < m)
-        LUPP_TRY(gemm_sub<T>(s, m - k - b, n - k - b, b, A + (k + b) + k * lda, lda, A + k + (k + b) * lda, lda,
-                             A + (k + b) + (k + b) * lda, lda));
+      const int64_t nr = n - k - b;
+      t = timer_begin(h, LUPP_PHASE_TRSM);
+      LUPP_TRY(trsm_lower_unit<T>(s, b, nr, A + k + k * lda, lda, A + k + (k + b) * lda, lda));
+      timer_end(h, t, (double)b * (double)b * (double)nr);
+      if (k + b < m) {
+        const int64_t mr = m - k - b;
+        int tile = -1;
+        t = timer_begin(h, LUPP_PHASE_UPDATE);
+        LUPP_TRY(gemm_sub<T>(s, mr, nr, b, A + (k + b) + k * lda, lda, A + k + (k + b) * lda, lda,
+                             A + (k + b) + (k + b) * lda, lda, &tile));
+        timer_end(h, t, 2.0 * (double)mr * (double)nr * (double)b, tile == 1);
+      }
     }
   }
   return hipSuccess;
@@ -190,6 +243,10 @@ int lupp_destroy(lupp_handle_t h) {
   int rc = LUPP_OK;
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) rc = lupp::hip_status(e);
+  for (auto& r : h->records) {
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
+  }
   if (h->slots) (void)hipFree(h->slots);
   delete h;
   return rc;
@@ -212,6 +269,10 @@ int lupp_set_option(lupp_handle_t h, int option, int64_t value) {
       if (value != 8 && value != 16 && value != 32) return -3;
       h->leaf = (int)value;
       return LUPP_OK;
+    case LUPP_OPT_TIMING:
+      if (value != 0 && value != 1) return -3;
+      h->timing = value != 0;
+      return LUPP_OK;
     default:
       return -2;
   }
@@ -231,6 +292,32 @@ int lupp_sync(lupp_handle_t h) {
       return LUPP_ERR_INTERNAL;
     }
   }
+  return LUPP_OK;
+}
+
+int lupp_timing_summary(lupp_handle_t h, int phase, int64_t* count, double* ms, double* flops, int reset) {
+  if (!h) return -1;
+  if (phase < LUPP_PHASE_PANEL || phase > LUPP_PHASE_UPDATE_BIG) return -2;
+  if (!count) return -3;
+  if (!ms) return -4;
+  if (!flops) return -5;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return lupp::hip_status(e);
+  *count = 0;
+  *ms = 0.0;
+  *flops = 0.0;
+  for (size_t i = 0; i < h->nrecords; ++i) {
+    const lupp::TimingRecord& r = h->records[i];
+    const bool match = (phase == LUPP_PHASE_UPDATE_BIG) ? (r.phase == LUPP_PHASE_UPDATE && r.big) : (r.phase == phase);
+    if (!match) continue;
+    float t = 0.f;
+    e = hipEventElapsedTime(&t, r.start, r.stop);
+    if (e != hipSuccess) return lupp::hip_status(e);
+    *count += 1;
+    *ms += t;
+    *flops += r.flops;
+  }
+  if (reset) h->nrecords = 0;
   return LUPP_OK;
 }
 

@@ -19,9 +19,48 @@ section); these recipes stand in for them.
 """
 from __future__ import annotations
 
+import ctypes
+import os
+import subprocess
+
 import numpy as np
 
 DEFAULT_SEED = 20210512
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "philox.c")
+_LIB = os.path.join(_HERE, "libsynth.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the threaded Philox fill (philox.c) into synth/libsynth.so."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", "-O3", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC],
+                       check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _fast():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        u64, vp, i64, c_int, dbl = ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        lib.synth_u01.argtypes = [u64, u64, u64, vp, i64, c_int]
+        lib.synth_affine_u01.argtypes = [u64, u64, u64, vp, i64, dbl, dbl, c_int]
+        _lib = lib
+    return _lib
+
+
+def _threads() -> int:
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:  # pragma: no cover
+        return 1
 
 
 def stream(seed: int, stream_id: int) -> np.random.Generator:
@@ -31,9 +70,11 @@ def stream(seed: int, stream_id: int) -> np.random.Generator:
     return np.random.Generator(np.random.Philox(key=(int(stream_id) << 64) | int(seed)))
 
 
-def _u01_colmajor(g: np.random.Generator, m: int, n: int) -> np.ndarray:
+def _u01_transposed(g: np.random.Generator, m: int, n: int) -> np.ndarray:
     # draw number j*m + i -> element (i, j): fill the transposed C-order array
-    return g.random((n, m)).T
+    buf = np.empty((n, m), dtype=np.float64)
+    g.random(out=buf)
+    return buf
 
 
 def uniform(seed: int, stream_id: int, m: int, n: int, lo: float = -1.0, hi: float = 1.0,
@@ -41,18 +82,33 @@ def uniform(seed: int, stream_id: int, m: int, n: int, lo: float = -1.0, hi: flo
     """m x n column-major matrix with iid U(lo, hi) entries.
 
     Only the exact affine maps (-1,1) and (-0.5,0.5) and (0,1) are offered so
-    that the FP64 values are exact functions of the 53-bit draws.
+    that the FP64 values are exact functions of the 53-bit draws.  Filled by
+    philox.c (threaded, same stream as numpy's Philox; see tests).
     """
-    u = _u01_colmajor(stream(seed, stream_id), m, n)
-    if (lo, hi) == (-1.0, 1.0):
-        a = 2.0 * u - 1.0
-    elif (lo, hi) == (-0.5, 0.5):
-        a = u - 0.5
-    elif (lo, hi) == (0.0, 1.0):
-        a = u
-    else:
+    maps = {(-1.0, 1.0): (2.0, -1.0), (-0.5, 0.5): (1.0, -0.5), (0.0, 1.0): (1.0, 0.0)}
+    if (lo, hi) not in maps:
         raise ValueError("supported ranges: (-1,1), (-0.5,0.5), (0,1)")
-    return np.asfortranarray(a.astype(dtype, copy=False))
+    stream(seed, stream_id)  # validates the key
+    a, b = maps[(lo, hi)]
+    t = np.empty((n, m), dtype=np.float64)
+    if t.size:
+        _fast().synth_affine_u01(int(seed), int(stream_id), 0, t.ctypes.data, t.size, a, b, _threads())
+    if dtype != np.float64:
+        t = t.astype(dtype)
+    return t.T
+
+
+def uniform_numpy(seed: int, stream_id: int, m: int, n: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """Reference path of ``uniform`` through numpy's own Philox generator."""
+    t = _u01_transposed(stream(seed, stream_id), m, n)
+    if (lo, hi) == (-1.0, 1.0):
+        t *= 2.0
+        t -= 1.0
+    elif (lo, hi) == (-0.5, 0.5):
+        t -= 0.5
+    elif (lo, hi) != (0.0, 1.0):
+        raise ValueError("supported ranges: (-1,1), (-0.5,0.5), (0,1)")
+    return t.T
 
 
 def permutation(seed: int, stream_id: int, n: int) -> np.ndarray:

@@ -425,3 +425,11 @@ def test_closed_form_ipiv_helper_small():
     assert list(checks.closed_form_ipiv([2, 0, 1])) == [3, 3, 3]
     assert list(checks.closed_form_ipiv([0, 1, 2])) == [1, 2, 3]
     assert list(checks.closed_form_ipiv([1, 0, 2])) == [2, 2, 3]
+
+
+def test_synth_fast_generator_matches_numpy_philox():
+    """The threaded C fill reproduces numpy's Philox-4x64-10 stream exactly."""
+    for (m, n, lo, hi) in [(1, 1, -1.0, 1.0), (7, 5, -1.0, 1.0), (33, 17, -0.5, 0.5), (64, 3, 0.0, 1.0)]:
+        a = synth.uniform(123, 9, m, n, lo, hi)
+        b = synth.uniform_numpy(123, 9, m, n, lo, hi)
+        assert a.flags["F_CONTIGUOUS"] and np.array_equal(a, b)
