@@ -148,7 +148,7 @@ def main():
     value = flops / (ms_per_step * 1e-3) / 1e12
     log("timed %d steps: %.2f ms/step, %.2f TFLOP/s" % (args.steps, ms_per_step, value))
     phases = {}
-    for ph in ("panel", "laswp", "trsm", "update", "update_big"):
+    for ph in ("panel", "laswp", "trsm", "update", "update_big", "panel_leaf", "panel_swap", "panel_trsm", "panel_gemm"):
         c, ms, fl = h.timing_summary(ph)
         phases[ph] = {"launches": c, "ms_per_step": ms / args.steps, "flops": fl / args.steps}
     c, ms, fl = h.timing_summary("update_big", reset=True)
@@ -156,7 +156,7 @@ def main():
     achieved = (fl / (ms * 1e-3) / 1e12) if ms > 0 else 0.0
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": None,
-                "kernel": "k_gemm_sub<%s,128,128,16,2,2>" % ("double" if args.dtype == "f64" else "float"),
+                "kernel": ("k_dgemm_sub_4x4<128,128,16,2,2,2>" if args.dtype == "f64" else "k_gemm_sub<float,128,128,16,2,2,2>"),
                 "launches_per_step": c // max(1, args.steps),
                 "avg_launch_ms": round(ms / max(1, c), 4),
                 "flops_per_launch": fl / max(1, c)}

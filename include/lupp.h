@@ -62,8 +62,12 @@ enum {
   LUPP_PHASE_PANEL = 0,     /* recursive column-block factorization          */
   LUPP_PHASE_LASWP = 1,     /* interchanges applied outside the column block */
   LUPP_PHASE_TRSM = 2,      /* U12 := inv(L11) * A12                         */
-  LUPP_PHASE_UPDATE = 3,    /* A22 := A22 - A21 * U12, every launch          */
-  LUPP_PHASE_UPDATE_BIG = 4 /* the same, launches of the 128x128-tile kernel */
+  LUPP_PHASE_UPDATE = 3,     /* A22 := A22 - A21 * U12, every launch          */
+  LUPP_PHASE_UPDATE_BIG = 4, /* the same, launches of the 128x128-tile kernel */
+  LUPP_PHASE_PANEL_LEAF = 5, /* inside the column block: leaf factorizations  */
+  LUPP_PHASE_PANEL_SWAP = 6, /* inside the column block: interchanges         */
+  LUPP_PHASE_PANEL_TRSM = 7, /* inside the column block: triangular solves    */
+  LUPP_PHASE_PANEL_GEMM = 8  /* inside the column block: updates              */
 };
 
 /* Create a handle on the current HIP device.  The handle owns its workspace

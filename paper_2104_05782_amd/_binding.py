@@ -30,7 +30,8 @@ for _name in ("lupp_dgetrs", "lupp_sgetrs"):
 OPT_NB = 1
 OPT_PANEL_LEAF = 2
 OPT_TIMING = 3
-PHASES = {"panel": 0, "laswp": 1, "trsm": 2, "update": 3, "update_big": 4}
+PHASES = {"panel": 0, "laswp": 1, "trsm": 2, "update": 3, "update_big": 4, "panel_leaf": 5, "panel_swap": 6,
+          "panel_trsm": 7, "panel_gemm": 8}
 
 
 class LuppError(RuntimeError):

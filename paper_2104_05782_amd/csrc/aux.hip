@@ -2,10 +2,12 @@
 //
 // laswp applies a step's sequential interchanges to the columns outside the
 // column block (the paper's in-place, right-looking update order, Section 3.2:
-// the current factor is overwritten at every step).  Column-major storage puts
-// the two elements of a swap in the same column, so one thread owns one
-// column and performs the interchanges in order; the pivots are staged once
-// per workgroup in LDS.
+// the current factor is overwritten at every step).  The run of interchanges
+// is first composed into one permutation of the rows it touches (a single
+// wavefront replays the swaps on row labels in LDS), then every (row, column)
+// element moves once, in parallel: reads of a band of columns, a barrier,
+// writes.  A swap chain never becomes a per-thread chain of dependent memory
+// accesses.
 //
 // trsm_leaf solves with a w x w triangle (w <= 64) for a band of 64 right-hand
 // columns per workgroup, entirely in LDS: U12 := inv(L11) * A12 (unit lower,
@@ -88,18 +90,154 @@ __global__ __launch_bounds__(256) void k_trsm_leaf(int w, int64_t ncols, const T
   }
 }
 
+// One wavefront replays interchanges k1..k2-1 on row labels.  Rows k1..k2-1
+// are tracked in s_cont; rows below k2 that are hit are appended to a short
+// list and found again by a ballot over it.
+__global__ __launch_bounds__(64) void k_swap_pairs(const int32_t* __restrict__ ipiv, int64_t k1, int64_t k2,
+                                                   int64_t m, SwapPairs* __restrict__ out) {
+  __shared__ int32_t s_piv[kMaxSwaps];
+  __shared__ int32_t s_cont[kMaxSwaps];
+  __shared__ int32_t s_erow[kMaxSwaps];
+  __shared__ int32_t s_econt[kMaxSwaps];
+  const int lane = threadIdx.x;
+  const int S = (int)(k2 - k1);
+  for (int i = lane; i < S; i += 64) {
+    s_piv[i] = ipiv[k1 + i] - 1;
+    s_cont[i] = (int32_t)(k1 + i);
+  }
+  __syncthreads();
+  int n_ext = 0;
+  for (int i = 0; i < S; ++i) {
+    const int64_t p = s_piv[i];
+    const int64_t row = k1 + i;
+    if (p <= row || p >= m) continue;  // no interchange (or NaN-born index)
+    if (p < k2) {
+      if (lane == 0) {
+        const int32_t t = s_cont[i];
+        s_cont[i] = s_cont[p - k1];
+        s_cont[p - k1] = t;
+      }
+    } else {
+      int found = -1;
+      for (int e0 = 0; e0 < n_ext; e0 += 64) {
+        const int e = e0 + lane;
+        const unsigned long long hit = __ballot(e < n_ext && s_erow[e] == (int32_t)p);
+        if (hit) {
+          found = e0 + __ffsll((long long)hit) - 1;
+          break;
+        }
+      }
+      if (found < 0) {
+        found = n_ext++;
+        if (lane == 0) {
+          s_erow[found] = (int32_t)p;
+          s_econt[found] = (int32_t)p;
+        }
+      }
+      if (lane == 0) {
+        const int32_t t = s_cont[i];
+        s_cont[i] = s_econt[found];
+        s_econt[found] = t;
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // lane 0's LDS writes precede the next replay step
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (int i = lane; i < S; i += 64) {
+    out->dst[i] = (int32_t)(k1 + i);
+    out->src[i] = s_cont[i];
+  }
+  for (int e = lane; e < n_ext; e += 64) {
+    out->dst[S + e] = s_erow[e];
+    out->src[S + e] = s_econt[e];
+  }
+  if (lane == 0) out->count = S + n_ext;
+}
+
+// Gather/scatter of a composed row permutation on a band of 64 columns per
+// workgroup, 8 columns at a time.
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_pairs(T* __restrict__ A, int64_t lda, int64_t c0, int64_t c1,
+                                                     int64_t skip0, int64_t skip1,
+                                                     const SwapPairs* __restrict__ pairs) {
+  constexpr int CB = 64, CC = 8, QP = (2 * kMaxSwaps) / 256;
+  __shared__ int32_t s_dst[2 * kMaxSwaps];
+  __shared__ int32_t s_src[2 * kMaxSwaps];
+  const int tid = threadIdx.x;
+  const int P = pairs->count;
+  for (int q = tid; q < P; q += 256) {
+    s_dst[q] = pairs->dst[q];
+    s_src[q] = pairs->src[q];
+  }
+  __syncthreads();
+  const int64_t width = (c1 - c0) - (skip1 - skip0);
+  const int64_t t0 = (int64_t)blockIdx.x * CB;
+  for (int cc0 = 0; cc0 < CB; cc0 += CC) {
+    T v[QP][CC];
+#pragma unroll
+    for (int qi = 0; qi < QP; ++qi) {
+      const int q = tid + 256 * qi;
+#pragma unroll
+      for (int cc = 0; cc < CC; ++cc) {
+        const int64_t t = t0 + cc0 + cc;
+        int64_t c = c0 + t;
+        if (c >= skip0) c += (skip1 - skip0);
+        if (q < P && t < width) v[qi][cc] = A[(int64_t)s_src[q] + c * lda];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int qi = 0; qi < QP; ++qi) {
+      const int q = tid + 256 * qi;
+#pragma unroll
+      for (int cc = 0; cc < CC; ++cc) {
+        const int64_t t = t0 + cc0 + cc;
+        int64_t c = c0 + t;
+        if (c >= skip0) c += (skip1 - skip0);
+        if (q < P && t < width) A[(int64_t)s_dst[q] + c * lda] = v[qi][cc];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void k_set_int(int32_t* p, int32_t v) { *p = v; }
 
 }  // namespace
 
+hipError_t swap_pairs(hipStream_t s, const int32_t* ipiv, int64_t k1, int64_t k2, int64_t m, SwapPairs* pairs) {
+  if (k2 - k1 > kMaxSwaps || k2 < k1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_swap_pairs, dim3(1), dim3(64), 0, s, ipiv, k1, k2, m, pairs);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t apply_pairs(hipStream_t s, T* A, int64_t lda, int64_t c0, int64_t c1, int64_t skip0, int64_t skip1,
+                       const SwapPairs* pairs, int64_t max_pairs) {
+  (void)max_pairs;
+  if (skip0 < c0) skip0 = c0;
+  if (skip1 > c1) skip1 = c1;
+  if (skip1 < skip0) skip1 = skip0;
+  const int64_t width = (c1 - c0) - (skip1 - skip0);
+  if (width <= 0) return hipSuccess;
+  const int64_t blocks = (width + 63) / 64;
+  hipLaunchKernelGGL(k_apply_pairs<T>, dim3((unsigned)blocks), dim3(256), 0, s, A, lda, c0, c1, skip0, skip1, pairs);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t laswp(hipStream_t s, T* A, int64_t lda, int64_t m, int64_t c0, int64_t c1, int64_t skip0, int64_t skip1,
-                 const int32_t* ipiv, int64_t k1, int64_t k2) {
+                 const int32_t* ipiv, int64_t k1, int64_t k2, SwapPairs* pairs) {
   if (skip0 < c0) skip0 = c0;
   if (skip1 > c1) skip1 = c1;
   if (skip1 < skip0) skip1 = skip0;
   const int64_t width = (c1 - c0) - (skip1 - skip0);
   if (width <= 0 || k2 <= k1) return hipSuccess;
+  if (pairs && k2 - k1 <= kMaxSwaps) {
+    hipError_t e = swap_pairs(s, ipiv, k1, k2, m, pairs);
+    if (e != hipSuccess) return e;
+    return apply_pairs<T>(s, A, lda, c0, c1, skip0, skip1, pairs, 2 * (k2 - k1));
+  }
   const int64_t blocks = (width + 255) / 256;
   // an interchange outside rows [0, m) is ignored (it can only come from NaN input)
   hipLaunchKernelGGL(k_laswp<T>, dim3((unsigned)blocks), dim3(256), 0, s, A, lda, c0, c1, skip0, skip1, ipiv, k1,
@@ -127,9 +265,13 @@ hipError_t set_int(hipStream_t s, int32_t* p, int32_t v) {
 }
 
 template hipError_t laswp<double>(hipStream_t, double*, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t,
-                                  const int32_t*, int64_t, int64_t);
+                                  const int32_t*, int64_t, int64_t, SwapPairs*);
 template hipError_t laswp<float>(hipStream_t, float*, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t,
-                                 const int32_t*, int64_t, int64_t);
+                                 const int32_t*, int64_t, int64_t, SwapPairs*);
+template hipError_t apply_pairs<double>(hipStream_t, double*, int64_t, int64_t, int64_t, int64_t, int64_t,
+                                        const SwapPairs*, int64_t);
+template hipError_t apply_pairs<float>(hipStream_t, float*, int64_t, int64_t, int64_t, int64_t, int64_t,
+                                       const SwapPairs*, int64_t);
 template hipError_t trsm_leaf<double>(hipStream_t, bool, int64_t, int64_t, const double*, int64_t, double*, int64_t);
 template hipError_t trsm_leaf<float>(hipStream_t, bool, int64_t, int64_t, const float*, int64_t, float*, int64_t);
 

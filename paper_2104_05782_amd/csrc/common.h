@@ -53,6 +53,18 @@ struct LeafSlots {
   double rowj[2][kLeafMaxWidth];                   // the diagonal row before the interchange
 };
 
+// Row movement of a run of consecutive interchanges k1..k2-1 (k2 - k1 <=
+// kMaxSwaps), composed into one permutation: after the run, row dst[q] holds
+// what row src[q] held before it.  The first k2 - k1 entries are the rows
+// k1..k2-1 in order; the rest are the rows below k2 that the run touched.
+constexpr int kMaxSwaps = 512;
+struct SwapPairs {
+  int32_t count;
+  int32_t pad_[63];
+  int32_t dst[2 * kMaxSwaps];
+  int32_t src[2 * kMaxSwaps];
+};
+
 // ---------------------------------------------------------------- launchers
 // C[M x N] -= A[M x K] * B[K x N], column-major (A, B and C must not overlap).
 // *tile_out (optional) receives the tile configuration used: 0 = 128x32,
@@ -69,11 +81,21 @@ template <typename T>
 hipError_t panel_leaf(hipStream_t s, int64_t r, int w, T* P, int64_t ld, int32_t* ipiv, int64_t k,
                       int32_t* info, LeafSlots* ws, uint32_t epoch);
 
+// Compose interchanges k1..k2-1 (ipiv, 1-based rows of an m-row matrix) into
+// *pairs (one workgroup).
+hipError_t swap_pairs(hipStream_t s, const int32_t* ipiv, int64_t k1, int64_t k2, int64_t m, SwapPairs* pairs);
+
+// Apply *pairs to columns [c0, c1) of A except the columns [skip0, skip1).
+template <typename T>
+hipError_t apply_pairs(hipStream_t s, T* A, int64_t lda, int64_t c0, int64_t c1, int64_t skip0, int64_t skip1,
+                       const SwapPairs* pairs, int64_t max_pairs);
+
 // Apply interchanges k1..k2-1 (ipiv, 1-based rows of the m-row matrix A) to
-// columns [c0, c1) of A except the columns [skip0, skip1).
+// columns [c0, c1) of A except the columns [skip0, skip1): swap_pairs then
+// apply_pairs (k2 - k1 <= kMaxSwaps), or one thread per column for longer runs.
 template <typename T>
 hipError_t laswp(hipStream_t s, T* A, int64_t lda, int64_t m, int64_t c0, int64_t c1, int64_t skip0, int64_t skip1,
-                 const int32_t* ipiv, int64_t k1, int64_t k2);
+                 const int32_t* ipiv, int64_t k1, int64_t k2, SwapPairs* pairs);
 
 // Triangular solve on a w x ncols block (w <= 64): lower=true solves with a
 // unit lower triangle (forward), lower=false with a non-unit upper triangle.

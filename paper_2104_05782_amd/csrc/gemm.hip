@@ -1,5 +1,6 @@
-// Trailing-update GEMM  C -= A * B  on MFMA (FP64: v_mfma_f64_16x16x4f64,
-// FP32: v_mfma_f32_16x16x4f32), column-major operands of any shape.
+// Trailing-update GEMM  C -= A * B  on MFMA (FP64: v_mfma_f64_4x4x4f64 for
+// the large tiles, FP32: v_mfma_f32_16x16x4f32), column-major operands of any
+// shape.
 //
 // This is the update A22 := A22 - A21 * U12 of the right-looking step, the
 // operation the paper identifies as the dominant cost of a blocked
@@ -10,8 +11,11 @@
 // Design (gfx950): a workgroup computes a BM x BN tile of C with
 // WGM x WGN wavefronts; K is consumed in steps of BK through double-buffered
 // LDS tiles (one barrier per step; the next step's global loads are issued
-// before the current step's MFMAs).  A is negated while it is staged, so the
-// accumulators hold -A*B and the epilogue is a single read-add-write of C.
+// before the current step's MFMAs).  Edge tiles clamp their load addresses
+// into the matrix and zero the loaded value instead of branching, so every
+// load is unconditional.  The accumulators are loaded from C at the start and
+// A is negated while it is staged, so the MFMAs accumulate C - A*B directly
+// and the epilogue is a plain store (no read-modify-write latency at the end).
 // Tiles are mapped XCD-aware: consecutive workgroup ids land on different XCDs
 // (round robin), so the id is first split into (xcd, slot) and each XCD walks
 // its own contiguous band of tiles in groups of 8 tile-rows, keeping the A
@@ -19,24 +23,26 @@
 #include "common.h"
 
 namespace lupp {
-namespace {
 
 constexpr int kXcds = 8;
 constexpr int kGroupM = 8;
 
-template <typename T, int BM, int BN, int BK, int WGM, int WGN>
-__global__ __launch_bounds__(64 * WGM* WGN) void k_gemm_sub(int64_t M, int64_t N, int64_t K,
-                                                            const T* __restrict__ A, int64_t lda,
-                                                            const T* __restrict__ B, int64_t ldb,
-                                                            T* __restrict__ C, int64_t ldc, int tiles_m,
-                                                            int tiles_n) {
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int MINB>
+__global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_gemm_sub(int64_t M, int64_t N, int64_t K,
+                                                                  const T* __restrict__ A, int64_t lda,
+                                                                  const T* __restrict__ B, int64_t ldb,
+                                                                  T* __restrict__ C, int64_t ldc, int tiles_m,
+                                                                  int tiles_n) {
   constexpr int NT = 64 * WGM * WGN;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int FM = WTM / 16, FN = WTN / 16;
   constexpr int PAD = 16;
   constexpr int LDSA = BM + PAD, LDSB = BN + PAD;
   constexpr int EA = BM * BK / NT, EB = BK * BN / NT;
+  constexpr int KA = NT / BM;  // k-rows of the A tile loaded per pass
+  constexpr int NB_ = NT / BK; // columns of the B tile loaded per pass
   static_assert(EA * NT == BM * BK && EB * NT == BK * BN, "tile/thread mismatch");
+  static_assert(KA * BM == NT && NB_ * BK == NT, "thread layout");
   typedef typename Mfma<T>::v4 v4;
 
   __shared__ T sA[2][BK * LDSA];
@@ -60,58 +66,82 @@ __global__ __launch_bounds__(64 * WGM* WGN) void k_gemm_sub(int64_t M, int64_t N
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
 
+  // A tile: thread loads row ai = tid % BM, k-rows ak0 + KA*s
+  const int ai = tid % BM, ak0 = tid / BM;
+  const bool arow_ok = (m0 + ai) < M;
+  const T* pa = A + (arow_ok ? (m0 + ai) : (M - 1));
+  // B tile: thread loads k-row bk = tid % BK of columns bn0 + NB_*s
+  const int bk = tid % BK, bn0 = tid / BK;
+  bool bcol_ok[EB];
+  const T* pb[EB];
+#pragma unroll
+  for (int s = 0; s < EB; ++s) {
+    const int64_t gn = n0 + bn0 + NB_ * s;
+    bcol_ok[s] = gn < N;
+    pb[s] = B + (bcol_ok[s] ? gn : (N - 1)) * ldb;
+  }
+
   T ra[EA], rb[EB];
   auto gload = [&](int64_t k0) {
 #pragma unroll
     for (int s = 0; s < EA; ++s) {
-      const int e = tid + NT * s;
-      const int i = e % BM, k = e / BM;
-      const int64_t gi = m0 + i, gk = k0 + k;
-      ra[s] = (gi < M && gk < K) ? A[gi + gk * lda] : T(0);
+      const int64_t gk = k0 + ak0 + KA * s;
+      const bool ok = arow_ok && gk < K;
+      const T v = pa[(gk < K ? gk : K - 1) * lda];
+      ra[s] = ok ? v : T(0);
     }
+    const int64_t gk = k0 + bk;
+    const bool kok = gk < K;
+    const int64_t gkc = kok ? gk : K - 1;
 #pragma unroll
     for (int s = 0; s < EB; ++s) {
-      const int e = tid + NT * s;
-      const int k = e % BK, n = e / BK;
-      const int64_t gk = k0 + k, gn = n0 + n;
-      rb[s] = (gk < K && gn < N) ? B[gk + gn * ldb] : T(0);
+      const T v = pb[s][gkc];
+      rb[s] = (kok && bcol_ok[s]) ? v : T(0);
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int s = 0; s < EA; ++s) {
-      const int e = tid + NT * s;
-      sA[buf][(e / BM) * LDSA + (e % BM)] = -ra[s];
-    }
+    for (int s = 0; s < EA; ++s) sA[buf][(ak0 + KA * s) * LDSA + ai] = -ra[s];
 #pragma unroll
-    for (int s = 0; s < EB; ++s) {
-      const int e = tid + NT * s;
-      sB[buf][(e % BK) * LDSB + (e / BK)] = rb[s];
-    }
+    for (int s = 0; s < EB; ++s) sB[buf][bk * LDSB + bn0 + NB_ * s] = rb[s];
   };
 
+  // the accumulators start from C (clamped addresses, zero outside): the
+  // epilogue is then a plain store and the loads overlap the first tile
   v4 acc[FM][FN];
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+  for (int i = 0; i < FM; ++i) {
+    const int64_t row = m0 + wm * WTM + i * 16 + (lane & 15);
+    const int64_t rowc = row < M ? row : M - 1;
 #pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = v4{0, 0, 0, 0};
+    for (int j = 0; j < FN; ++j) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t col = n0 + wn * WTN + j * 16 + Mfma<T>::col(lane, r);
+        const int64_t colc = col < N ? col : N - 1;
+        const T v = C[rowc + colc * ldc];
+        acc[i][j][r] = (row < M && col < N) ? v : T(0);
+      }
+    }
+  }
 
   const int KT = (int)((K + BK - 1) / BK);
   gload(0);
   sstore(0);
   __syncthreads();
+  const int arow = wm * WTM + (lane & 15);
+  const int bcol = wn * WTN + (lane & 15);
   for (int kt = 0; kt < KT; ++kt) {
     if (kt + 1 < KT) gload((int64_t)(kt + 1) * BK);
-    const T* as = sA[kt & 1];
-    const T* bs = sB[kt & 1];
+    const T* as = sA[kt & 1] + (lane >> 4) * LDSA + arow;
+    const T* bs = sB[kt & 1] + (lane >> 4) * LDSB + bcol;
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       T af[FM], bf[FN];
-      const int krow = kk * 4 + (lane >> 4);
 #pragma unroll
-      for (int i = 0; i < FM; ++i) af[i] = as[krow * LDSA + wm * WTM + i * 16 + (lane & 15)];
+      for (int i = 0; i < FM; ++i) af[i] = as[kk * 4 * LDSA + i * 16];
 #pragma unroll
-      for (int j = 0; j < FN; ++j) bf[j] = bs[krow * LDSB + wn * WTN + j * 16 + (lane & 15)];
+      for (int j = 0; j < FN; ++j) bf[j] = bs[kk * 4 * LDSB + j * 16];
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -129,24 +159,207 @@ __global__ __launch_bounds__(64 * WGM* WGN) void k_gemm_sub(int64_t M, int64_t N
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t col = n0 + wn * WTN + j * 16 + Mfma<T>::col(lane, r);
-        if (row < M && col < N) {
-          T* p = C + row + col * ldc;
-          *p = *p + acc[i][j][r];
-        }
+        if (row < M && col < N) C[row + col * ldc] = acc[i][j][r];
       }
     }
   }
 }
 
-template <typename T, int BM, int BN, int BK, int WGM, int WGN>
+// FP64 variant on v_mfma_f64_4x4x4f64 (four independent 4x4x4 products per
+// instruction).  Lane L = x + 4b + 16y of an instruction holds A_b(x, y),
+// B_b(y, x) and C_b(y, x), b = 0..3.  The four blocks are arranged 2 x 2
+// (rb = b & 1 picks rows, cb = b >> 1 columns), so one instruction updates an
+// 8 x 8 piece of C, and a 64 x 64 wave tile needs 8 + 8 operand registers per
+// K-step of 4 for its 64 instructions.
+//
+// The K loop is peeled so that the next step's global loads are issued
+// unconditionally at the top of each iteration and consumed only by the LDS
+// stores at its bottom: the loads' latency overlaps the MFMAs.  Interior tiles
+// (the vast majority) run without any bounds masking; edge tiles clamp their
+// addresses and zero the values.
+template <int BM, int BN, int BK, int WGM, int WGN, bool EDGE>
+__device__ __forceinline__ void dgemm4_body(int64_t M, int64_t N, int64_t K, const double* __restrict__ A,
+                                            int64_t lda, const double* __restrict__ B, int64_t ldb,
+                                            double* __restrict__ C, int64_t ldc, int64_t m0, int64_t n0,
+                                            double* sA, double* sB) {
+  typedef double T;
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int RG = WTM / 8, CG = WTN / 8;
+  constexpr int PAD = 16;
+  constexpr int LDSA = BM + PAD, LDSB = BN + PAD;
+  constexpr int SA = BK * LDSA, SB = BK * LDSB;
+  constexpr int EA = BM * BK / NT, EB = BK * BN / NT;
+  constexpr int KA = NT / BM;
+  constexpr int NB_ = NT / BK;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+
+  // global load pointers: A rows ai, k-rows ak0 + KA*s; B k-row bk, columns bn0 + NB_*s
+  const int ai = tid % BM, ak0 = tid / BM;
+  const int bk = tid % BK, bn0 = tid / BK;
+  const bool arow_ok = !EDGE || (m0 + ai) < M;
+  const T* pa = A + (arow_ok ? (m0 + ai) : (M - 1)) + (int64_t)ak0 * lda;
+  const int64_t astep = (int64_t)KA * lda;
+  bool bcol_ok[EB];
+  const T* pb[EB];
+#pragma unroll
+  for (int s = 0; s < EB; ++s) {
+    const int64_t gn = n0 + bn0 + NB_ * s;
+    bcol_ok[s] = !EDGE || gn < N;
+    pb[s] = B + (bcol_ok[s] ? gn : (N - 1)) * ldb + bk;
+  }
+
+  T ra[EA], rb[EB];
+  auto gload = [&](int64_t k0) {
+    if (!EDGE) {
+      const T* q = pa + k0 * lda;
+#pragma unroll
+      for (int s = 0; s < EA; ++s) ra[s] = q[s * astep];
+#pragma unroll
+      for (int s = 0; s < EB; ++s) rb[s] = pb[s][k0];
+    } else {
+#pragma unroll
+      for (int s = 0; s < EA; ++s) {
+        const int64_t gk = k0 + ak0 + KA * s;
+        const int64_t gkc = gk < K ? gk : K - 1;
+        const T v = pa[(gkc - ak0) * lda];
+        ra[s] = (arow_ok && gk < K) ? v : T(0);
+      }
+      const int64_t gk = k0 + bk;
+      const bool kok = gk < K;
+      const int64_t off = (kok ? gk : K - 1) - bk;
+#pragma unroll
+      for (int s = 0; s < EB; ++s) {
+        const T v = pb[s][off];
+        rb[s] = (kok && bcol_ok[s]) ? v : T(0);
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+    T* a = sA + buf * SA + ak0 * LDSA + ai;
+    T* b = sB + buf * SB + bk * LDSB + bn0;
+#pragma unroll
+    for (int s = 0; s < EA; ++s) a[s * KA * LDSA] = ra[s];
+#pragma unroll
+    for (int s = 0; s < EB; ++s) b[s * NB_] = rb[s];
+  };
+
+  const int x = lane & 3, blk = (lane >> 2) & 3, y = lane >> 4;
+  const int rb_ = blk & 1, cb_ = blk >> 1;
+
+  // the accumulators start from -C (clamped addresses, zero outside), the
+  // MFMAs add A*B and the epilogue stores the negation: C - A*B exactly as if
+  // A had been negated, without any arithmetic between the loads and the LDS
+  T acc[RG][CG];
+#pragma unroll
+  for (int i = 0; i < RG; ++i) {
+    const int64_t row = m0 + wm * WTM + i * 8 + rb_ * 4 + y;
+    const int64_t rowc = (!EDGE || row < M) ? row : M - 1;
+#pragma unroll
+    for (int j = 0; j < CG; ++j) {
+      const int64_t col = n0 + wn * WTN + j * 8 + cb_ * 4 + x;
+      const int64_t colc = (!EDGE || col < N) ? col : N - 1;
+      const T v = C[rowc + colc * ldc];
+      acc[i][j] = (!EDGE || (row < M && col < N)) ? -v : T(0);
+    }
+  }
+
+  const int arow = wm * WTM + rb_ * 4 + x;
+  const int bcol = wn * WTN + cb_ * 4 + x;
+  auto compute = [&](int buf) {
+    const T* as = sA + buf * SA + y * LDSA + arow;
+    const T* bs = sB + buf * SB + y * LDSB + bcol;
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      T af[RG], bf[CG];
+#pragma unroll
+      for (int i = 0; i < RG; ++i) af[i] = as[kk * 4 * LDSA + i * 8];
+#pragma unroll
+      for (int j = 0; j < CG; ++j) bf[j] = bs[kk * 4 * LDSB + j * 8];
+#pragma unroll
+      for (int i = 0; i < RG; ++i)
+#pragma unroll
+        for (int j = 0; j < CG; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+  };
+
+  const int KT = (int)((K + BK - 1) / BK);
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt + 1 < KT; ++kt) {
+    gload((int64_t)(kt + 1) * BK);
+    compute(kt & 1);
+    sstore((kt + 1) & 1);
+    __syncthreads();
+  }
+  compute((KT - 1) & 1);
+
+#pragma unroll
+  for (int i = 0; i < RG; ++i) {
+    const int64_t row = m0 + wm * WTM + i * 8 + rb_ * 4 + y;
+#pragma unroll
+    for (int j = 0; j < CG; ++j) {
+      const int64_t col = n0 + wn * WTN + j * 8 + cb_ * 4 + x;
+      if (!EDGE || (row < M && col < N)) C[row + col * ldc] = -acc[i][j];
+    }
+  }
+}
+
+template <int BM, int BN, int BK, int WGM, int WGN, int MINB>
+__global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_dgemm_sub_4x4(int64_t M, int64_t N, int64_t K,
+                                                                       const double* __restrict__ A, int64_t lda,
+                                                                       const double* __restrict__ B, int64_t ldb,
+                                                                       double* __restrict__ C, int64_t ldc,
+                                                                       int tiles_m, int tiles_n) {
+  constexpr int PAD = 16;
+  __shared__ double sA[2 * BK * (BM + PAD)];
+  __shared__ double sB[2 * BK * (BN + PAD)];
+  const int total = tiles_m * tiles_n;
+  const int per_xcd = (total + kXcds - 1) / kXcds;
+  const int bid = blockIdx.x;
+  const int t = (bid % kXcds) * per_xcd + bid / kXcds;
+  if (t >= total) return;
+  const int group_size = kGroupM * tiles_n;
+  const int group = t / group_size;
+  const int first_m = group * kGroupM;
+  const int gm = min(tiles_m - first_m, kGroupM);
+  const int within = t - group * group_size;
+  const int tm = first_m + within % gm;
+  const int tn = within / gm;
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const bool interior = (m0 + BM <= M) && (n0 + BN <= N) && (K % BK == 0);
+  if (interior)
+    dgemm4_body<BM, BN, BK, WGM, WGN, false>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sA, sB);
+  else
+    dgemm4_body<BM, BN, BK, WGM, WGN, true>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sA, sB);
+}
+
+namespace {
+
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int MINB>
 hipError_t launch(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B,
                   int64_t ldb, T* C, int64_t ldc) {
   const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
   if (tm * tn > (int64_t)1 << 30) return hipErrorInvalidValue;
   const int total = (int)(tm * tn);
   const int per_xcd = (total + kXcds - 1) / kXcds;
-  hipLaunchKernelGGL((k_gemm_sub<T, BM, BN, BK, WGM, WGN>), dim3(per_xcd * kXcds), dim3(64 * WGM * WGN), 0, s,
-                     M, N, K, A, lda, B, ldb, C, ldc, (int)tm, (int)tn);
+  hipLaunchKernelGGL((k_gemm_sub<T, BM, BN, BK, WGM, WGN, MINB>), dim3(per_xcd * kXcds), dim3(64 * WGM * WGN), 0,
+                     s, M, N, K, A, lda, B, ldb, C, ldc, (int)tm, (int)tn);
+  return hipGetLastError();
+}
+
+template <int BM, int BN, int BK, int WGM, int WGN, int MINB>
+hipError_t launch_d4(hipStream_t s, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
+                     int64_t ldb, double* C, int64_t ldc) {
+  const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
+  if (tm * tn > (int64_t)1 << 30) return hipErrorInvalidValue;
+  const int total = (int)(tm * tn);
+  const int per_xcd = (total + kXcds - 1) / kXcds;
+  hipLaunchKernelGGL((k_dgemm_sub_4x4<BM, BN, BK, WGM, WGN, MINB>), dim3(per_xcd * kXcds), dim3(64 * WGM * WGN), 0,
+                     s, M, N, K, A, lda, B, ldb, C, ldc, (int)tm, (int)tn);
   return hipGetLastError();
 }
 
@@ -161,15 +374,24 @@ hipError_t gemm_sub(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, 
   if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
   if (N <= 32) {
     tile = 0;
-    return launch<T, 128, 32, 16, 4, 1>(s, M, N, K, A, lda, B, ldb, C, ldc);
+    return launch<T, 128, 32, 16, 4, 1, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
   }
   const int64_t big_tiles = ((M + 127) / 128) * ((N + 127) / 128);
-  if (big_tiles >= 512) {
-    tile = 1;
-    return launch<T, 128, 128, 16, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
+  if constexpr (sizeof(T) == 8) {
+    if (big_tiles >= 512) {
+      tile = 1;
+      return launch_d4<128, 128, 16, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
+    }
+    tile = 2;
+    return launch_d4<64, 64, 16, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
+  } else {
+    if (big_tiles >= 512) {
+      tile = 1;
+      return launch<T, 128, 128, 16, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
+    }
+    tile = 2;
+    return launch<T, 64, 64, 16, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
   }
-  tile = 2;
-  return launch<T, 64, 64, 16, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
 }
 
 template hipError_t gemm_sub<double>(hipStream_t, int64_t, int64_t, int64_t, const double*, int64_t,

@@ -35,6 +35,7 @@ struct lupp_handle_st {
   int64_t nb = 256;
   int leaf = 32;
   lupp::LeafSlots* slots = nullptr;
+  lupp::SwapPairs* pairs = nullptr;
   uint32_t epoch = 0;
   bool timing = false;
   std::vector<lupp::TimingRecord> records;  // events are created once and reused
@@ -119,18 +120,30 @@ hipError_t panel(lupp_handle_t h, int64_t m, int64_t k, int64_t w, T* A, int64_t
   if (w <= h->leaf) {
     uint32_t ep;
     LUPP_TRY(next_epoch(h, (int)w, &ep));
-    return panel_leaf<T>(s, m - k, (int)w, A + k + k * lda, lda, ipiv, k, info, h->slots, ep);
+    const int t = timer_begin(h, LUPP_PHASE_PANEL_LEAF);
+    LUPP_TRY(panel_leaf<T>(s, m - k, (int)w, A + k + k * lda, lda, ipiv, k, info, h->slots, ep));
+    timer_end(h, t, 0.0);
+    return hipSuccess;
   }
   int64_t w1 = w / 2;
   if (w1 > 8) w1 = (w1 / 8) * 8;
   const int64_t w2 = w - w1;
   LUPP_TRY(panel<T>(h, m, k, w1, A, lda, ipiv, info));
-  LUPP_TRY(laswp<T>(s, A, lda, m, k + w1, k + w, 0, 0, ipiv, k, k + w1));
+  int t = timer_begin(h, LUPP_PHASE_PANEL_SWAP);
+  LUPP_TRY(laswp<T>(s, A, lda, m, k + w1, k + w, 0, 0, ipiv, k, k + w1, h->pairs));
+  timer_end(h, t, 0.0);
+  t = timer_begin(h, LUPP_PHASE_PANEL_TRSM);
   LUPP_TRY(trsm_lower_unit<T>(s, w1, w2, A + k + k * lda, lda, A + k + (k + w1) * lda, lda));
+  timer_end(h, t, (double)w1 * (double)w1 * (double)w2);
+  t = timer_begin(h, LUPP_PHASE_PANEL_GEMM);
   LUPP_TRY(gemm_sub<T>(s, m - k - w1, w2, w1, A + (k + w1) + k * lda, lda, A + k + (k + w1) * lda, lda,
                        A + (k + w1) + (k + w1) * lda, lda));
+  timer_end(h, t, 2.0 * (double)(m - k - w1) * (double)w2 * (double)w1);
   LUPP_TRY(panel<T>(h, m, k + w1, w2, A, lda, ipiv, info));
-  return laswp<T>(s, A, lda, m, k, k + w1, 0, 0, ipiv, k + w1, k + w);
+  t = timer_begin(h, LUPP_PHASE_PANEL_SWAP);
+  LUPP_TRY(laswp<T>(s, A, lda, m, k, k + w1, 0, 0, ipiv, k + w1, k + w, h->pairs));
+  timer_end(h, t, 0.0);
+  return hipSuccess;
 }
 
 template <typename T>
@@ -145,7 +158,7 @@ hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32
     timer_end(h, t, 0.0);
     // interchanges of this block on every column outside it
     t = timer_begin(h, LUPP_PHASE_LASWP);
-    LUPP_TRY(laswp<T>(s, A, lda, m, 0, n, k, k + b, ipiv, k, k + b));
+    LUPP_TRY(laswp<T>(s, A, lda, m, 0, n, k, k + b, ipiv, k, k + b, h->pairs));
     timer_end(h, t, 0.0);
     if (k + b < n) {
       const int64_t nr = n - k - b;
@@ -169,7 +182,7 @@ template <typename T>
 hipError_t getrs(lupp_handle_t h, int64_t n, int64_t nrhs, const T* LU, int64_t lda, const int32_t* ipiv, T* B,
                  int64_t ldb) {
   hipStream_t s = h->stream;
-  LUPP_TRY(laswp<T>(s, B, ldb, n, 0, nrhs, 0, 0, ipiv, 0, n));
+  LUPP_TRY(laswp<T>(s, B, ldb, n, 0, nrhs, 0, 0, ipiv, 0, n, nullptr));
   LUPP_TRY(trsm_lower_unit<T>(s, n, nrhs, LU, lda, B, ldb));
   return trsm_upper<T>(s, n, nrhs, LU, lda, B, ldb);
 }
@@ -177,14 +190,16 @@ hipError_t getrs(lupp_handle_t h, int64_t n, int64_t nrhs, const T* LU, int64_t 
 hipError_t ensure_workspace(lupp_handle_t h) {
   if (h->slots) return hipSuccess;
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, sizeof(LeafSlots));
+  const size_t bytes = sizeof(LeafSlots) + sizeof(SwapPairs);
+  hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) return e;
-  e = hipMemset(p, 0, sizeof(LeafSlots));
+  e = hipMemset(p, 0, bytes);
   if (e != hipSuccess) {
     (void)hipFree(p);
     return e;
   }
   h->slots = (LeafSlots*)p;
+  h->pairs = (SwapPairs*)((char*)p + sizeof(LeafSlots));
   h->epoch = 0;
   return hipSuccess;
 }
@@ -297,7 +312,7 @@ int lupp_sync(lupp_handle_t h) {
 
 int lupp_timing_summary(lupp_handle_t h, int phase, int64_t* count, double* ms, double* flops, int reset) {
   if (!h) return -1;
-  if (phase < LUPP_PHASE_PANEL || phase > LUPP_PHASE_UPDATE_BIG) return -2;
+  if (phase < LUPP_PHASE_PANEL || phase > LUPP_PHASE_PANEL_GEMM) return -2;
   if (!count) return -3;
   if (!ms) return -4;
   if (!flops) return -5;
