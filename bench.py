@@ -99,6 +99,7 @@ def main():
     ap.add_argument("--seed", type=int, default=20210513)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-lookahead", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -124,6 +125,8 @@ def main():
     h = lupp.Handle()
     if args.nb:
         h.set_option(1, args.nb)
+    if args.no_lookahead:
+        h.set_option(4, 0)
     fn = lupp.lupp_dgetrf if args.dtype == "f64" else lupp.lupp_sgetrf
 
     def step():
@@ -190,7 +193,8 @@ def main():
         "data": "synthetic: A iid U(-1,1) from seed %d (Philox-4x64-10)" % args.seed,
         "config": {"workload": "plain blocked LUPP FP64 n=%d" % n if args.dtype == "f64"
                    else "plain blocked LUPP FP32 n=%d" % n,
-                   "n": n, "nb": args.nb or 256, "flops_per_step": flops, "parallelism": "single GPU"},
+                   "n": n, "nb": args.nb or 256, "lookahead": 0 if args.no_lookahead else 1,
+                   "flops_per_step": flops, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phases": phases,

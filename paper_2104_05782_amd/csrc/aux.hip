@@ -201,6 +201,66 @@ __global__ __launch_bounds__(256) void k_apply_pairs(T* __restrict__ A, int64_t 
   }
 }
 
+// One thread per right-hand column, the triangle in LDS (read as broadcasts),
+// no barrier inside the substitution.  The column is solved in chunks of 16
+// rows: a chunk lives in registers, finished rows in LDS (each lane its own
+// column, so lanes touch consecutive LDS words).
+template <typename T, bool LOWER>
+__global__ __launch_bounds__(64) void k_trsm_small(int w, int64_t ncols, const T* __restrict__ L, int64_t ldl,
+                                                   T* __restrict__ B, int64_t ldb) {
+  constexpr int WM = 64, CH = 16;
+  __shared__ T sL[WM * WM];  // sL[kk * WM + i] = L(i, kk)
+  __shared__ T sX[WM * 64];  // sX[i * 64 + lane] = row i of this lane's column
+  const int tid = threadIdx.x;
+  for (int e = tid; e < WM * WM; e += 64) {
+    const int i = e % WM, kk = e / WM;
+    sL[e] = (i < w && kk < w) ? L[i + (int64_t)kk * ldl] : T(0);
+  }
+  const int64_t c = (int64_t)blockIdx.x * 64 + tid;
+  const bool active = c < ncols;
+  T* col = B + (active ? c : 0) * ldb;
+  for (int i = 0; i < WM; ++i) sX[i * 64 + tid] = (active && i < w) ? col[i] : T(0);
+  __syncthreads();
+  const int nch = (w + CH - 1) / CH;
+  for (int q = 0; q < nch; ++q) {
+    const int ch = LOWER ? q : (nch - 1 - q);
+    const int r0 = ch * CH;
+    T x[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) x[i] = sX[(r0 + i) * 64 + tid];
+    if (LOWER) {
+      for (int kk = 0; kk < r0; ++kk) {  // finished rows above the chunk
+        const T xk = sX[kk * 64 + tid];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) x[i] = x[i] - sL[kk * WM + r0 + i] * xk;
+      }
+#pragma unroll
+      for (int kk = 0; kk < CH; ++kk) {
+        const T xk = x[kk];
+#pragma unroll
+        for (int i = kk + 1; i < CH; ++i) x[i] = x[i] - sL[(r0 + kk) * WM + r0 + i] * xk;
+      }
+    } else {
+      for (int kk = r0 + CH; kk < w; ++kk) {  // finished rows below the chunk
+        const T xk = sX[kk * 64 + tid];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) x[i] = x[i] - sL[kk * WM + r0 + i] * xk;
+      }
+#pragma unroll
+      for (int kk = CH - 1; kk >= 0; --kk) {
+        if (r0 + kk < w) x[kk] = x[kk] / sL[(r0 + kk) * WM + r0 + kk];
+        const T xk = x[kk];
+#pragma unroll
+        for (int i = 0; i < kk; ++i) x[i] = x[i] - sL[(r0 + kk) * WM + r0 + i] * xk;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < CH; ++i) sX[(r0 + i) * 64 + tid] = x[i];
+  }
+  if (active)
+    for (int i = 0; i < w; ++i) col[i] = sX[i * 64 + tid];
+}
+
 __global__ void k_set_int(int32_t* p, int32_t v) { *p = v; }
 
 }  // namespace
@@ -258,6 +318,23 @@ hipError_t trsm_leaf(hipStream_t s, bool lower, int64_t w, int64_t ncols, const 
                        ldb);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t trsm_small(hipStream_t s, bool lower, int64_t w, int64_t ncols, const T* L, int64_t ldl, T* B,
+                      int64_t ldb) {
+  if (w <= 0 || ncols <= 0) return hipSuccess;
+  if (w > 64) return hipErrorInvalidValue;
+  const int64_t blocks = (ncols + 63) / 64;
+  if (lower)
+    hipLaunchKernelGGL((k_trsm_small<T, true>), dim3((unsigned)blocks), dim3(64), 0, s, (int)w, ncols, L, ldl, B, ldb);
+  else
+    hipLaunchKernelGGL((k_trsm_small<T, false>), dim3((unsigned)blocks), dim3(64), 0, s, (int)w, ncols, L, ldl, B,
+                       ldb);
+  return hipGetLastError();
+}
+
+template hipError_t trsm_small<double>(hipStream_t, bool, int64_t, int64_t, const double*, int64_t, double*, int64_t);
+template hipError_t trsm_small<float>(hipStream_t, bool, int64_t, int64_t, const float*, int64_t, float*, int64_t);
 
 hipError_t set_int(hipStream_t s, int32_t* p, int32_t v) {
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, p, v);

@@ -39,18 +39,19 @@ struct Mfma<float> {
 // ---------------------------------------------------------------- workspace
 // Device-resident state of the cooperative panel kernel: one slot per
 // workgroup with its pivot candidate and the candidate's row, a copy of the
-// current diagonal row, per-workgroup progress flags and an error flag.
+// current diagonal row, per-workgroup progress flags and an error flag.  All
+// slot traffic uses device-coherent (agent-scope) atomic loads and stores.
 constexpr int kLeafMaxGroups = 128;
 constexpr int kLeafMaxWidth = 32;
 
 struct LeafSlots {
-  uint32_t flags[kLeafMaxGroups];                  // progress flag per workgroup
-  int32_t err;                                     // set when a bounded wait expires
+  uint32_t flags[kLeafMaxGroups];                     // progress flag per workgroup
+  int32_t err;                                        // set when a bounded wait expires
   int32_t pad_[31];
-  double cand_val[2][kLeafMaxGroups];              // |candidate|, double-buffered by column parity
-  int64_t cand_idx[2][kLeafMaxGroups];             // candidate row (panel-local)
+  double cand_val[2][kLeafMaxGroups];                 // |candidate|, double-buffered by column parity
+  int64_t cand_idx[2][kLeafMaxGroups];                // candidate row (panel-local)
   double cand_row[2][kLeafMaxGroups][kLeafMaxWidth];  // candidate row values (T stored as double)
-  double rowj[2][kLeafMaxWidth];                   // the diagonal row before the interchange
+  double rowj[2][kLeafMaxWidth];                      // the diagonal row before the interchange
 };
 
 // Row movement of a run of consecutive interchanges k1..k2-1 (k2 - k1 <=
@@ -75,11 +76,22 @@ hipError_t gemm_sub(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, 
 
 // Factor the r x w column block P (leading dimension ld) whose first row and
 // column are the global row/column k: partial pivoting column by column, the
-// interchanges applied across the w columns of the block.  Writes
-// ipiv[k + j] = k + piv + 1 and, on the first exactly zero pivot, *info.
+// interchanges applied across the w columns of the block and also to the
+// columns P[:, c] for c in [oc_lo, 0) and [w, oc_hi) (the rest of the
+// enclosing column block).  Writes ipiv[k + j] = k + piv + 1 and, on the first
+// exactly zero pivot, *info.
 template <typename T>
 hipError_t panel_leaf(hipStream_t s, int64_t r, int w, T* P, int64_t ld, int32_t* ipiv, int64_t k,
-                      int32_t* info, LeafSlots* ws, uint32_t epoch);
+                      int32_t* info, LeafSlots* ws, uint32_t epoch, int64_t oc_lo, int64_t oc_hi);
+
+// Number of cooperating workgroups panel_leaf uses for r rows.
+int panel_groups(int64_t r);
+
+// Triangular solve, one thread per right-hand column kept in registers
+// (w <= 64): lower = unit lower (forward), else non-unit upper (backward).
+template <typename T>
+hipError_t trsm_small(hipStream_t s, bool lower, int64_t w, int64_t ncols, const T* L, int64_t ldl, T* B,
+                      int64_t ldb);
 
 // Compose interchanges k1..k2-1 (ipiv, 1-based rows of an m-row matrix) into
 // *pairs (one workgroup).

@@ -40,10 +40,19 @@ struct lupp_handle_st {
   bool timing = false;
   std::vector<lupp::TimingRecord> records;  // events are created once and reused
   size_t nrecords = 0;
+  int lookahead = 1;                // factor the next column block on a side stream
+  hipStream_t side = nullptr;       // panel stream, restricted to panel_cus CUs
+  hipStream_t bulk = nullptr;       // trailing-update stream, restricted to the other CUs
+  int panel_cus = 0;                // CUs reserved for the panel while they overlap
+  hipEvent_t ev_cols = nullptr;     // next block's columns updated (main -> side, bulk)
+  hipEvent_t ev_panel = nullptr;    // next block factored (side -> main)
+  hipEvent_t ev_bulk = nullptr;     // bulk update done (bulk -> main)
 };
 
 namespace lupp {
 namespace {
+
+constexpr int kLookaheadPanelCUs = 32;
 
 inline int hip_status(hipError_t e) { return e == hipSuccess ? LUPP_OK : LUPP_ERR_HIP + (int)e; }
 
@@ -55,9 +64,9 @@ inline int hip_status(hipError_t e) { return e == hipSuccess ? LUPP_OK : LUPP_ER
 
 // Epoch of the panel kernel's progress flags: every launch uses flag values
 // above all values written before; the flags are cleared before wrap-around.
-inline hipError_t next_epoch(lupp_handle_t h, int w, uint32_t* out) {
+inline hipError_t next_epoch(lupp_handle_t h, hipStream_t st, int w, uint32_t* out) {
   if (h->epoch > 0xF0000000u) {
-    LUPP_TRY(reset_flags(h->stream, h->slots));
+    LUPP_TRY(reset_flags(st, h->slots));
     h->epoch = 0;
   }
   *out = h->epoch;
@@ -66,7 +75,7 @@ inline hipError_t next_epoch(lupp_handle_t h, int w, uint32_t* out) {
 }
 
 // Phase timing: HIP events on the handle's stream around a phase's launches.
-int timer_begin(lupp_handle_t h, int phase) {
+int timer_begin(lupp_handle_t h, int phase, hipStream_t st) {
   if (!h->timing) return -1;
   if (h->nrecords == h->records.size()) {
     TimingRecord r;
@@ -78,25 +87,25 @@ int timer_begin(lupp_handle_t h, int phase) {
     h->records.push_back(r);
   }
   TimingRecord& r = h->records[h->nrecords];
-  if (hipEventRecord(r.start, h->stream) != hipSuccess) return -1;
+  if (hipEventRecord(r.start, st) != hipSuccess) return -1;
   r.phase = phase;
   r.big = false;
   r.flops = 0.0;
   return (int)h->nrecords++;
 }
 
-void timer_end(lupp_handle_t h, int idx, double flops, bool big = false) {
+void timer_end(lupp_handle_t h, int idx, hipStream_t st, double flops, bool big = false) {
   if (idx < 0) return;
   TimingRecord& r = h->records[idx];
   r.flops = flops;
   r.big = big;
-  (void)hipEventRecord(r.stop, h->stream);
+  (void)hipEventRecord(r.stop, st);
 }
 
 // B (w x ncols) := inv(L) * B with L unit lower triangular (w x w).
 template <typename T>
 hipError_t trsm_lower_unit(hipStream_t s, int64_t w, int64_t ncols, const T* L, int64_t ldl, T* B, int64_t ldb) {
-  if (w <= 64) return trsm_leaf<T>(s, true, w, ncols, L, ldl, B, ldb);
+  if (w <= 64) return trsm_small<T>(s, true, w, ncols, L, ldl, B, ldb);
   const int64_t w1 = w / 2;
   LUPP_TRY(trsm_lower_unit<T>(s, w1, ncols, L, ldl, B, ldb));
   LUPP_TRY(gemm_sub<T>(s, w - w1, ncols, w1, L + w1, ldl, B, ldb, B + w1, ldb));
@@ -106,72 +115,117 @@ hipError_t trsm_lower_unit(hipStream_t s, int64_t w, int64_t ncols, const T* L, 
 // B (w x ncols) := inv(U) * B with U upper triangular, non-unit (w x w).
 template <typename T>
 hipError_t trsm_upper(hipStream_t s, int64_t w, int64_t ncols, const T* U, int64_t ldu, T* B, int64_t ldb) {
-  if (w <= 64) return trsm_leaf<T>(s, false, w, ncols, U, ldu, B, ldb);
+  if (w <= 64) return trsm_small<T>(s, false, w, ncols, U, ldu, B, ldb);
   const int64_t w1 = w / 2;
   LUPP_TRY(trsm_upper<T>(s, w - w1, ncols, U + w1 + w1 * ldu, ldu, B + w1, ldb));
   LUPP_TRY(gemm_sub<T>(s, w1, ncols, w - w1, U + w1 * ldu, ldu, B + w1, ldb, B, ldb));
   return trsm_upper<T>(s, w1, ncols, U, ldu, B, ldb);
 }
 
-// Recursive column-block factorization of columns [k, k+w), rows [k, m).
+// Recursive column-block factorization of columns [k, k+w), rows [k, m),
+// inside the enclosing column block [p0, p1): the leaves apply their
+// interchanges to every column of [p0, p1), so the recursion itself moves no
+// rows.  Split: factor the left half; U12 := inv(L11) * A12; A22 -= A21 * U12;
+// factor the right half (which also interchanges rows of the left half).
 template <typename T>
-hipError_t panel(lupp_handle_t h, int64_t m, int64_t k, int64_t w, T* A, int64_t lda, int32_t* ipiv, int32_t* info) {
-  hipStream_t s = h->stream;
+hipError_t panel(lupp_handle_t h, hipStream_t s, int64_t m, int64_t k, int64_t w, int64_t p0, int64_t p1, T* A,
+                 int64_t lda, int32_t* ipiv, int32_t* info) {
   if (w <= h->leaf) {
     uint32_t ep;
-    LUPP_TRY(next_epoch(h, (int)w, &ep));
-    const int t = timer_begin(h, LUPP_PHASE_PANEL_LEAF);
-    LUPP_TRY(panel_leaf<T>(s, m - k, (int)w, A + k + k * lda, lda, ipiv, k, info, h->slots, ep));
-    timer_end(h, t, 0.0);
+    LUPP_TRY(next_epoch(h, s, (int)w, &ep));
+    const int t = timer_begin(h, LUPP_PHASE_PANEL_LEAF, s);
+    LUPP_TRY(panel_leaf<T>(s, m - k, (int)w, A + k + k * lda, lda, ipiv, k, info, h->slots, ep, p0 - k, p1 - k));
+    timer_end(h, t, s, 0.0);
     return hipSuccess;
   }
   int64_t w1 = w / 2;
   if (w1 > 8) w1 = (w1 / 8) * 8;
   const int64_t w2 = w - w1;
-  LUPP_TRY(panel<T>(h, m, k, w1, A, lda, ipiv, info));
-  int t = timer_begin(h, LUPP_PHASE_PANEL_SWAP);
-  LUPP_TRY(laswp<T>(s, A, lda, m, k + w1, k + w, 0, 0, ipiv, k, k + w1, h->pairs));
-  timer_end(h, t, 0.0);
-  t = timer_begin(h, LUPP_PHASE_PANEL_TRSM);
-  LUPP_TRY(trsm_lower_unit<T>(s, w1, w2, A + k + k * lda, lda, A + k + (k + w1) * lda, lda));
-  timer_end(h, t, (double)w1 * (double)w1 * (double)w2);
-  t = timer_begin(h, LUPP_PHASE_PANEL_GEMM);
+  LUPP_TRY(panel<T>(h, s, m, k, w1, p0, p1, A, lda, ipiv, info));
+  int t = timer_begin(h, LUPP_PHASE_PANEL_TRSM, s);
+  if (w1 <= 64)
+    LUPP_TRY(trsm_small<T>(s, true, w1, w2, A + k + k * lda, lda, A + k + (k + w1) * lda, lda));
+  else
+    LUPP_TRY(trsm_lower_unit<T>(s, w1, w2, A + k + k * lda, lda, A + k + (k + w1) * lda, lda));
+  timer_end(h, t, s, (double)w1 * (double)w1 * (double)w2);
+  t = timer_begin(h, LUPP_PHASE_PANEL_GEMM, s);
   LUPP_TRY(gemm_sub<T>(s, m - k - w1, w2, w1, A + (k + w1) + k * lda, lda, A + k + (k + w1) * lda, lda,
                        A + (k + w1) + (k + w1) * lda, lda));
-  timer_end(h, t, 2.0 * (double)(m - k - w1) * (double)w2 * (double)w1);
-  LUPP_TRY(panel<T>(h, m, k + w1, w2, A, lda, ipiv, info));
-  t = timer_begin(h, LUPP_PHASE_PANEL_SWAP);
-  LUPP_TRY(laswp<T>(s, A, lda, m, k, k + w1, 0, 0, ipiv, k + w1, k + w, h->pairs));
-  timer_end(h, t, 0.0);
+  timer_end(h, t, s, 2.0 * (double)(m - k - w1) * (double)w2 * (double)w1);
+  return panel<T>(h, s, m, k + w1, w2, p0, p1, A, lda, ipiv, info);
+}
+
+// Column block [k, k+b): factor it on stream st, with its phase timing.
+template <typename T>
+hipError_t factor_block(lupp_handle_t h, hipStream_t st, int64_t m, int64_t k, int64_t b, T* A, int64_t lda,
+                        int32_t* ipiv, int32_t* info) {
+  const int t = timer_begin(h, LUPP_PHASE_PANEL, st);
+  LUPP_TRY(panel<T>(h, st, m, k, b, k, k + b, A, lda, ipiv, info));
+  timer_end(h, t, st, 0.0);
   return hipSuccess;
 }
 
+// Blocked right-looking factorization with depth-1 lookahead: while the bulk
+// of step k's trailing update runs on the main stream, the next column block
+// (whose columns are updated first) is factored on the side stream.  The
+// paper removes the same synchronization point of the column-block
+// factorization by scheduling its tasks out of order (Section 4.1,
+// algorithm-by-blocks; Section 4.4, the runtime's dataflow order); here the
+// dataflow is fixed and expressed with two streams and two events per step.
 template <typename T>
 hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32_t* ipiv, int32_t* info) {
   hipStream_t s = h->stream;
   LUPP_TRY(set_int(s, info, 0));
   const int64_t p = m < n ? m : n;
+  if (p == 0) return hipSuccess;
+  const bool la = h->lookahead && h->side && h->bulk;
+  LUPP_TRY(factor_block<T>(h, s, m, 0, (p < h->nb) ? p : h->nb, A, lda, ipiv, info));
   for (int64_t k = 0; k < p; k += h->nb) {
     const int64_t b = (p - k < h->nb) ? (p - k) : h->nb;
-    int t = timer_begin(h, LUPP_PHASE_PANEL);
-    LUPP_TRY(panel<T>(h, m, k, b, A, lda, ipiv, info));
-    timer_end(h, t, 0.0);
+    const int64_t kn = k + b;
+    const int64_t bn = (kn < p) ? ((p - kn < h->nb) ? (p - kn) : h->nb) : 0;
     // interchanges of this block on every column outside it
-    t = timer_begin(h, LUPP_PHASE_LASWP);
+    int t = timer_begin(h, LUPP_PHASE_LASWP, s);
     LUPP_TRY(laswp<T>(s, A, lda, m, 0, n, k, k + b, ipiv, k, k + b, h->pairs));
-    timer_end(h, t, 0.0);
-    if (k + b < n) {
-      const int64_t nr = n - k - b;
-      t = timer_begin(h, LUPP_PHASE_TRSM);
-      LUPP_TRY(trsm_lower_unit<T>(s, b, nr, A + k + k * lda, lda, A + k + (k + b) * lda, lda));
-      timer_end(h, t, (double)b * (double)b * (double)nr);
-      if (k + b < m) {
-        const int64_t mr = m - k - b;
+    timer_end(h, t, s, 0.0);
+    if (kn < n) {
+      const int64_t nr = n - kn;
+      t = timer_begin(h, LUPP_PHASE_TRSM, s);
+      LUPP_TRY(trsm_lower_unit<T>(s, b, nr, A + k + k * lda, lda, A + k + kn * lda, lda));
+      timer_end(h, t, s, (double)b * (double)b * (double)nr);
+      const int64_t mr = m - kn;
+      // columns of the next block first, so that it can be factored early
+      const int64_t n1 = (mr > 0) ? bn : 0;
+      if (n1 > 0) {
+        t = timer_begin(h, LUPP_PHASE_UPDATE, s);
+        LUPP_TRY(gemm_sub<T>(s, mr, n1, b, A + kn + k * lda, lda, A + k + kn * lda, lda, A + kn + kn * lda, lda));
+        timer_end(h, t, s, 2.0 * (double)mr * (double)n1 * (double)b);
+      }
+      // overlap only when the next block's cooperative factorization fits in
+      // the reserved CUs (one workgroup per CU at most)
+      const bool overlap = la && n1 > 0 && panel_groups(mr) <= h->panel_cus && nr > n1;
+      hipStream_t su = s;
+      if (overlap) {
+        LUPP_TRY(hipEventRecord(h->ev_cols, s));
+        LUPP_TRY(hipStreamWaitEvent(h->side, h->ev_cols, 0));
+        LUPP_TRY(hipStreamWaitEvent(h->bulk, h->ev_cols, 0));
+        LUPP_TRY(factor_block<T>(h, h->side, m, kn, bn, A, lda, ipiv, info));
+        LUPP_TRY(hipEventRecord(h->ev_panel, h->side));
+        su = h->bulk;
+      }
+      if (mr > 0 && nr > n1) {
         int tile = -1;
-        t = timer_begin(h, LUPP_PHASE_UPDATE);
-        LUPP_TRY(gemm_sub<T>(s, mr, nr, b, A + (k + b) + k * lda, lda, A + k + (k + b) * lda, lda,
-                             A + (k + b) + (k + b) * lda, lda, &tile));
-        timer_end(h, t, 2.0 * (double)mr * (double)nr * (double)b, tile == 1);
+        t = timer_begin(h, LUPP_PHASE_UPDATE, su);
+        LUPP_TRY(gemm_sub<T>(su, mr, nr - n1, b, A + kn + k * lda, lda, A + k + (kn + n1) * lda, lda,
+                             A + kn + (kn + n1) * lda, lda, &tile));
+        timer_end(h, t, su, 2.0 * (double)mr * (double)(nr - n1) * (double)b, tile == 1);
+      }
+      if (overlap) {
+        LUPP_TRY(hipEventRecord(h->ev_bulk, h->bulk));
+        LUPP_TRY(hipStreamWaitEvent(s, h->ev_bulk, 0));
+        LUPP_TRY(hipStreamWaitEvent(s, h->ev_panel, 0));
+      } else if (n1 > 0) {
+        LUPP_TRY(factor_block<T>(h, s, m, kn, bn, A, lda, ipiv, info));
       }
     }
   }
@@ -201,6 +255,25 @@ hipError_t ensure_workspace(lupp_handle_t h) {
   h->slots = (LeafSlots*)p;
   h->pairs = (SwapPairs*)((char*)p + sizeof(LeafSlots));
   h->epoch = 0;
+  // lookahead streams: the panel's CUs and the bulk update's CUs are disjoint,
+  // so the latency-bound panel is not slowed by co-resident GEMM workgroups
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || ncu < 64) {
+    h->lookahead = 0;
+    return hipSuccess;
+  }
+  h->panel_cus = kLookaheadPanelCUs;
+  std::vector<uint32_t> mside((ncu + 31) / 32, 0u), mbulk((ncu + 31) / 32, 0u);
+  for (int c = 0; c < ncu; ++c) {
+    if (c < h->panel_cus) mside[c / 32] |= 1u << (c % 32);
+    else mbulk[c / 32] |= 1u << (c % 32);
+  }
+  if (hipExtStreamCreateWithCUMask(&h->side, (uint32_t)mside.size(), mside.data()) != hipSuccess) h->side = nullptr;
+  if (hipExtStreamCreateWithCUMask(&h->bulk, (uint32_t)mbulk.size(), mbulk.data()) != hipSuccess) h->bulk = nullptr;
+  if (!h->side || !h->bulk || hipEventCreateWithFlags(&h->ev_cols, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_bulk, hipEventDisableTiming) != hipSuccess)
+    h->lookahead = 0;
   return hipSuccess;
 }
 
@@ -262,6 +335,13 @@ int lupp_destroy(lupp_handle_t h) {
     (void)hipEventDestroy(r.start);
     (void)hipEventDestroy(r.stop);
   }
+  if (h->side) (void)hipStreamSynchronize(h->side);
+  if (h->bulk) (void)hipStreamSynchronize(h->bulk);
+  if (h->ev_cols) (void)hipEventDestroy(h->ev_cols);
+  if (h->ev_panel) (void)hipEventDestroy(h->ev_panel);
+  if (h->ev_bulk) (void)hipEventDestroy(h->ev_bulk);
+  if (h->side) (void)hipStreamDestroy(h->side);
+  if (h->bulk) (void)hipStreamDestroy(h->bulk);
   if (h->slots) (void)hipFree(h->slots);
   delete h;
   return rc;
@@ -277,7 +357,7 @@ int lupp_set_option(lupp_handle_t h, int option, int64_t value) {
   if (!h) return -1;
   switch (option) {
     case LUPP_OPT_NB:
-      if (value < 1 || value > 4096) return -3;
+      if (value < 1 || value > 1024) return -3;
       h->nb = value;
       return LUPP_OK;
     case LUPP_OPT_PANEL_LEAF:
@@ -288,6 +368,10 @@ int lupp_set_option(lupp_handle_t h, int option, int64_t value) {
       if (value != 0 && value != 1) return -3;
       h->timing = value != 0;
       return LUPP_OK;
+    case LUPP_OPT_LOOKAHEAD:
+      if (value != 0 && value != 1) return -3;
+      h->lookahead = (int)value;
+      return LUPP_OK;
     default:
       return -2;
   }
@@ -296,6 +380,8 @@ int lupp_set_option(lupp_handle_t h, int option, int64_t value) {
 int lupp_sync(lupp_handle_t h) {
   if (!h) return -1;
   hipError_t e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess && h->side) e = hipStreamSynchronize(h->side);
+  if (e == hipSuccess && h->bulk) e = hipStreamSynchronize(h->bulk);
   if (e != hipSuccess) return lupp::hip_status(e);
   if (h->slots) {
     int32_t err = 0;
@@ -317,6 +403,8 @@ int lupp_timing_summary(lupp_handle_t h, int phase, int64_t* count, double* ms, 
   if (!ms) return -4;
   if (!flops) return -5;
   hipError_t e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess && h->side) e = hipStreamSynchronize(h->side);
+  if (e == hipSuccess && h->bulk) e = hipStreamSynchronize(h->bulk);
   if (e != hipSuccess) return lupp::hip_status(e);
   *count = 0;
   *ms = 0.0;

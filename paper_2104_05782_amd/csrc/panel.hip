@@ -4,26 +4,32 @@
 // (Section 4.1).  Its latency is a chain of w dependent pivot decisions, each
 // a reduction over all r rows of the block.
 //
-// Design (gfx950): G workgroups of 256 threads split the r rows; every thread
-// keeps RPT rows x W columns of the block in registers for the whole call, so
-// the rank-1 updates never touch memory.  Per column j:
-//   1. each thread scans its rows, wavefront shuffles and LDS reduce to the
-//      workgroup's best (|a|, row) under the total order (|a| desc, row asc):
-//      any reduction tree then reproduces the sequential first-maximum scan;
-//   2. with G > 1 each workgroup publishes its candidate and the candidate's
-//      row (and the owner of row j publishes row j) to its own slot, then
-//      raises its own progress flag; every workgroup polls all G flags (no
-//      shared counter, so no atomic contention) and reduces the G candidates;
+// Design (gfx950): G workgroups split the r rows; every thread keeps RPT rows
+// x W columns of the block in registers for the whole call, so the rank-1
+// updates never touch memory.  Per column j:
+//   1. each thread scans its rows; wavefront shuffles and an LDS step reduce
+//      to the workgroup's best (|a|, row) under the total order (|a| desc, row
+//      asc), so any reduction tree reproduces the sequential first-maximum
+//      scan;
+//   2. with G > 1 each workgroup publishes its candidate, the candidate's row
+//      (and, from the owner of row j, row j) with device-coherent stores,
+//      waits for their completion, and raises its own progress flag; every
+//      workgroup polls the G flags (no shared counter: no atomic contention),
+//      then reads all G candidates and candidate rows in one round trip;
 //   3. interchange (the two owning threads exchange whole rows), true-division
 //      scaling of column j, rank-1 update of the remaining columns.
+// The same interchange is applied to the other columns of the enclosing
+// column block by threads that own one such column each; a step's loads are
+// issued as soon as the pivot is known and its stores in the next step, so
+// their latency hides behind the next pivot search.
 // Wait loops are bounded: an expired wait sets ws->err and the kernel finishes.
 #include "common.h"
 
 namespace lupp {
 namespace {
 
-constexpr int NT = 256;
 constexpr long kSpinLimit = 1L << 22;
+constexpr int kMaxOther = 4;  // other columns per thread
 
 __device__ __forceinline__ bool better(double v, int64_t i, double bv, int64_t bi) {
   return v > bv || (v == bv && i < bi);
@@ -38,22 +44,101 @@ __device__ __forceinline__ uint64_t ld_u64(const void* p) {
 __device__ __forceinline__ void st_f64(double* p, double v) { st_u64(p, __double_as_longlong(v)); }
 __device__ __forceinline__ double ld_f64(const double* p) { return __longlong_as_double(ld_u64(p)); }
 
-template <typename T, int W, int RPT>
+// Wavefront argmax of (|a|, row) under the total order (|a| desc, row asc).
+// |a| >= 0, so its binary64 pattern read as an unsigned integer is ordered
+// like the value.  Four DPP steps (partners lane^1, lane^2, the mirror inside
+// 8 lanes, the mirror inside 16) leave every lane with its 16-lane row's
+// winner; the four row winners are then read as uniform values and combined.
+// No LDS round trip (ds_bpermute) is involved.
+__device__ __forceinline__ bool key_better(uint32_t hi, uint32_t lo, uint32_t idx, uint32_t bhi, uint32_t blo,
+                                           uint32_t bidx) {
+  return hi > bhi || (hi == bhi && (lo > blo || (lo == blo && idx < bidx)));
+}
+
+template <int CTRL>
+__device__ __forceinline__ void dpp_step(uint32_t& hi, uint32_t& lo, uint32_t& idx) {
+  const uint32_t ohi = (uint32_t)__builtin_amdgcn_update_dpp((int)hi, (int)hi, CTRL, 0xF, 0xF, false);
+  const uint32_t olo = (uint32_t)__builtin_amdgcn_update_dpp((int)lo, (int)lo, CTRL, 0xF, 0xF, false);
+  const uint32_t oidx = (uint32_t)__builtin_amdgcn_update_dpp((int)idx, (int)idx, CTRL, 0xF, 0xF, false);
+  if (key_better(ohi, olo, oidx, hi, lo, idx)) {
+    hi = ohi;
+    lo = olo;
+    idx = oidx;
+  }
+}
+
+// returns the wavefront's winner in every lane (value as double, row index)
+__device__ __forceinline__ void wave_argmax(double& v, int64_t& i) {
+  const uint64_t bits = (uint64_t)__double_as_longlong(v);
+  uint32_t hi = (uint32_t)(bits >> 32), lo = (uint32_t)bits;
+  // an empty candidate (v < 0) must lose to any real one: map it to key 0 and
+  // the largest index
+  uint32_t idx = (v < 0.0 || i >= INT32_MAX) ? 0xFFFFFFFFu : (uint32_t)i;
+  if (v < 0.0) hi = lo = 0;
+  dpp_step<0xB1>(hi, lo, idx);   // quad_perm(1,0,3,2)
+  dpp_step<0x4E>(hi, lo, idx);   // quad_perm(2,3,0,1)
+  dpp_step<0x141>(hi, lo, idx);  // row_half_mirror
+  dpp_step<0x140>(hi, lo, idx);  // row_mirror
+  uint32_t bhi = __builtin_amdgcn_readlane(hi, 0), blo = __builtin_amdgcn_readlane(lo, 0),
+           bidx = __builtin_amdgcn_readlane(idx, 0);
+#pragma unroll
+  for (int rrow = 1; rrow < 4; ++rrow) {
+    const uint32_t h2 = __builtin_amdgcn_readlane(hi, rrow * 16), l2 = __builtin_amdgcn_readlane(lo, rrow * 16),
+                   i2 = __builtin_amdgcn_readlane(idx, rrow * 16);
+    if (key_better(h2, l2, i2, bhi, blo, bidx)) {
+      bhi = h2;
+      blo = l2;
+      bidx = i2;
+    }
+  }
+  if (bidx == 0xFFFFFFFFu) {
+    v = -1.0;
+    i = INT64_MAX;
+  } else {
+    v = __longlong_as_double((long long)(((uint64_t)bhi << 32) | blo));
+    i = (int64_t)bidx;
+  }
+}
+
+// wait until this thread's stores have completed (reached the coherence point)
+__device__ __forceinline__ void drain_stores() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Workgroup barrier that waits only for LDS traffic.  (__syncthreads also
+// waits for every outstanding global load and store of the wave, which would
+// put a memory round trip on each pivot step.)  The signal fences keep the
+// compiler from moving LDS accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), vmcnt and expcnt untouched
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+template <typename T, int W, int RPT, int NT>
 __global__ __launch_bounds__(NT) void k_panel_leaf(int64_t r, int w, T* __restrict__ P, int64_t ld,
                                                    int32_t* __restrict__ ipiv, int64_t k,
                                                    int32_t* __restrict__ info, LeafSlots* __restrict__ ws,
-                                                   uint32_t epoch) {
+                                                   uint32_t epoch, int64_t oc_lo, int64_t oc_hi) {
+  constexpr int NW = NT / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = blockIdx.x, G = gridDim.x;
   const int64_t rbase = (int64_t)g * NT * RPT;
 
   __shared__ T s_prow[W];
   __shared__ T s_rowj[W];
-  __shared__ double s_wv[NT / 64];
-  __shared__ int64_t s_wi[NT / 64];
-  __shared__ double s_bv;
+  __shared__ double s_wv[2][NW];
+  __shared__ int64_t s_wi[2][NW];
   __shared__ int64_t s_bi;
   __shared__ int s_broken;
+  __shared__ int32_t s_ipiv[W];
+  __shared__ int32_t s_zero;
+  __shared__ double s_cv[kLeafMaxGroups];
+  __shared__ int64_t s_ci[kLeafMaxGroups];
+  __shared__ double s_crow[kLeafMaxGroups * W];
 
   T a[RPT][W];
 #pragma unroll
@@ -62,7 +147,27 @@ __global__ __launch_bounds__(NT) void k_panel_leaf(int64_t r, int w, T* __restri
 #pragma unroll
     for (int c = 0; c < W; ++c) a[q][c] = (i < r && c < w) ? P[i + c * ld] : T(0);
   }
-  if (tid == 0) s_broken = 0;
+
+  // other columns of the enclosing block owned by this thread
+  const int64_t n_left = -oc_lo, n_other = n_left + (oc_hi - w);
+  const int64_t gt = (int64_t)g * NT + tid, gstride = (int64_t)G * NT;
+  T* ocol[kMaxOther];
+  bool own[kMaxOther];
+#pragma unroll
+  for (int u = 0; u < kMaxOther; ++u) {
+    const int64_t q = gt + u * gstride;
+    own[u] = q < n_other;
+    const int64_t c = (q < n_left) ? (oc_lo + q) : (w + (q - n_left));
+    ocol[u] = P + (own[u] ? c : 0) * ld;
+  }
+  bool pend = false;
+  int64_t prj = 0, prp = 0;
+  T pvj[kMaxOther], pvp[kMaxOther];
+
+  if (tid == 0) {
+    s_broken = 0;
+    s_zero = 0;
+  }
   __syncthreads();
 
   for (int j = 0; j < w; ++j) {
@@ -83,36 +188,24 @@ __global__ __launch_bounds__(NT) void k_panel_leaf(int64_t r, int w, T* __restri
         bi = i;
       }
     }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ov = __shfl_xor(bv, off);
-      const int64_t oi = __shfl_xor(bi, off);
-      if (better(ov, oi, bv, bi)) {
-        bv = ov;
-        bi = oi;
-      }
-    }
+    wave_argmax(bv, bi);
     if (lane == 0) {
-      s_wv[wave] = bv;
-      s_wi[wave] = bi;
+      s_wv[par][wave] = bv;
+      s_wi[par][wave] = bi;
     }
-    __syncthreads();
-    if (tid == 0) {
-      double v = s_wv[0];
-      int64_t i = s_wi[0];
+    lds_barrier();
+    // every thread combines the wavefront candidates itself (no extra barrier)
+    double wg_v = s_wv[par][0];
+    int64_t wg_best = s_wi[par][0];
 #pragma unroll
-      for (int q = 1; q < NT / 64; ++q)
-        if (better(s_wv[q], s_wi[q], v, i)) {
-          v = s_wv[q];
-          i = s_wi[q];
-        }
-      s_bv = v;
-      s_bi = i;
-    }
-    __syncthreads();
-    const int64_t wg_best = s_bi;
+    for (int q = 1; q < NW; ++q)
+      if (better(s_wv[par][q], s_wi[par][q], wg_v, wg_best)) {
+        wg_v = s_wv[par][q];
+        wg_best = s_wi[par][q];
+      }
 
     // 2. publish and combine
+    int64_t gbest;
     if (G == 1) {
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
@@ -126,31 +219,34 @@ __global__ __launch_bounds__(NT) void k_panel_leaf(int64_t r, int w, T* __restri
           for (int c = 0; c < W; ++c) s_rowj[c] = a[q][c];
         }
       }
-      __syncthreads();
+      lds_barrier();
+      gbest = wg_best;
     } else {
+      bool wrote = false;
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
         const int64_t i = rbase + q * NT + tid;
         if (i == wg_best && wg_best < r) {
 #pragma unroll
           for (int c = 0; c < W; ++c) st_f64(&ws->cand_row[par][g][c], (double)a[q][c]);
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          wrote = true;
         }
         if (i == j) {
 #pragma unroll
           for (int c = 0; c < W; ++c) st_f64(&ws->rowj[par][c], (double)a[q][c]);
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          wrote = true;
         }
       }
       if (tid == 0) {
-        st_f64(&ws->cand_val[par][g], s_bv);
-        st_u64(&ws->cand_idx[par][g], (uint64_t)s_bi);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        st_f64(&ws->cand_val[par][g], wg_v);
+        st_u64(&ws->cand_idx[par][g], (uint64_t)wg_best);
+        wrote = true;
       }
-      __syncthreads();
+      if (wrote) drain_stores();
+      lds_barrier();
       const uint32_t target = epoch + (uint32_t)j + 1u;
-      if (tid == 0) __hip_atomic_store(&ws->flags[g], target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       if (wave == 0) {
+        if (lane == 0) __hip_atomic_store(&ws->flags[g], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (!s_broken) {
           long spins = 0;
           for (;;) {
@@ -167,47 +263,65 @@ __global__ __launch_bounds__(NT) void k_panel_leaf(int64_t r, int w, T* __restri
             }
           }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      lds_barrier();
+      // one round trip: every candidate, every candidate row, row j
+      for (int q = tid; q < G; q += NT) {
+        s_cv[q] = ld_f64(&ws->cand_val[par][q]);
+        s_ci[q] = (int64_t)ld_u64(&ws->cand_idx[par][q]);
+      }
+      for (int e = tid; e < G * W; e += NT) s_crow[e] = ld_f64(&ws->cand_row[par][e / W][e % W]);
+      if (tid < W) s_rowj[tid] = (T)ld_f64(&ws->rowj[par][tid]);
+      lds_barrier();
+      if (wave == 0) {
         double v = -1.0;
         int64_t i = INT64_MAX;
-        int gw = 0;
         for (int q = lane; q < G; q += 64) {
-          const double qv = ld_f64(&ws->cand_val[par][q]);
-          const int64_t qi = (int64_t)ld_u64(&ws->cand_idx[par][q]);
-          if (better(qv, qi, v, i)) {
-            v = qv;
-            i = qi;
-            gw = q;
+          if (better(s_cv[q], s_ci[q], v, i)) {
+            v = s_cv[q];
+            i = s_ci[q];
           }
         }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-          const double ov = __shfl_xor(v, off);
-          const int64_t oi = __shfl_xor(i, off);
-          const int og = __shfl_xor(gw, off);
-          if (better(ov, oi, v, i)) {
-            v = ov;
-            i = oi;
-            gw = og;
-          }
-        }
-        if (lane < W) {
-          s_prow[lane] = (T)ld_f64(&ws->cand_row[par][gw][lane]);
-          s_rowj[lane] = (T)ld_f64(&ws->rowj[par][lane]);
-        }
+        wave_argmax(v, i);
+        // the winning row index identifies its workgroup
+        const int gw = (i == INT64_MAX) ? 0 : (int)(i / ((int64_t)NT * RPT));
+        if (lane < W) s_prow[lane] = (T)s_crow[gw * W + lane];
         if (lane == 0) s_bi = i;
       }
-      __syncthreads();
+      lds_barrier();
+      gbest = s_bi;
     }
 
     // 3. interchange, scale, update (a winner outside the block can only come
     // from NaN input: keep the diagonal row then)
-    int64_t piv = s_bi;
+    int64_t piv = gbest;
     if (piv < j || piv >= r) piv = j;
     const T pv = s_prow[j];
-    if (g == 0 && tid == 0) {
-      ipiv[k + j] = (int32_t)(k + piv + 1);
-      if (pv == T(0) && *info == 0) *info = (int32_t)(k + j + 1);
+    if (tid == 0) {
+      s_ipiv[j] = (int32_t)(k + piv + 1);
+      if (pv == T(0) && s_zero == 0) s_zero = (int32_t)(k + j + 1);
+    }
+    // the same interchange on the other columns of the enclosing block:
+    // stores of the previous step, loads of this one
+    if (pend) {
+#pragma unroll
+      for (int u = 0; u < kMaxOther; ++u)
+        if (own[u]) {
+          ocol[u][prj] = pvp[u];
+          ocol[u][prp] = pvj[u];
+        }
+      pend = false;
+    }
+    if (piv != j && pv != T(0)) {
+#pragma unroll
+      for (int u = 0; u < kMaxOther; ++u)
+        if (own[u]) {
+          pvj[u] = ocol[u][j];
+          pvp[u] = ocol[u][piv];
+        }
+      pend = true;
+      prj = j;
+      prp = piv;
     }
     if (pv != T(0)) {
 #pragma unroll
@@ -234,9 +348,23 @@ __global__ __launch_bounds__(NT) void k_panel_leaf(int64_t r, int w, T* __restri
         }
       }
     }
-    __syncthreads();
+    // s_prow/s_rowj are rewritten only after the next column's first barrier,
+    // which every wave reaches after finishing this column
   }
 
+  if (pend) {
+#pragma unroll
+    for (int u = 0; u < kMaxOther; ++u)
+      if (own[u]) {
+        ocol[u][prj] = pvp[u];
+        ocol[u][prp] = pvj[u];
+      }
+  }
+  lds_barrier();  // s_ipiv / s_zero complete
+  if (g == 0) {
+    for (int jj = tid; jj < w; jj += NT) ipiv[k + jj] = s_ipiv[jj];
+    if (tid == 0 && s_zero != 0 && *info == 0) *info = s_zero;
+  }
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int64_t i = rbase + q * NT + tid;
@@ -252,10 +380,11 @@ __global__ void k_reset_flags(LeafSlots* ws) {
   for (int i = threadIdx.x; i < kLeafMaxGroups; i += blockDim.x) ws->flags[i] = 0;
 }
 
-template <typename T, int W, int RPT>
+template <typename T, int W, int RPT, int NT>
 hipError_t launch_leaf(hipStream_t s, int G, int64_t r, int w, T* P, int64_t ld, int32_t* ipiv, int64_t k,
-                       int32_t* info, LeafSlots* ws, uint32_t epoch) {
-  hipLaunchKernelGGL((k_panel_leaf<T, W, RPT>), dim3(G), dim3(NT), 0, s, r, w, P, ld, ipiv, k, info, ws, epoch);
+                       int32_t* info, LeafSlots* ws, uint32_t epoch, int64_t oc_lo, int64_t oc_hi) {
+  hipLaunchKernelGGL((k_panel_leaf<T, W, RPT, NT>), dim3(G), dim3(NT), 0, s, r, w, P, ld, ipiv, k, info, ws, epoch,
+                     oc_lo, oc_hi);
   return hipGetLastError();
 }
 
@@ -266,32 +395,47 @@ hipError_t reset_flags(hipStream_t s, LeafSlots* ws) {
   return hipGetLastError();
 }
 
+namespace {
+constexpr int kLeafThreads = 256;
+// rows per thread: fewest workgroups (cheapest exchange) that keep the block
+// in registers
+int leaf_rpt(int64_t r) {
+  constexpr int NT = kLeafThreads;
+  if (r <= NT * 4) return (r <= NT) ? 1 : (r <= 2 * NT ? 2 : 4);
+  return (r <= (int64_t)16 * NT * 2) ? 2 : 4;
+}
+}  // namespace
+
+int panel_groups(int64_t r) {
+  const int rpt = leaf_rpt(r);
+  return (int)((r + (int64_t)kLeafThreads * rpt - 1) / ((int64_t)kLeafThreads * rpt));
+}
+
 template <typename T>
 hipError_t panel_leaf(hipStream_t s, int64_t r, int w, T* P, int64_t ld, int32_t* ipiv, int64_t k, int32_t* info,
-                      LeafSlots* ws, uint32_t epoch) {
+                      LeafSlots* ws, uint32_t epoch, int64_t oc_lo, int64_t oc_hi) {
   if (w <= 0 || r <= 0) return hipSuccess;
-  if (w > kLeafMaxWidth) return hipErrorInvalidValue;
-  // rows per thread: fewest workgroups (cheapest exchange) that keep the
-  // block in registers
-  int rpt;
-  if (r <= NT * 4) rpt = (r <= NT) ? 1 : (r <= 2 * NT ? 2 : 4);
-  else rpt = (r <= (int64_t)16 * NT * 2) ? 2 : 4;
+  if (w > kLeafMaxWidth || oc_lo > 0 || oc_hi < w) return hipErrorInvalidValue;
+  constexpr int NT = kLeafThreads;
+  const int rpt = leaf_rpt(r);
   const int64_t G64 = (r + (int64_t)NT * rpt - 1) / ((int64_t)NT * rpt);
   if (G64 > kLeafMaxGroups) return hipErrorInvalidValue;
   const int G = (int)G64;
+  const int64_t n_other = -oc_lo + (oc_hi - w);
+  if (n_other > (int64_t)kMaxOther * G * NT) return hipErrorInvalidValue;
   if (w <= 16) {
-    if (rpt == 1) return launch_leaf<T, 16, 1>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch);
-    if (rpt == 2) return launch_leaf<T, 16, 2>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch);
-    return launch_leaf<T, 16, 4>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch);
+    if (rpt == 1) return launch_leaf<T, 16, 1, NT>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch, oc_lo, oc_hi);
+    if (rpt == 2) return launch_leaf<T, 16, 2, NT>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch, oc_lo, oc_hi);
+    return launch_leaf<T, 16, 4, NT>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch, oc_lo, oc_hi);
   }
-  if (rpt == 1) return launch_leaf<T, 32, 1>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch);
-  if (rpt == 2) return launch_leaf<T, 32, 2>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch);
-  return launch_leaf<T, 32, 4>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch);
+  if (rpt == 1) return launch_leaf<T, 32, 1, NT>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch, oc_lo, oc_hi);
+  if (rpt == 2) return launch_leaf<T, 32, 2, NT>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch, oc_lo, oc_hi);
+  return launch_leaf<T, 32, 4, NT>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch, oc_lo, oc_hi);
 }
 
 template hipError_t panel_leaf<double>(hipStream_t, int64_t, int, double*, int64_t, int32_t*, int64_t, int32_t*,
-                                       LeafSlots*, uint32_t);
+                                       LeafSlots*, uint32_t, int64_t, int64_t);
 template hipError_t panel_leaf<float>(hipStream_t, int64_t, int, float*, int64_t, int32_t*, int64_t, int32_t*,
-                                      LeafSlots*, uint32_t);
+                                      LeafSlots*, uint32_t, int64_t, int64_t);
 
 }  // namespace lupp
