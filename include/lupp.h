@@ -55,8 +55,24 @@ enum {
   LUPP_OPT_NB = 1,         /* outer block size b of the right-looking loop (default 256)  */
   LUPP_OPT_PANEL_LEAF = 2, /* column width at which the recursive panel stops (8/16/32)    */
   LUPP_OPT_TIMING = 3,     /* 1: record HIP events around every phase of xGETRF (below)    */
-  LUPP_OPT_LOOKAHEAD = 4   /* 1 (default): factor the next column block on a second stream
+  LUPP_OPT_LOOKAHEAD = 4,  /* 1 (default): factor the next column block on a second stream
                               while the trailing update runs; 0: one stream, in order      */
+  LUPP_OPT_UPDATE_PREC = 5 /* lupp_sgetrf only: format of the operands of the trailing
+                              update A22 -= A21*U12, one of LUPP_PREC_* (default FP32).  The
+                              column-block factorization and U12 stay FP32; the products are
+                              accumulated in FP32 and A22 is stored in FP32.               */
+};
+
+/* Operand formats of the trailing update (LUPP_OPT_UPDATE_PREC) and of the
+ * factorization inside lupp_dgesv_mixed.  FP16 and FP8 multiply every 128-row
+ * block of A21 and every 128-column block of U12 by a power of two so that its
+ * largest magnitude lands just under the format's largest finite value (65504,
+ * 448) before rounding; the scales are exact and are undone in FP32. */
+enum {
+  LUPP_PREC_FP32 = 0,
+  LUPP_PREC_BF16 = 1,  /* bfloat16, round to nearest even, unscaled             */
+  LUPP_PREC_FP16 = 2,  /* IEEE binary16, round to nearest even, block-scaled     */
+  LUPP_PREC_FP8_E4M3 = 3 /* OCP FP8 e4m3, round to nearest even with saturation, block-scaled */
 };
 
 /* Phases reported by lupp_timing_summary. */
@@ -135,6 +151,86 @@ int lupp_dgetrs(lupp_handle_t h, char trans, int64_t n, int64_t nrhs, const doub
                 int64_t lda, const int32_t* dipiv, double* dB, int64_t ldb);
 int lupp_sgetrs(lupp_handle_t h, char trans, int64_t n, int64_t nrhs, const float* dLU,
                 int64_t lda, const int32_t* dipiv, float* dB, int64_t ldb);
+
+/*
+ * Mixed-precision solve with FP64 iterative refinement.
+ *
+ * The paper factors in FP64 only; this entry point extends the same blocked
+ * factorization (the column-block step and the dominant matrix-matrix update
+ * of Sections 4.1 and 5.4) with cheaper update formats, and recovers FP64
+ * accuracy with iterative refinement in the textbook form (Higham, Accuracy
+ * and Stability of Numerical Algorithms, 2nd ed., Ch. 12) and its
+ * GMRES-preconditioned variant (Carson and Higham, SIAM J. Sci. Comput. 40,
+ * 2018).
+ *
+ * The FP64 matrix A (n x n, not modified) is rounded to FP32 and factored with
+ * lupp_sgetrf, the trailing updates taking their operands in opts->factor_prec
+ * (FP32 accumulation and storage).  Each right-hand side is then refined in
+ * FP64 against the original A:
+ *   r = b - A x (FP64), eta = ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf),
+ * stopping when eta <= opts->tol.  The correction d solves A d = r:
+ *   LUPP_IR_CLASSICAL: d = inv(U) inv(L) P r with the FP32 factors;
+ *   LUPP_IR_GMRES: d from restarted GMRES in FP64 on the left-preconditioned
+ *     system inv(U) inv(L) P A d = inv(U) inv(L) P r (one cycle of at most
+ *     gmres_restart Arnoldi steps per outer iteration, classical Gram-Schmidt
+ *     applied twice, stopped at relative preconditioned residual inner_tol).
+ * x starts at 0, so the first correction is the plain low-precision solve.
+ * Stopping: CONVERGED when eta <= tol; DIVERGED when eta is NaN or grows above
+ * 10x the best value so far; STAGNATED when eta fails to halve over two
+ * iterations; MAXITER after max_iter outer iterations.  On any stop other than
+ * CONVERGED, dX holds the iterate with the smallest eta.  With fallback_fp64
+ * set, a non-converged system is solved again with lupp_dgetrf/lupp_dgetrs on
+ * an FP64 copy and the report says so.
+ *
+ *   dA  device FP64 n x n, lda >= max(1,n), read only
+ *   dB  device FP64 n x nrhs, ldb >= max(1,n), read only
+ *   dX  device FP64 n x nrhs, ldx >= max(1,n), written
+ *   opts  host, NULL = defaults (lupp_ir_opts_default); rep host, may be NULL
+ * The call allocates its workspace (FP32 copy of A and O(n * gmres_restart)
+ * vectors) in the handle, keeps it for later calls, and returns after the
+ * work is done (it synchronizes the handle's stream).  The report aggregates
+ * over the right-hand sides: the worst status, the largest eta, the largest
+ * outer and the summed inner iteration counts.
+ * Errors: -2 n, -3 nrhs, -4 dA, -5 lda, -6 dB, -7 ldb, -8 dX, -9 ldx,
+ * -10 opts out of range.
+ */
+enum { LUPP_IR_CLASSICAL = 0, LUPP_IR_GMRES = 1 };
+enum {
+  LUPP_IR_CONVERGED = 0,
+  LUPP_IR_STAGNATED = 1,
+  LUPP_IR_DIVERGED = 2,
+  LUPP_IR_SINGULAR = 3, /* the FP32 factorization met an exactly zero pivot */
+  LUPP_IR_MAXITER = 4
+};
+
+typedef struct lupp_ir_opts {
+  int32_t factor_prec;        /* LUPP_PREC_*                              (FP16)  */
+  int32_t solver;             /* LUPP_IR_CLASSICAL or LUPP_IR_GMRES   (GMRES)     */
+  double tol;                 /* target backward error                  (1e-14)  */
+  int32_t max_iter;           /* outer iterations, 1..1000 (50 classical, 10 GMRES) */
+  int32_t gmres_restart;      /* Arnoldi steps per GMRES cycle, 1..60      (30)   */
+  double inner_tol;           /* GMRES relative residual target          (1e-6)  */
+  int64_t nb;                 /* block size of the factorization, 0 = handle's   */
+  int32_t fallback_fp64;      /* 1: re-solve non-converged systems in FP64  (0)  */
+} lupp_ir_opts;
+
+typedef struct lupp_ir_report {
+  int32_t status;             /* LUPP_IR_*                                        */
+  int32_t iters;              /* outer iterations (largest over the RHS)          */
+  int32_t inner_iters;        /* GMRES steps (sum over the RHS)                   */
+  int32_t info;               /* info of the FP32 factorization                    */
+  int32_t fallback_used;      /* number of RHS solved again in FP64               */
+  double backward_error;      /* final eta (largest over the RHS)                 */
+  double factor_ms;           /* FP64->FP32 rounding and factorization             */
+  double refine_ms;           /* refinement of all right-hand sides                */
+} lupp_ir_report;
+
+/* Fill *opts with the defaults above for the given solver. */
+void lupp_ir_opts_default(lupp_ir_opts* opts, int32_t solver);
+
+int lupp_dgesv_mixed(lupp_handle_t h, int64_t n, int64_t nrhs, const double* dA, int64_t lda,
+                     const double* dB, int64_t ldb, double* dX, int64_t ldx,
+                     const lupp_ir_opts* opts, lupp_ir_report* rep);
 
 #ifdef __cplusplus
 }

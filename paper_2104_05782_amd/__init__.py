@@ -10,6 +10,10 @@ with ``A.stride(0) == 1`` (e.g. ``torch.empty(n, m).t()``).
 """
 from ._binding import (  # noqa: F401
     LIB_PATH,
+    IR_STATUS,
+    PREC,
+    IrOpts,
+    IrReport,
     LuppError,
     Handle,
     colmajor,
@@ -20,5 +24,8 @@ from ._binding import (  # noqa: F401
     lupp_sgetrs,
     getrf,
     getrs,
+    gesv_mixed,
+    ir_opts,
+    lupp_dgesv_mixed,
     status_string,
 )

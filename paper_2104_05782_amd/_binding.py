@@ -30,6 +30,31 @@ for _name in ("lupp_dgetrs", "lupp_sgetrs"):
 OPT_NB = 1
 OPT_PANEL_LEAF = 2
 OPT_TIMING = 3
+OPT_LOOKAHEAD = 4
+OPT_UPDATE_PREC = 5
+PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "fp8": 3}
+IR_SOLVER = {"classical": 0, "gmres": 1}
+IR_STATUS = {0: "converged", 1: "stagnated", 2: "diverged", 3: "singular", 4: "maxiter"}
+
+
+class IrOpts(ctypes.Structure):
+    """lupp_ir_opts (field order and types as in include/lupp.h)."""
+    _fields_ = [("factor_prec", ctypes.c_int32), ("solver", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("gmres_restart", ctypes.c_int32), ("inner_tol", ctypes.c_double),
+                ("nb", ctypes.c_int64), ("fallback_fp64", ctypes.c_int32)]
+
+
+class IrReport(ctypes.Structure):
+    """lupp_ir_report."""
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("inner_iters", ctypes.c_int32),
+                ("info", ctypes.c_int32), ("fallback_used", ctypes.c_int32), ("backward_error", ctypes.c_double),
+                ("factor_ms", ctypes.c_double), ("refine_ms", ctypes.c_double)]
+
+
+_lib.lupp_ir_opts_default.argtypes = [ctypes.POINTER(IrOpts), ctypes.c_int32]
+_lib.lupp_ir_opts_default.restype = None
+_lib.lupp_dgesv_mixed.argtypes = [_vp, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(IrOpts),
+                                  ctypes.POINTER(IrReport)]
 PHASES = {"panel": 0, "laswp": 1, "trsm": 2, "update": 3, "update_big": 4, "panel_leaf": 5, "panel_swap": 6,
           "panel_trsm": 7, "panel_gemm": 8}
 
@@ -172,6 +197,48 @@ def lupp_dgetrs(LU, ipiv, B, handle: Handle | None = None):
 def lupp_sgetrs(LU, ipiv, B, handle: Handle | None = None):
     """B := inv(A) * B from the float32 factors (B column-major, in place)."""
     _getrs(_lib.lupp_sgetrs, torch.float32, LU, ipiv, B, handle)
+
+
+def ir_opts(solver: str = "gmres", **kw) -> IrOpts:
+    """lupp_ir_opts with the library defaults for `solver`, then the keyword overrides
+    (factor_prec accepts a name of PREC)."""
+    o = IrOpts()
+    _lib.lupp_ir_opts_default(ctypes.byref(o), IR_SOLVER[solver])
+    for k, v in kw.items():
+        if k == "factor_prec" and isinstance(v, str):
+            v = PREC[v]
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def lupp_dgesv_mixed(A, B, X, opts: IrOpts | None = None, handle: Handle | None = None) -> dict:
+    """X := solution of A X = B by the mixed-precision factorization and FP64
+    refinement (A, B, X float64 column-major device matrices; A and B are not
+    modified).  Returns the report as a dict."""
+    _dev(A, torch.float64, "A")
+    _dev(B, torch.float64, "B")
+    _dev(X, torch.float64, "X")
+    n = A.shape[0]
+    if A.shape[1] != n or B.shape[0] != n or tuple(X.shape) != tuple(B.shape):
+        raise ValueError("A must be n x n, B and X n x nrhs")
+    h = _prep(handle)
+    rep = IrReport()
+    o = opts if opts is not None else ir_opts()
+    _check(_lib.lupp_dgesv_mixed(h.ptr, n, B.shape[1], A.data_ptr(), _lead(A), B.data_ptr(), _lead(B), X.data_ptr(),
+                                 _lead(X), ctypes.byref(o), ctypes.byref(rep)), "lupp_dgesv_mixed")
+    out = {f: getattr(rep, f) for f, _ in IrReport._fields_}
+    out["status_name"] = IR_STATUS.get(rep.status, "unknown")
+    return out
+
+
+def gesv_mixed(A: torch.Tensor, B: torch.Tensor, handle: Handle | None = None, solver: str = "gmres", **kw):
+    """Solve A X = B (B a matrix or a vector) with lupp_dgesv_mixed; returns (X, report)."""
+    B2 = B if B.dim() == 2 else B.view(-1, 1)
+    X = torch.empty(B2.shape[1], B2.shape[0], dtype=torch.float64, device=B.device).t()
+    rep = lupp_dgesv_mixed(A, colmajor(B2), X, ir_opts(solver, **kw), handle)
+    return (X if B.dim() == 2 else X[:, 0]), rep
 
 
 def getrf(A: torch.Tensor, handle: Handle | None = None):

@@ -115,6 +115,65 @@ template <typename T>
 hipError_t trsm_leaf(hipStream_t s, bool lower, int64_t w, int64_t ncols, const T* L, int64_t ldl, T* B,
                      int64_t ldb);
 
+// ---------------------------------------------------------------- mixed precision
+// Number of int slots gemm_lp_sub needs as scale workspace for an M x N update.
+int64_t gemm_lp_scale_slots(int64_t M, int64_t N);
+
+// C (FP32) -= A * B with A and B rounded to a low format while staged:
+// mode 1 = BF16, 2 = FP16, 3 = FP8 e4m3 (2 and 3 scale each 128-row block of A
+// and 128-column block of B by a power of two first, using scale_ws).
+hipError_t gemm_lp_sub(hipStream_t s, int mode, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+                       const float* B, int64_t ldb, float* C, int64_t ldc, int* scale_ws);
+
+// State of the one-launch triangular solve: per-block flags tagged with a
+// call epoch and a ticket counter that hands out blocks in dispatch order.
+struct TrsvState {
+  uint32_t* flags;     // device, max_blocks entries
+  uint64_t* ticket;    // device counter, only ever incremented
+  int32_t* err;        // device, set when a bounded wait expires
+  int64_t max_blocks;  // capacity of flags (rows / 64)
+  uint32_t epoch;      // host copy of the last epoch used
+  uint64_t tickets;    // host copy of the tickets handed out so far
+};
+
+// x := L^{-1} x (unit lower, lower = true) or U^{-1} x (non-unit upper) for
+// one right-hand side, with L/U in the n x n matrix A.
+template <typename T>
+hipError_t trsv_wave(hipStream_t s, bool lower, int64_t n, const T* A, int64_t lda, T* x, TrsvState* st);
+
+// r = b - A x in FP64 (deterministic: nchunk column chunks, part holds nchunk*n)
+hipError_t residual(hipStream_t s, int64_t n, const double* A, int64_t lda, const double* x, const double* b,
+                    double* r, double* part, int64_t nchunk);
+// *out = max(*out, max_i |v_i|) as the bit pattern of a double (*out starts at 0)
+hipError_t absmax(hipStream_t s, int64_t n, const double* v, unsigned long long* out);
+// *out = max(*out, ||A||_inf) (part holds nchunk*n)
+hipError_t norm_inf_mat(hipStream_t s, int64_t n, const double* A, int64_t lda, double* part, int64_t nchunk,
+                        unsigned long long* out);
+hipError_t d2s_mat(hipStream_t s, int64_t rows, int64_t cols, const double* src, int64_t lds, float* dst,
+                   int64_t ldd);
+hipError_t d2s_vec(hipStream_t s, int64_t n, const double* src, float* dst);
+// y = x + alpha * z
+hipError_t axpy_s2d(hipStream_t s, int64_t n, double alpha, const float* z, const double* x, double* y);
+// y = alpha * z
+hipError_t s2d_scaled(hipStream_t s, int64_t n, double alpha, const float* z, double* y);
+// out[c] = V(:, c) . w for c < k (k <= 64); part holds ceil(n/256)*k
+hipError_t mdot(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* w, double* part,
+                double* out);
+// w -= V(:, 0:k) h
+hipError_t mgemv_sub(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h, double* w);
+// y += V(:, 0:k) c
+hipError_t mgemv_add(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* c, double* y);
+// dst = alpha * src
+hipError_t scale_copy(hipStream_t s, int64_t n, double alpha, const double* src, double* dst);
+// x += d
+hipError_t vec_add(hipStream_t s, int64_t n, const double* d, double* x);
+// dst[i] = (float)(src[perm[i]] / *smax)   (*smax: bit pattern of a double >= 0)
+hipError_t gather_scale(hipStream_t s, int64_t n, const int32_t* perm, const double* src,
+                        const unsigned long long* smax, float* dst);
+// y = x + sign * (*smax) * z   (x may be NULL for zero, or equal to y)
+hipError_t axpy_dev(hipStream_t s, int64_t n, double sign, const unsigned long long* smax, const float* z,
+                    const double* x, double* y);
+
 hipError_t set_int(hipStream_t s, int32_t* p, int32_t v);
 hipError_t reset_flags(hipStream_t s, LeafSlots* ws);
 

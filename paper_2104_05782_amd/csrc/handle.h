@@ -1,0 +1,67 @@
+// The handle and the host-side helpers shared by the driver sources.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace lupp {
+struct TimingRecord {
+  hipEvent_t start = nullptr, stop = nullptr;
+  int phase = 0;
+  bool big = false;
+  double flops = 0.0;
+};
+struct MixedWs;
+}  // namespace lupp
+
+struct lupp_handle_st {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t nb = 256;
+  int leaf = 32;
+  lupp::LeafSlots* slots = nullptr;
+  lupp::SwapPairs* pairs = nullptr;
+  uint32_t epoch = 0;
+  bool timing = false;
+  std::vector<lupp::TimingRecord> records;  // events are created once and reused
+  size_t nrecords = 0;
+  int lookahead = 1;                // factor the next column block on a side stream
+  hipStream_t side = nullptr;       // panel stream, restricted to panel_cus CUs
+  hipStream_t bulk = nullptr;       // trailing-update stream, restricted to the other CUs
+  int panel_cus = 0;                // CUs reserved for the panel while they overlap
+  hipEvent_t ev_cols = nullptr;     // next block's columns updated (main -> side, bulk)
+  hipEvent_t ev_panel = nullptr;    // next block factored (side -> main)
+  hipEvent_t ev_bulk = nullptr;     // bulk update done (bulk -> main)
+  int update_prec = 0;              // LUPP_PREC_* of sgetrf's trailing update
+  int* lp_scale[2] = {nullptr, nullptr};  // block exponents: next-block and bulk updates
+  int64_t lp_scale_cap = 0;         // ints in each of lp_scale[0], lp_scale[1]
+  lupp::TrsvState trsv{};           // one-launch triangular solve state (flags on demand)
+  lupp::MixedWs* mixed = nullptr;   // workspace of lupp_dgesv_mixed
+};
+
+namespace lupp {
+
+inline int hip_status(hipError_t e) { return e == hipSuccess ? LUPP_OK : LUPP_ERR_HIP + (int)e; }
+
+#define LUPP_TRY(expr)               \
+  do {                               \
+    hipError_t e_ = (expr);          \
+    if (e_ != hipSuccess) return e_; \
+  } while (0)
+
+// Handle workspace of the factorization (slots, swap pairs, lookahead streams).
+hipError_t ensure_workspace(lupp_handle_t h);
+// Scale workspace of the low-precision update for an m x n factorization.
+hipError_t ensure_lp_scale(lupp_handle_t h, int64_t m, int64_t n);
+// Flags of the one-launch triangular solve for n rows.
+hipError_t ensure_trsv(lupp_handle_t h, int64_t n);
+// The factorization and the solve on the handle's stream (arguments checked).
+template <typename T>
+hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32_t* ipiv, int32_t* info);
+template <typename T>
+hipError_t getrs(lupp_handle_t h, int64_t n, int64_t nrhs, const T* LU, int64_t lda, const int32_t* ipiv, T* B,
+                 int64_t ldb);
+void free_mixed(lupp_handle_t h);
+
+}  // namespace lupp

@@ -16,51 +16,15 @@
 #include <stdlib.h>
 
 #include <new>
+#include <type_traits>
 #include <vector>
 
-#include "common.h"
-
-namespace lupp {
-struct TimingRecord {
-  hipEvent_t start = nullptr, stop = nullptr;
-  int phase = 0;
-  bool big = false;
-  double flops = 0.0;
-};
-}  // namespace lupp
-
-struct lupp_handle_st {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  int64_t nb = 256;
-  int leaf = 32;
-  lupp::LeafSlots* slots = nullptr;
-  lupp::SwapPairs* pairs = nullptr;
-  uint32_t epoch = 0;
-  bool timing = false;
-  std::vector<lupp::TimingRecord> records;  // events are created once and reused
-  size_t nrecords = 0;
-  int lookahead = 1;                // factor the next column block on a side stream
-  hipStream_t side = nullptr;       // panel stream, restricted to panel_cus CUs
-  hipStream_t bulk = nullptr;       // trailing-update stream, restricted to the other CUs
-  int panel_cus = 0;                // CUs reserved for the panel while they overlap
-  hipEvent_t ev_cols = nullptr;     // next block's columns updated (main -> side, bulk)
-  hipEvent_t ev_panel = nullptr;    // next block factored (side -> main)
-  hipEvent_t ev_bulk = nullptr;     // bulk update done (bulk -> main)
-};
+#include "handle.h"
 
 namespace lupp {
 namespace {
 
 constexpr int kLookaheadPanelCUs = 32;
-
-inline int hip_status(hipError_t e) { return e == hipSuccess ? LUPP_OK : LUPP_ERR_HIP + (int)e; }
-
-#define LUPP_TRY(expr)                       \
-  do {                                       \
-    hipError_t e_ = (expr);                  \
-    if (e_ != hipSuccess) return e_;         \
-  } while (0)
 
 // Epoch of the panel kernel's progress flags: every launch uses flag values
 // above all values written before; the flags are cleared before wrap-around.
@@ -155,6 +119,22 @@ hipError_t panel(lupp_handle_t h, hipStream_t s, int64_t m, int64_t k, int64_t w
   return panel<T>(h, s, m, k + w1, w2, p0, p1, A, lda, ipiv, info);
 }
 
+// Trailing update C -= A * B of the outer loop: FP64 and FP32 on the MFMA GEMM
+// of the working precision, or (FP32 factorization with a low-precision update
+// format) on the low-precision GEMM; `which` selects the scale workspace of
+// the two updates that may run concurrently (next block, bulk).
+template <typename T>
+hipError_t update(lupp_handle_t h, hipStream_t s, int which, int64_t M, int64_t N, int64_t K, const T* A,
+                  int64_t lda, const T* B, int64_t ldb, T* C, int64_t ldc, int* tile = nullptr) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (h->update_prec != LUPP_PREC_FP32) {
+      if (tile) *tile = 1;
+      return gemm_lp_sub(s, h->update_prec, M, N, K, A, lda, B, ldb, C, ldc, h->lp_scale[which]);
+    }
+  }
+  return gemm_sub<T>(s, M, N, K, A, lda, B, ldb, C, ldc, tile);
+}
+
 // Column block [k, k+b): factor it on stream st, with its phase timing.
 template <typename T>
 hipError_t factor_block(lupp_handle_t h, hipStream_t st, int64_t m, int64_t k, int64_t b, T* A, int64_t lda,
@@ -164,6 +144,8 @@ hipError_t factor_block(lupp_handle_t h, hipStream_t st, int64_t m, int64_t k, i
   timer_end(h, t, st, 0.0);
   return hipSuccess;
 }
+
+}  // namespace
 
 // Blocked right-looking factorization with depth-1 lookahead: while the bulk
 // of step k's trailing update runs on the main stream, the next column block
@@ -198,7 +180,7 @@ hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32
       const int64_t n1 = (mr > 0) ? bn : 0;
       if (n1 > 0) {
         t = timer_begin(h, LUPP_PHASE_UPDATE, s);
-        LUPP_TRY(gemm_sub<T>(s, mr, n1, b, A + kn + k * lda, lda, A + k + kn * lda, lda, A + kn + kn * lda, lda));
+        LUPP_TRY(update<T>(h, s, 0, mr, n1, b, A + kn + k * lda, lda, A + k + kn * lda, lda, A + kn + kn * lda, lda));
         timer_end(h, t, s, 2.0 * (double)mr * (double)n1 * (double)b);
       }
       // overlap only when the next block's cooperative factorization fits in
@@ -216,8 +198,8 @@ hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32
       if (mr > 0 && nr > n1) {
         int tile = -1;
         t = timer_begin(h, LUPP_PHASE_UPDATE, su);
-        LUPP_TRY(gemm_sub<T>(su, mr, nr - n1, b, A + kn + k * lda, lda, A + k + (kn + n1) * lda, lda,
-                             A + kn + (kn + n1) * lda, lda, &tile));
+        LUPP_TRY(update<T>(h, su, 1, mr, nr - n1, b, A + kn + k * lda, lda, A + k + (kn + n1) * lda, lda,
+                           A + kn + (kn + n1) * lda, lda, &tile));
         timer_end(h, t, su, 2.0 * (double)mr * (double)(nr - n1) * (double)b, tile == 1);
       }
       if (overlap) {
@@ -232,13 +214,76 @@ hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32
   return hipSuccess;
 }
 
+// Solve with the factors: the interchanges in runs of at most kMaxSwaps
+// (composed per run, applied to all right-hand sides at once), then the two
+// triangular solves -- for one or two right-hand sides the one-launch
+// wavefront solve (reads each factor once), otherwise the recursive trsm.
 template <typename T>
 hipError_t getrs(lupp_handle_t h, int64_t n, int64_t nrhs, const T* LU, int64_t lda, const int32_t* ipiv, T* B,
                  int64_t ldb) {
   hipStream_t s = h->stream;
-  LUPP_TRY(laswp<T>(s, B, ldb, n, 0, nrhs, 0, 0, ipiv, 0, n, nullptr));
+  for (int64_t k1 = 0; k1 < n; k1 += kMaxSwaps) {
+    const int64_t k2 = (n - k1 < kMaxSwaps) ? n : k1 + kMaxSwaps;
+    LUPP_TRY(laswp<T>(s, B, ldb, n, 0, nrhs, 0, 0, ipiv, k1, k2, h->pairs));
+  }
+  if (nrhs <= 2) {
+    for (int64_t j = 0; j < nrhs; ++j) {
+      LUPP_TRY(trsv_wave<T>(s, true, n, LU, lda, B + j * ldb, &h->trsv));
+      LUPP_TRY(trsv_wave<T>(s, false, n, LU, lda, B + j * ldb, &h->trsv));
+    }
+    return hipSuccess;
+  }
   LUPP_TRY(trsm_lower_unit<T>(s, n, nrhs, LU, lda, B, ldb));
   return trsm_upper<T>(s, n, nrhs, LU, lda, B, ldb);
+}
+
+template hipError_t getrf<double>(lupp_handle_t, int64_t, int64_t, double*, int64_t, int32_t*, int32_t*);
+template hipError_t getrf<float>(lupp_handle_t, int64_t, int64_t, float*, int64_t, int32_t*, int32_t*);
+template hipError_t getrs<double>(lupp_handle_t, int64_t, int64_t, const double*, int64_t, const int32_t*, double*,
+                                  int64_t);
+template hipError_t getrs<float>(lupp_handle_t, int64_t, int64_t, const float*, int64_t, const int32_t*, float*,
+                                 int64_t);
+
+hipError_t ensure_lp_scale(lupp_handle_t h, int64_t m, int64_t n) {
+  const int64_t need = gemm_lp_scale_slots(m, n);
+  if (need <= h->lp_scale_cap) return hipSuccess;
+  LUPP_TRY(hipStreamSynchronize(h->stream));
+  if (h->bulk) LUPP_TRY(hipStreamSynchronize(h->bulk));
+  if (h->lp_scale[0]) (void)hipFree(h->lp_scale[0]);
+  h->lp_scale[0] = h->lp_scale[1] = nullptr;
+  h->lp_scale_cap = 0;
+  void* p = nullptr;
+  LUPP_TRY(hipMalloc(&p, (size_t)need * 2 * sizeof(int)));
+  h->lp_scale[0] = (int*)p;
+  h->lp_scale[1] = (int*)p + need;
+  h->lp_scale_cap = need;
+  return hipSuccess;
+}
+
+hipError_t ensure_trsv(lupp_handle_t h, int64_t n) {
+  const int64_t need = (n + 63) / 64;
+  TrsvState& t = h->trsv;
+  if (need <= t.max_blocks && t.epoch < 0xF0000000u) return hipSuccess;
+  LUPP_TRY(hipStreamSynchronize(h->stream));
+  if (need > t.max_blocks) {
+    if (t.flags) (void)hipFree(t.flags);
+    t.flags = nullptr;
+    t.max_blocks = 0;
+    const int64_t cap = need < 1024 ? 1024 : need;
+    void* p = nullptr;
+    // flags, then the ticket counter and the error flag
+    LUPP_TRY(hipMalloc(&p, (size_t)cap * sizeof(uint32_t) + 64));
+    t.flags = (uint32_t*)p;
+    t.ticket = (uint64_t*)((char*)p + ((size_t)cap * sizeof(uint32_t) + 7) / 8 * 8);
+    t.err = (int32_t*)(t.ticket + 1);
+    t.max_blocks = cap;
+    LUPP_TRY(hipMemsetAsync(p, 0, (size_t)cap * sizeof(uint32_t) + 64, h->stream));
+    t.tickets = 0;
+  } else {
+    LUPP_TRY(hipMemsetAsync(t.flags, 0, (size_t)t.max_blocks * sizeof(uint32_t), h->stream));
+  }
+  t.epoch = 0;
+  return hipSuccess;
 }
 
 hipError_t ensure_workspace(lupp_handle_t h) {
@@ -277,6 +322,8 @@ hipError_t ensure_workspace(lupp_handle_t h) {
   return hipSuccess;
 }
 
+namespace {
+
 template <typename T>
 int getrf_entry(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32_t* ipiv, int32_t* info) {
   if (!h) return -1;
@@ -289,6 +336,10 @@ int getrf_entry(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32_
   if (m - 0 > (int64_t)kLeafMaxGroups * 256 * 4) return LUPP_ERR_UNSUPPORTED;
   hipError_t e = ensure_workspace(h);
   if (e != hipSuccess) return LUPP_ERR_ALLOC;
+  if (std::is_same<T, float>::value && h->update_prec != LUPP_PREC_FP32) {
+    e = ensure_lp_scale(h, m, n);
+    if (e != hipSuccess) return LUPP_ERR_ALLOC;
+  }
   return hip_status(getrf<T>(h, m, n, A, lda, ipiv, info));
 }
 
@@ -305,6 +356,9 @@ int getrs_entry(lupp_handle_t h, char trans, int64_t n, int64_t nrhs, const T* L
   if (!B && n > 0 && nrhs > 0) return -8;
   if (ldb < (n > 1 ? n : 1)) return -9;
   if (n == 0 || nrhs == 0) return LUPP_OK;
+  hipError_t e = ensure_workspace(h);
+  if (e == hipSuccess && nrhs <= 2) e = ensure_trsv(h, n);
+  if (e != hipSuccess) return LUPP_ERR_ALLOC;
   return hip_status(getrs<T>(h, n, nrhs, LU, lda, ipiv, B, ldb));
 }
 
@@ -343,6 +397,9 @@ int lupp_destroy(lupp_handle_t h) {
   if (h->side) (void)hipStreamDestroy(h->side);
   if (h->bulk) (void)hipStreamDestroy(h->bulk);
   if (h->slots) (void)hipFree(h->slots);
+  if (h->lp_scale[0]) (void)hipFree(h->lp_scale[0]);
+  if (h->trsv.flags) (void)hipFree(h->trsv.flags);
+  lupp::free_mixed(h);
   delete h;
   return rc;
 }
@@ -371,6 +428,10 @@ int lupp_set_option(lupp_handle_t h, int option, int64_t value) {
     case LUPP_OPT_LOOKAHEAD:
       if (value != 0 && value != 1) return -3;
       h->lookahead = (int)value;
+      return LUPP_OK;
+    case LUPP_OPT_UPDATE_PREC:
+      if (value < LUPP_PREC_FP32 || value > LUPP_PREC_FP8_E4M3) return -3;
+      h->update_prec = (int)value;
       return LUPP_OK;
     default:
       return -2;

@@ -1,0 +1,431 @@
+// Kernels of the solve and of the FP64 iterative refinement.
+//
+// * k_trsv: one-launch triangular solve for one right-hand side.  The n rows
+//   are cut into 64-row blocks; each workgroup takes the next block in
+//   dispatch order (a ticket from an atomic counter, so every block it waits
+//   for was dispatched before it), subtracts the contributions of the finished
+//   blocks as their flags appear (it polls 64 flags per load), solves its
+//   diagonal block inside one wavefront (lane i holds row i of the block in
+//   registers; x_k is read with readlane), and publishes its x with
+//   device-coherent stores before raising its flag.  The matrix is read once.
+// * k_gemv_part / k_gemv_fin: r = b - A x in FP64, two passes over column
+//   chunks, deterministic (no floating-point atomics).
+// * norms, dot products, axpy and format conversions for the refinement.
+#include "common.h"
+
+namespace lupp {
+namespace {
+
+constexpr int TB = 64;  // rows per triangular-solve block
+
+__device__ __forceinline__ double readlane_t(double v, int k) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, k);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), k);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ float readlane_t(float v, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+
+template <typename T>
+__device__ __forceinline__ void st_coh(T* p, T v);
+template <>
+__device__ __forceinline__ void st_coh<double>(double* p, double v) {
+  __hip_atomic_store((uint64_t*)p, (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <>
+__device__ __forceinline__ void st_coh<float>(float* p, float v) {
+  __hip_atomic_store((uint32_t*)p, __float_as_uint(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T ld_coh(const T* p);
+template <>
+__device__ __forceinline__ double ld_coh<double>(const double* p) {
+  return __longlong_as_double(
+      (long long)__hip_atomic_load((const uint64_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+template <>
+__device__ __forceinline__ float ld_coh<float>(const float* p) {
+  return __uint_as_float(__hip_atomic_load((const uint32_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+template <typename T, bool LOWER>
+__global__ __launch_bounds__(256) void k_trsv(int64_t n, const T* __restrict__ A, int64_t lda, T* __restrict__ x,
+                                              uint32_t* __restrict__ flags, uint64_t* __restrict__ ticket,
+                                              uint64_t tbase, uint32_t epoch, int32_t* __restrict__ err) {
+  __shared__ T s_part[4][TB];
+  __shared__ int64_t s_blk;
+  __shared__ int s_ready;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t nblk = (n + TB - 1) / TB;
+  if (tid == 0) s_blk = (int64_t)(atomicAdd((unsigned long long*)ticket, 1ull) - tbase);
+  __syncthreads();
+  const int64_t q = s_blk;
+  if (q < 0 || q >= nblk) {  // ticket bookkeeping out of step: report, touch nothing
+    if (tid == 0) *err = 2;
+    return;
+  }
+  const int64_t b = LOWER ? q : (nblk - 1 - q);
+  const int64_t r0 = b * TB;
+  const int64_t row = r0 + lane;
+  const bool rok = row < n;
+  T acc = T(0);
+  // dependencies: blocks [0, b) (lower) or (b, nblk) (upper), in order
+  const int64_t ndep = LOWER ? b : (nblk - 1 - b);
+  int64_t done = 0;
+  long spins = 0;
+  while (done < ndep) {
+    // wave 0 finds how many further blocks are ready
+    if (wave == 0) {
+      const int64_t d0 = done + lane;
+      const int64_t blk = LOWER ? d0 : (nblk - 1 - d0);
+      bool ok = true;
+      if (d0 < ndep) ok = __hip_atomic_load(&flags[blk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+      const unsigned long long notready = __ballot(!ok);
+      const int nready = notready ? (__ffsll((long long)notready) - 1) : 64;
+      if (lane == 0) s_ready = nready;
+    }
+    __syncthreads();
+    int nready = s_ready;
+    if (nready == 0) {
+      if (++spins > (1L << 22)) {
+        if (tid == 0) *err = 1;
+        nready = (int)(ndep - done);  // give up waiting (results invalid, flagged)
+      } else {
+        __syncthreads();
+        continue;
+      }
+    }
+    for (int64_t d = done; d < done + nready && d < ndep; ++d) {
+      const int64_t blk = LOWER ? d : (nblk - 1 - d);
+      const int64_t c0 = blk * TB;
+      // this wave's 16 columns of the 64x64 tile
+#pragma unroll 4
+      for (int cc = 0; cc < 16; ++cc) {
+        const int64_t c = c0 + wave * 16 + cc;
+        if (c < n && rok) acc = acc - A[row + c * lda] * ld_coh(&x[c]);
+      }
+    }
+    done += nready;
+    __syncthreads();
+  }
+  s_part[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0) {
+    T v = rok ? x[row] : T(0);
+    v = v + s_part[0][lane] + s_part[1][lane] + s_part[2][lane] + s_part[3][lane];
+    // diagonal block: lane holds row `lane` of it
+    T dr[TB];
+#pragma unroll
+    for (int c = 0; c < TB; ++c) dr[c] = (rok && r0 + c < n) ? A[row + (r0 + c) * lda] : T(0);
+    if (LOWER) {
+#pragma unroll
+      for (int k = 0; k < TB; ++k) {
+        const T xk = readlane_t(v, k);
+        if (lane > k) v = v - dr[k] * xk;
+      }
+    } else {
+#pragma unroll
+      for (int k = TB - 1; k >= 0; --k) {
+        if (lane == k && rok) v = v / dr[k];
+        const T xk = readlane_t(v, k);
+        if (lane < k) v = v - dr[k] * xk;
+      }
+    }
+    if (rok) st_coh(&x[row], v);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    if (lane == 0) __hip_atomic_store(&flags[b], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// partial[c][i] = sum over the c-th chunk of columns of A(i, j) * x(j)
+__global__ __launch_bounds__(256) void k_gemv_part(int64_t n, const double* __restrict__ A, int64_t lda,
+                                                   const double* __restrict__ x, int64_t chunk,
+                                                   double* __restrict__ part) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  const int64_t j0 = c * chunk, j1 = (j0 + chunk < n) ? j0 + chunk : n;
+  if (i >= n) return;
+  double s0 = 0.0, s1 = 0.0;
+  int64_t j = j0;
+  for (; j + 1 < j1; j += 2) {
+    s0 = fma(A[i + j * lda], x[j], s0);
+    s1 = fma(A[i + (j + 1) * lda], x[j + 1], s1);
+  }
+  if (j < j1) s0 = fma(A[i + j * lda], x[j], s0);
+  part[c * n + i] = s0 + s1;
+}
+
+// r = b - sum_c partial[c] (fixed order)
+__global__ void k_gemv_fin(int64_t n, int64_t nchunk, const double* __restrict__ part, const double* __restrict__ b,
+                           double* __restrict__ r) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int64_t c = 0; c < nchunk; ++c) s += part[c * n + i];
+  r[i] = b[i] - s;
+}
+
+// out[0] = max |v| (bit pattern of a non-negative double orders like the value)
+__global__ void k_absmax(int64_t n, const double* __restrict__ v, unsigned long long* __restrict__ out) {
+  __shared__ double s[256];
+  double m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    m = fmax(m, fabs(v[i]));
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + k]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(s[0]));
+}
+
+// row absolute sums of A (FP64): part[c][i] over column chunks
+__global__ __launch_bounds__(256) void k_rowabs_part(int64_t n, const double* __restrict__ A, int64_t lda,
+                                                     int64_t chunk, double* __restrict__ part) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  const int64_t j0 = c * chunk, j1 = (j0 + chunk < n) ? j0 + chunk : n;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int64_t j = j0; j < j1; ++j) s += fabs(A[i + j * lda]);
+  part[c * n + i] = s;
+}
+
+__global__ void k_rowabs_fin(int64_t n, int64_t nchunk, const double* __restrict__ part,
+                             unsigned long long* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double s = 0.0;
+  if (i < n)
+    for (int64_t c = 0; c < nchunk; ++c) s += part[c * n + i];
+  __shared__ double sm[256];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + k]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(sm[0]));
+}
+
+__global__ void k_d2s_mat(int64_t rows, int64_t cols, const double* __restrict__ src, int64_t lds,
+                          float* __restrict__ dst, int64_t ldd) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  for (int64_t jj = j; jj < cols; jj += gridDim.y)
+    if (i < rows) dst[i + jj * ldd] = (float)src[i + jj * lds];
+}
+
+__global__ void k_d2s_vec(int64_t n, const double* __restrict__ s, float* __restrict__ d) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) d[i] = (float)s[i];
+}
+
+// y = x + alpha * (double)z  (alpha applied in FP64)
+__global__ void k_axpy_s2d(int64_t n, double alpha, const float* __restrict__ z, const double* __restrict__ x,
+                           double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = x[i] + alpha * (double)z[i];
+}
+
+__global__ void k_s2d_scaled(int64_t n, double alpha, const float* __restrict__ z, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = alpha * (double)z[i];
+}
+
+// partial dot products of w with the columns 0..k-1 of V: part[blk][c]
+__global__ __launch_bounds__(256) void k_mdot_part(int64_t n, int k, const double* __restrict__ V, int64_t ldv,
+                                                   const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double s[256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const double wi = i < n ? w[i] : 0.0;
+  for (int c = 0; c < k; ++c) {
+    s[threadIdx.x] = (i < n) ? V[i + c * ldv] * wi : 0.0;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * k + c] = s[0];
+    __syncthreads();
+  }
+}
+
+__global__ void k_mdot_fin(int64_t nb, int k, const double* __restrict__ part, double* __restrict__ out) {
+  const int c = threadIdx.x;
+  if (c >= k) return;
+  double s = 0.0;
+  for (int64_t b = 0; b < nb; ++b) s += part[b * k + c];
+  out[c] = s;
+}
+
+// w -= V(:, 0:k) * h   (h on the device)
+__global__ void k_mgemv_sub(int64_t n, int k, const double* __restrict__ V, int64_t ldv,
+                            const double* __restrict__ h, double* __restrict__ w) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double s = w[i];
+  for (int c = 0; c < k; ++c) s -= V[i + c * ldv] * h[c];
+  w[i] = s;
+}
+
+// y += V(:, 0:k) * c   (c on the device)
+__global__ void k_mgemv_add(int64_t n, int k, const double* __restrict__ V, int64_t ldv,
+                            const double* __restrict__ c, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double s = y[i];
+  for (int q = 0; q < k; ++q) s += V[i + q * ldv] * c[q];
+  y[i] = s;
+}
+
+__global__ void k_scale_copy(int64_t n, double alpha, const double* __restrict__ src, double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = alpha * src[i];
+}
+
+__global__ void k_add(int64_t n, const double* __restrict__ d, double* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) x[i] += d[i];
+}
+
+// dst[i] = (float)(src[perm[i]] / s) with s = *smax (a non-negative double's
+// bit pattern): the row permutation of the factorization and a scaling that
+// keeps the FP32 right-hand side away from under- and overflow.  A zero or
+// non-finite s leaves the values unscaled.
+__global__ void k_gather_scale(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ src,
+                               const unsigned long long* __restrict__ smax, float* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double sv = __longlong_as_double((long long)*smax);
+  const double inv = (sv > 0.0 && sv < 1.0e308) ? 1.0 / sv : 1.0;
+  dst[i] = (float)(src[perm[i]] * inv);
+}
+
+// y[i] = x[i] + sign * s * (double)z[i] with s = *smax as above (y may be x)
+__global__ void k_axpy_dev(int64_t n, double sign, const unsigned long long* __restrict__ smax,
+                           const float* __restrict__ z, const double* x, double* y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double sv = __longlong_as_double((long long)*smax);
+  const double sc = (sv > 0.0 && sv < 1.0e308) ? sv : 1.0;
+  const double xi = x ? x[i] : 0.0;
+  y[i] = xi + sign * sc * (double)z[i];
+}
+
+inline unsigned grid1(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+template <typename T>
+hipError_t trsv_wave(hipStream_t s, bool lower, int64_t n, const T* A, int64_t lda, T* x, TrsvState* st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nblk = (n + TB - 1) / TB;
+  if (nblk > st->max_blocks) return hipErrorInvalidValue;
+  if (st->epoch > 0xF0000000u) return hipErrorInvalidValue;  // caller resets
+  st->epoch += 1;
+  const uint64_t tbase = st->tickets;
+  st->tickets += (uint64_t)nblk;
+  if (lower)
+    hipLaunchKernelGGL((k_trsv<T, true>), dim3((unsigned)nblk), dim3(256), 0, s, n, A, lda, x, st->flags, st->ticket,
+                       tbase, st->epoch, st->err);
+  else
+    hipLaunchKernelGGL((k_trsv<T, false>), dim3((unsigned)nblk), dim3(256), 0, s, n, A, lda, x, st->flags, st->ticket,
+                       tbase, st->epoch, st->err);
+  return hipGetLastError();
+}
+template hipError_t trsv_wave<double>(hipStream_t, bool, int64_t, const double*, int64_t, double*, TrsvState*);
+template hipError_t trsv_wave<float>(hipStream_t, bool, int64_t, const float*, int64_t, float*, TrsvState*);
+
+hipError_t residual(hipStream_t s, int64_t n, const double* A, int64_t lda, const double* x, const double* b,
+                    double* r, double* part, int64_t nchunk) {
+  const int64_t chunk = (n + nchunk - 1) / nchunk;
+  hipLaunchKernelGGL(k_gemv_part, dim3(grid1(n), (unsigned)nchunk), dim3(256), 0, s, n, A, lda, x, chunk, part);
+  hipLaunchKernelGGL(k_gemv_fin, dim3(grid1(n)), dim3(256), 0, s, n, nchunk, part, b, r);
+  return hipGetLastError();
+}
+
+hipError_t absmax(hipStream_t s, int64_t n, const double* v, unsigned long long* out) {
+  unsigned g = grid1(n);
+  if (g > 1024) g = 1024;
+  hipLaunchKernelGGL(k_absmax, dim3(g), dim3(256), 0, s, n, v, out);
+  return hipGetLastError();
+}
+
+hipError_t norm_inf_mat(hipStream_t s, int64_t n, const double* A, int64_t lda, double* part, int64_t nchunk,
+                        unsigned long long* out) {
+  const int64_t chunk = (n + nchunk - 1) / nchunk;
+  hipLaunchKernelGGL(k_rowabs_part, dim3(grid1(n), (unsigned)nchunk), dim3(256), 0, s, n, A, lda, chunk, part);
+  hipLaunchKernelGGL(k_rowabs_fin, dim3(grid1(n)), dim3(256), 0, s, n, nchunk, part, out);
+  return hipGetLastError();
+}
+
+hipError_t d2s_mat(hipStream_t s, int64_t rows, int64_t cols, const double* src, int64_t lds, float* dst,
+                   int64_t ldd) {
+  const unsigned gy = (unsigned)(cols < 65535 ? cols : 65535);
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_d2s_mat, dim3(grid1(rows), gy), dim3(256), 0, s, rows, cols, src, lds, dst, ldd);
+  return hipGetLastError();
+}
+
+hipError_t d2s_vec(hipStream_t s, int64_t n, const double* src, float* dst) {
+  hipLaunchKernelGGL(k_d2s_vec, dim3(grid1(n)), dim3(256), 0, s, n, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t axpy_s2d(hipStream_t s, int64_t n, double alpha, const float* z, const double* x, double* y) {
+  hipLaunchKernelGGL(k_axpy_s2d, dim3(grid1(n)), dim3(256), 0, s, n, alpha, z, x, y);
+  return hipGetLastError();
+}
+
+hipError_t s2d_scaled(hipStream_t s, int64_t n, double alpha, const float* z, double* y) {
+  hipLaunchKernelGGL(k_s2d_scaled, dim3(grid1(n)), dim3(256), 0, s, n, alpha, z, y);
+  return hipGetLastError();
+}
+
+hipError_t mdot(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* w, double* part,
+                double* out) {
+  const unsigned nb = grid1(n);
+  hipLaunchKernelGGL(k_mdot_part, dim3(nb), dim3(256), 0, s, n, k, V, ldv, w, part);
+  hipLaunchKernelGGL(k_mdot_fin, dim3(1), dim3(64), 0, s, (int64_t)nb, k, part, out);
+  return hipGetLastError();
+}
+
+hipError_t mgemv_sub(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h, double* w) {
+  hipLaunchKernelGGL(k_mgemv_sub, dim3(grid1(n)), dim3(256), 0, s, n, k, V, ldv, h, w);
+  return hipGetLastError();
+}
+
+hipError_t mgemv_add(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* c, double* y) {
+  hipLaunchKernelGGL(k_mgemv_add, dim3(grid1(n)), dim3(256), 0, s, n, k, V, ldv, c, y);
+  return hipGetLastError();
+}
+
+hipError_t scale_copy(hipStream_t s, int64_t n, double alpha, const double* src, double* dst) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(grid1(n)), dim3(256), 0, s, n, alpha, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t gather_scale(hipStream_t s, int64_t n, const int32_t* perm, const double* src,
+                        const unsigned long long* smax, float* dst) {
+  hipLaunchKernelGGL(k_gather_scale, dim3(grid1(n)), dim3(256), 0, s, n, perm, src, smax, dst);
+  return hipGetLastError();
+}
+
+hipError_t axpy_dev(hipStream_t s, int64_t n, double sign, const unsigned long long* smax, const float* z,
+                    const double* x, double* y) {
+  hipLaunchKernelGGL(k_axpy_dev, dim3(grid1(n)), dim3(256), 0, s, n, sign, smax, z, x, y);
+  return hipGetLastError();
+}
+
+hipError_t vec_add(hipStream_t s, int64_t n, const double* d, double* x) {
+  hipLaunchKernelGGL(k_add, dim3(grid1(n)), dim3(256), 0, s, n, d, x);
+  return hipGetLastError();
+}
+
+}  // namespace lupp

@@ -45,3 +45,14 @@ def test_null_handle_codes(lib):
     lib.lupp_status_string.restype = ctypes.c_char_p
     assert lib.lupp_status_string(0) == b"success"
     assert lib.lupp_status_string(-3) == b"invalid argument"
+
+
+def test_ir_opts_defaults():
+    """lupp_ir_opts_default is host-only: the documented defaults."""
+    import paper_2104_05782_amd as lupp
+    g = lupp.ir_opts("gmres")
+    c = lupp.ir_opts("classical")
+    assert (g.factor_prec, g.solver, g.tol, g.max_iter, g.gmres_restart, g.inner_tol, g.nb, g.fallback_fp64) == \
+        (lupp.PREC["fp16"], 1, 1e-14, 10, 30, 1e-6, 0, 0)
+    assert (c.solver, c.max_iter) == (0, 50)
+    assert lupp.ir_opts("gmres", factor_prec="fp8").factor_prec == 3
