@@ -232,6 +232,45 @@ int lupp_dgesv_mixed(lupp_handle_t h, int64_t n, int64_t nrhs, const double* dA,
                      const double* dB, int64_t ldb, double* dX, int64_t ldx,
                      const lupp_ir_opts* opts, lupp_ir_report* rep);
 
+/*
+ * Batched factorization and solve of many independent small systems.
+ *
+ * The paper's factorizations are of one large matrix; this entry point
+ * applies the same factorization (partial pivoting, LAPACK conventions, the
+ * blocked right-looking loop of Section 4.3 with its column-block step of
+ * Section 4.1) to a batch of small systems at once, one workgroup per system
+ * with the system held in on-chip memory.
+ *
+ *   batch       number of systems (>= 0)
+ *   dn          device int32[batch]: order n_i of system i, 0 <= n_i <= 128
+ *   dA, dA_off  device: system i is the column-major n_i x n_i matrix at
+ *               dA + dA_off[i] (leading dimension n_i), overwritten by L\U
+ *   dipiv, dipiv_off  device: ipiv of system i at dipiv + dipiv_off[i]
+ *               (n_i int32 entries, 1-based, LAPACK convention)
+ *   dB, dB_off  device: right-hand side of system i (n_i entries) at
+ *               dB + dB_off[i], overwritten by the solution x_i
+ *   dinfo       device int32[batch]: 0; k > 0 when U(k,k) of system i is
+ *               exactly zero (the factorization completes, x_i is not
+ *               computed and b_i is left unchanged, as in LAPACK's gesv);
+ *               -1 when n_i is outside [0, 128] (system untouched)
+ * Systems must not overlap.  The call is asynchronous on the handle's
+ * stream; it allocates its workspace on the first call for a batch size and
+ * afterwards neither allocates nor synchronizes with the host, so it can be
+ * captured in a HIP graph.  Host-side errors: -2 batch, then the pointer
+ * arguments in order (-3 dn ... -10 dinfo; for xGETRF_BATCHED -8 dinfo).
+ */
+int lupp_dgesv_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_t* dA_off,
+                       double* dA, const int64_t* dipiv_off, int32_t* dipiv,
+                       const int64_t* dB_off, double* dB, int32_t* dinfo);
+int lupp_sgesv_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_t* dA_off,
+                       float* dA, const int64_t* dipiv_off, int32_t* dipiv,
+                       const int64_t* dB_off, float* dB, int32_t* dinfo);
+/* Factorization only (no right-hand sides). */
+int lupp_dgetrf_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_t* dA_off,
+                        double* dA, const int64_t* dipiv_off, int32_t* dipiv, int32_t* dinfo);
+int lupp_sgetrf_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_t* dA_off,
+                        float* dA, const int64_t* dipiv_off, int32_t* dipiv, int32_t* dinfo);
+
 #ifdef __cplusplus
 }
 #endif

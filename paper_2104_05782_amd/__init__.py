@@ -24,7 +24,9 @@ from ._binding import (  # noqa: F401
     lupp_sgetrs,
     getrf,
     getrs,
+    gesv_batched,
     gesv_mixed,
+    lupp_xgesv_batched,
     ir_opts,
     lupp_dgesv_mixed,
     status_string,

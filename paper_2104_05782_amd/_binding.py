@@ -55,6 +55,11 @@ _lib.lupp_ir_opts_default.argtypes = [ctypes.POINTER(IrOpts), ctypes.c_int32]
 _lib.lupp_ir_opts_default.restype = None
 _lib.lupp_dgesv_mixed.argtypes = [_vp, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(IrOpts),
                                   ctypes.POINTER(IrReport)]
+for _name in ("lupp_dgesv_batched", "lupp_sgesv_batched"):
+    getattr(_lib, _name).argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+for _name in ("lupp_dgetrf_batched", "lupp_sgetrf_batched"):
+    getattr(_lib, _name).argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]
+BATCH_MAX_N = 128
 PHASES = {"panel": 0, "laswp": 1, "trsm": 2, "update": 3, "update_big": 4, "panel_leaf": 5, "panel_swap": 6,
           "panel_trsm": 7, "panel_gemm": 8}
 
@@ -239,6 +244,50 @@ def gesv_mixed(A: torch.Tensor, B: torch.Tensor, handle: Handle | None = None, s
     X = torch.empty(B2.shape[1], B2.shape[0], dtype=torch.float64, device=B.device).t()
     rep = lupp_dgesv_mixed(A, colmajor(B2), X, ir_opts(solver, **kw), handle)
     return (X if B.dim() == 2 else X[:, 0]), rep
+
+
+def lupp_xgesv_batched(n, A, a_off, ipiv, p_off, B, b_off, info, handle: Handle | None = None):
+    """Batched factorization and solve (lupp_dgesv_batched / lupp_sgesv_batched by
+    A's dtype): every argument is a device tensor (n int32, offsets int64, ipiv
+    and info int32, A and B packed float64/float32); B=None factors only."""
+    batch = int(n.numel())
+    for t, dt, what in ((n, torch.int32, "n"), (a_off, torch.int64, "a_off"), (p_off, torch.int64, "p_off"),
+                        (ipiv, torch.int32, "ipiv"), (info, torch.int32, "info")):
+        _dev(t, dt, what)
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % what)
+    if A.dtype not in (torch.float64, torch.float32):
+        raise TypeError("A must be float64 or float32")
+    _dev(A, A.dtype, "A")
+    if info.numel() < batch or a_off.numel() < batch or p_off.numel() < batch:
+        raise ValueError("n, a_off, p_off and info need one entry per system")
+    h = _prep(handle)
+    d = A.dtype == torch.float64
+    if B is None:
+        fn = _lib.lupp_dgetrf_batched if d else _lib.lupp_sgetrf_batched
+        _check(fn(h.ptr, batch, n.data_ptr(), a_off.data_ptr(), A.data_ptr(), p_off.data_ptr(), ipiv.data_ptr(),
+                  info.data_ptr()), fn.__name__)
+        return
+    _dev(B, A.dtype, "B")
+    _dev(b_off, torch.int64, "b_off")
+    if b_off.numel() < batch:
+        raise ValueError("b_off needs one entry per system")
+    fn = _lib.lupp_dgesv_batched if d else _lib.lupp_sgesv_batched
+    _check(fn(h.ptr, batch, n.data_ptr(), a_off.data_ptr(), A.data_ptr(), p_off.data_ptr(), ipiv.data_ptr(),
+              b_off.data_ptr(), B.data_ptr(), info.data_ptr()), fn.__name__)
+
+
+def gesv_batched(n, A, a_off, B=None, b_off=None, handle: Handle | None = None):
+    """Factor (and solve, when B is given) the packed batch in place; returns
+    (ipiv, p_off, info) device tensors (p_off: exclusive prefix sums of n)."""
+    n64 = n.to(torch.int64)
+    p_off = torch.zeros_like(n64)
+    if n.numel() > 1:
+        p_off[1:] = torch.cumsum(n64, 0)[:-1]
+    ipiv = torch.zeros(max(1, int(n64.clamp(min=0).sum().item())), dtype=torch.int32, device=A.device)
+    info = torch.zeros(max(1, n.numel()), dtype=torch.int32, device=A.device)
+    lupp_xgesv_batched(n, A, a_off, ipiv, p_off, B, b_off, info, handle)
+    return ipiv, p_off, info
 
 
 def getrf(A: torch.Tensor, handle: Handle | None = None):

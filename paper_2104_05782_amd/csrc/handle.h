@@ -13,6 +13,7 @@ struct TimingRecord {
   double flops = 0.0;
 };
 struct MixedWs;
+struct BatchWs;
 }  // namespace lupp
 
 struct lupp_handle_st {
@@ -38,6 +39,7 @@ struct lupp_handle_st {
   int64_t lp_scale_cap = 0;         // ints in each of lp_scale[0], lp_scale[1]
   lupp::TrsvState trsv{};           // one-launch triangular solve state (flags on demand)
   lupp::MixedWs* mixed = nullptr;   // workspace of lupp_dgesv_mixed
+  lupp::BatchWs* batch = nullptr;   // workspace and streams of the batched path
 };
 
 namespace lupp {
@@ -63,5 +65,6 @@ template <typename T>
 hipError_t getrs(lupp_handle_t h, int64_t n, int64_t nrhs, const T* LU, int64_t lda, const int32_t* ipiv, T* B,
                  int64_t ldb);
 void free_mixed(lupp_handle_t h);
+void free_batched(lupp_handle_t h);
 
 }  // namespace lupp

@@ -400,6 +400,7 @@ int lupp_destroy(lupp_handle_t h) {
   if (h->lp_scale[0]) (void)hipFree(h->lp_scale[0]);
   if (h->trsv.flags) (void)hipFree(h->trsv.flags);
   lupp::free_mixed(h);
+  lupp::free_batched(h);
   delete h;
   return rc;
 }
