@@ -25,6 +25,13 @@ The JSON line carries:
               U(-0.5,0.5), then a_ii := sum_j |a_ij|) and b iid U(-1,1); its
               effective rate is 2/3 n^3 over the wall time of factorization
               plus refinement
+  batched     20000 independent systems, n_i iid uniform on [8, 128], A_i and
+              b_i iid U(-1,1), packed column-major (lupp_xgesv_batched: LU with
+              partial pivoting and solve): factorizations per second from the
+              median of 20 replays of a captured HIP graph (inputs restored
+              between replays, outside the timed interval), against the HBM
+              roofline of the call's algorithmic bytes (A and b read, the factors and x
+              written, pivots written, sizes and offsets read)
 """
 from __future__ import annotations
 
@@ -130,6 +137,73 @@ def mixed_leg(torch, lupp, A0, n, seed, fp64_ms, runs):
             "runs": out, "best_converged": best}
 
 
+def batched_leg(torch, lupp, seed, count=20000, replays=20, dtype="f64"):
+    import synth
+    npdt = np.float64 if dtype == "f64" else np.float32
+    sizes = synth.batch_sizes(seed, count)
+    A, a_off, B, b_off = synth.batch_uniform(seed, sizes, npdt)
+    dn = torch.from_numpy(sizes).cuda()
+    dao = torch.from_numpy(a_off).cuda()
+    dbo = torch.from_numpy(b_off).cuda()
+    A0 = torch.from_numpy(A).cuda()
+    B0 = torch.from_numpy(B).cuda()
+    dA, dB = A0.clone(), B0.clone()
+    n64 = dn.to(torch.int64)
+    p_off = torch.zeros_like(n64)
+    p_off[1:] = torch.cumsum(n64, 0)[:-1]
+    ipiv = torch.zeros(int(n64.sum()), dtype=torch.int32, device="cuda")
+    info = torch.zeros(count, dtype=torch.int32, device="cuda")
+    h = lupp.Handle()
+    lupp.lupp_xgesv_batched(dn, dA, dao, ipiv, p_off, dB, dbo, info, handle=h)  # workspace
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    dA.copy_(A0)
+    dB.copy_(B0)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        lupp.lupp_xgesv_batched(dn, dA, dao, ipiv, p_off, dB, dbo, info, handle=h)
+    times = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for r in range(replays + 2):
+        dA.copy_(A0)
+        dB.copy_(B0)
+        torch.cuda.synchronize()
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        if r >= 2:
+            times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    bad = int((info != 0).sum().item())
+    # algorithmic bytes: A read + L\U written (n^2 each), b read + x written,
+    # ipiv written (4 B), n and three offsets read (4 + 24 B)
+    isz = 8 if dtype == "f64" else 4
+    s64 = sizes.astype(np.float64)
+    nbytes = float((2 * s64 * s64 * isz + 2 * s64 * isz + 4 * s64 + 28).sum())
+    flops = float((2.0 / 3.0 * s64 ** 3 + 2 * s64 ** 2).sum())
+    # a sampled backward-error check of the last replay
+    X = dB.cpu().numpy()
+    from oracle import checks
+    worst = 0.0
+    for i in range(0, count, max(1, count // 200)):
+        n = int(sizes[i])
+        Ai = A[a_off[i]:a_off[i] + n * n].reshape(n, n, order="F").astype(np.float64)
+        eta = checks.backward_error(Ai, X[b_off[i]:b_off[i] + n].astype(np.float64),
+                                    B[b_off[i]:b_off[i] + n].astype(np.float64))
+        worst = max(worst, eta / (n * (checks.U64 if dtype == "f64" else checks.U32)))
+    h.close()
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    out = {"workload": "%d systems, n_i ~ U{8..128}, A_i and b_i iid U(-1,1), %s, LU + solve" % (count, dtype),
+           "value": round(count / (ms * 1e-3), 1), "unit": "factorizations/s", "ms": round(ms, 4),
+           "replays": replays, "min_ms": round(min(times), 4), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
+                        "frac": round(gbs / 8000.0, 4), "traffic": None, "bytes": nbytes},
+           "check": {"nonzero_info": bad, "max_backward_error_over_n_u_sampled": worst}}
+    log("batched: %s" % out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +217,7 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-lookahead", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solve leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched small-systems leg")
     ap.add_argument("--profile-once", action="store_true",
                     help="counter runs: factor once without a pristine device copy, after a 1 GiB "
                          "device-to-device copy that calibrates the byte counters")
@@ -258,6 +333,11 @@ def main():
                           [("fp16", "gmres"), ("bf16", "gmres"), ("fp8", "gmres"), ("fp16", "classical"),
                            ("bf16", "classical")])
 
+    batched = None
+    if not args.no_batched and not args.profile_once:
+        log("batched leg")
+        batched = {"f64": batched_leg(torch, lupp, args.seed), "f32": batched_leg(torch, lupp, args.seed, dtype="f32")}
+
     out = {
         "metric": "LU TFLOP/s @n=32768: FP64 vs mixed+IR at FP64 backward err; batched LUs/s",
         "value": round(value, 3),
@@ -280,6 +360,7 @@ def main():
         "phases": phases,
         "check": check,
         "mixed": mixed,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
     h.close()

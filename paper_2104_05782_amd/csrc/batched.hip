@@ -11,13 +11,14 @@
 //
 // Scheduling: a binning kernel sorts the systems into four size classes
 // (n <= 32, 64, 96, 128), each served by one persistent launch whose
-// workgroups (64, 128, 256, 256 threads) take systems from an atomic queue;
+// workgroups (64, 256, 512, 512 threads) take systems from an atomic queue;
 // the LDS footprint of a class is its largest augmented matrix, so smaller
 // classes run more workgroups per CU.  The classes are launched on four
 // streams so that the short classes fill the CUs the long ones leave idle.
 // No host synchronization or allocation happens per call (graph-capturable
 // once the workspace exists for the batch size).
 #include "handle.h"
+#include "wave.h"
 
 namespace lupp {
 
@@ -85,14 +86,43 @@ __global__ __launch_bounds__(1024) void k_batch_bin(int32_t batch, const int32_t
   }
 }
 
-// (|v|, row) argmax with the lowest row among equal magnitudes
-template <typename T>
-__device__ __forceinline__ void better_of(T& av, int& ai, T& sv, T bv, int bi, T bs) {
-  if (bv > av || (bv == av && bi < ai)) {
-    av = bv;
-    ai = bi;
-    sv = bs;
-  }
+// DPP partner values inside 16-lane rows (quad_perm / row_half_mirror /
+// row_mirror), for 64-bit and 32-bit lanes
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)u, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(u >> 32), (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+// wavefront max of doubles (NaN ignored), the same value in every lane
+__device__ __forceinline__ double wave_max_f64(double v) {
+  v = fmax(v, dpp_f64<0xB1>(v));
+  v = fmax(v, dpp_f64<0x4E>(v));
+  v = fmax(v, dpp_f64<0x141>(v));
+  v = fmax(v, dpp_f64<0x140>(v));
+  double m = readlane_d(v, 0);
+  m = fmax(m, readlane_d(v, 16));
+  m = fmax(m, readlane_d(v, 32));
+  return fmax(m, readlane_d(v, 48));
+}
+
+// wavefront min of unsigned ints, the same value in every lane
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  v = min(v, dpp_u32<0xB1>(v));
+  v = min(v, dpp_u32<0x4E>(v));
+  v = min(v, dpp_u32<0x141>(v));
+  v = min(v, dpp_u32<0x140>(v));
+  uint32_t m = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+  m = min(m, (uint32_t)__builtin_amdgcn_readlane((int)v, 16));
+  m = min(m, (uint32_t)__builtin_amdgcn_readlane((int)v, 32));
+  return min(m, (uint32_t)__builtin_amdgcn_readlane((int)v, 48));
 }
 
 template <typename T, int NT>
@@ -103,12 +133,12 @@ __global__ __launch_bounds__(NT) void k_batch_lu(int cls, const int32_t* __restr
                                                  int32_t* __restrict__ ginfo, const int32_t* __restrict__ list,
                                                  int32_t* __restrict__ meta) {
   constexpr int NW = NT / 64;
+  constexpr int W = kPanelW;
   extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
   T* As = (T*)dyn;  // n x (n + 1), leading dimension n
-  __shared__ T s_wabs[NW], s_wval[NW];
-  __shared__ int s_widx[NW];
   __shared__ int s_piv[kBatchMaxN];
-  __shared__ int s_sys, s_info;
+  __shared__ int s_pdst[2 * W], s_psrc[2 * W];
+  __shared__ int s_sys, s_info, s_npairs;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int count = meta[cls], first = meta[4 + cls];
 
@@ -126,130 +156,214 @@ __global__ __launch_bounds__(NT) void k_batch_lu(int cls, const int32_t* __restr
     T* Bv = gB ? gB + boff[sys] : nullptr;
     const int ncol = n + (Bv ? 1 : 0);
     const int nn = n * n;
-    for (int e = tid; e < nn; e += NT) As[e] = A[e];
+    // ---- system into LDS, eight loads in flight per thread
+    for (int base = 0; base < nn; base += 8 * NT) {
+      T tmp[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = base + u * NT + tid;
+        tmp[u] = (e < nn) ? A[e] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = base + u * NT + tid;
+        if (e < nn) As[e] = tmp[u];
+      }
+    }
     if (Bv)
       for (int i = tid; i < n; i += NT) As[nn + i] = Bv[i];
     __syncthreads();
 
-    for (int j0 = 0; j0 < n; j0 += kPanelW) {
-      const int w = (n - j0 < kPanelW) ? (n - j0) : kPanelW;
-      // ---- panel: columns j0 .. j0+w-1, rows j0 .. n-1
-      for (int t = 0; t < w; ++t) {
-        const int c = j0 + t;
-        T av = T(-1), sv = T(0);
-        int ai = 0x7fffffff;
-        if (tid >= c && tid < n) {
-          sv = As[tid + c * n];
-          av = fabs(sv);
-          ai = tid;
+    for (int j0 = 0; j0 < n; j0 += W) {
+      const int w = (n - j0 < W) ? (n - j0) : W;
+      // ---- panel: columns j0 .. j0+w-1, rows j0 .. n-1, factored by wave 0
+      // with the rows in registers (lane holds rows lane and lane + 64).  Rows
+      // are not moved during the panel: pos0/pos1 give the logical row whose
+      // data each slot holds, an interchange swaps two logical positions, and
+      // the data is written to its final rows once at the end.
+      if (wave == 0) {
+        const int r0 = lane, r1 = lane + 64;
+        const bool ok0 = r0 >= j0 && r0 < n, ok1 = r1 >= j0 && r1 < n;
+        int pos0 = r0, pos1 = r1;
+        T v0[W], v1[W];
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+          v0[t] = (t < w && ok0) ? As[r0 + (j0 + t) * n] : T(0);
+          v1[t] = (t < w && ok1) ? As[r1 + (j0 + t) * n] : T(0);
         }
 #pragma unroll
-        for (int m = 1; m < 64; m <<= 1) {
-          const T bv = __shfl_xor(av, m, 64);
-          const int bi = __shfl_xor(ai, m, 64);
-          const T bs = __shfl_xor(sv, m, 64);
-          better_of(av, ai, sv, bv, bi, bs);
-        }
-        if (lane == 0) {
-          s_wabs[wave] = av;
-          s_wval[wave] = sv;
-          s_widx[wave] = ai;
-        }
-        __syncthreads();
-        T pa = s_wabs[0], pv = s_wval[0];
-        int p = s_widx[0];
+        for (int t = 0; t < W; ++t) {
+          if (t < w) {
+            const int c = j0 + t;
+            // pivot: the largest |a| over logical rows >= c, lowest row on ties
+            const bool q0 = ok0 && pos0 >= c, q1 = ok1 && pos1 >= c;
+            const double a0 = q0 ? (double)fabs(v0[t]) : -1.0, a1 = q1 ? (double)fabs(v1[t]) : -1.0;
+            const double m = wave_max_f64(fmax(a0, a1));
+            const uint32_t k0 = (q0 && a0 == m) ? (uint32_t)pos0 : 0x7fffffffu;
+            const uint32_t k1 = (q1 && a1 == m) ? (uint32_t)pos1 : 0x7fffffffu;
+            const uint32_t pm = wave_min_u32(min(k0, k1));
+            const int p = (pm >= (uint32_t)c && pm < (uint32_t)n) ? (int)pm : c;  // c only with NaN entries
+            // where logical row p lives
+            const uint64_t b0 = __ballot(ok0 && pos0 == p), b1 = __ballot(ok1 && pos1 == p);
+            const bool in1 = b0 == 0;
+            const uint64_t bm = in1 ? b1 : b0;
+            const int pl = bm ? (int)__builtin_ctzll(bm) : 0;
+            T rp[W];
 #pragma unroll
-        for (int q = 1; q < NW; ++q) better_of(pa, p, pv, s_wabs[q], s_widx[q], s_wval[q]);
-        if (p < c || p >= n) p = c;  // only reachable with NaN entries (outside the contract)
-        if (tid == 0) {
-          s_piv[c] = p;
-          if (pv == T(0) && s_info == 0) s_info = c + 1;
-        }
-        // interchange rows c and p in every column (b included); one column per thread
-        if (p != c && tid < ncol) {
-          const T x = As[c + tid * n];
-          As[c + tid * n] = As[p + tid * n];
-          As[p + tid * n] = x;
-        }
-        __syncthreads();
-        // multipliers of column c and their update of the rest of the panel
-        if (pv != T(0) && tid > c && tid < n) {
-          const T l = As[tid + c * n] / pv;
-          As[tid + c * n] = l;
-          for (int t2 = t + 1; t2 < w; ++t2) {
-            const int col = j0 + t2;
-            As[tid + col * n] -= l * As[c + col * n];
-          }
-        }
-        __syncthreads();
-      }
-      const int j1 = j0 + w;
-      if (j1 >= ncol) break;
-      // ---- U12 := inv(L11) A12 (rows j0..j1-1, columns j1..ncol-1), one column per thread
-      for (int j = j1 + tid; j < ncol; j += NT) {
-        T x[kPanelW];
+            for (int t2 = 0; t2 < W; ++t2) {
+              rp[t2] = T(0);
+              if (t2 >= t && t2 < w) rp[t2] = readlane_d(in1 ? v1[t2] : v0[t2], pl);
+            }
+            const T pv = rp[t];
+            if (lane == 0) {
+              s_piv[c] = p;
+              if (pv == T(0) && s_info == 0) s_info = c + 1;
+            }
+            if (p != c) {
+              pos0 = (pos0 == c) ? p : ((pos0 == p) ? c : pos0);
+              pos1 = (pos1 == c) ? p : ((pos1 == p) ? c : pos1);
+            }
+            // multipliers (true division: |l| <= 1 exactly) and the panel's rank-1 update
+            if (pv != T(0)) {
+              if (ok0 && pos0 > c) {
+                const T l = v0[t] / pv;
+                v0[t] = l;
 #pragma unroll
-        for (int r = 0; r < kPanelW; ++r) x[r] = (r < w) ? As[j0 + r + j * n] : T(0);
+                for (int t2 = t + 1; t2 < W; ++t2) v0[t2] -= l * rp[t2];
+              }
+              if (ok1 && pos1 > c) {
+                const T l = v1[t] / pv;
+                v1[t] = l;
 #pragma unroll
-        for (int r = 1; r < kPanelW; ++r) {
-          if (r < w) {
-            T s = x[r];
-#pragma unroll
-            for (int q = 0; q < kPanelW; ++q)
-              if (q < r) s -= As[j0 + r + (j0 + q) * n] * x[q];
-            x[r] = s;
+                for (int t2 = t + 1; t2 < W; ++t2) v1[t2] -= l * rp[t2];
+              }
+            }
           }
         }
 #pragma unroll
-        for (int r = 1; r < kPanelW; ++r)
-          if (r < w) As[j0 + r + j * n] = x[r];
+        for (int t = 0; t < W; ++t) {
+          if (t < w && ok0) As[pos0 + (j0 + t) * n] = v0[t];
+          if (t < w && ok1) As[pos1 + (j0 + t) * n] = v1[t];
+        }
+        // the block's interchanges composed: row pos <- row r for every moved row
+        const bool mv0 = ok0 && pos0 != r0, mv1 = ok1 && pos1 != r1;
+        const uint64_t m0 = __ballot(mv0), m1 = __ballot(mv1);
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        const int cnt0 = __popcll(m0);
+        if (mv0) {
+          const int q = __popcll(m0 & below);
+          s_pdst[q] = pos0;
+          s_psrc[q] = r0;
+        }
+        if (mv1) {
+          const int q = cnt0 + __popcll(m1 & below);
+          s_pdst[q] = pos1;
+          s_psrc[q] = r1;
+        }
+        if (lane == 0) s_npairs = cnt0 + __popcll(m1);
       }
       __syncthreads();
-      // ---- A22 -= L21 U12: lanes over rows (two 64-row halves), waves over columns
+      // ---- per column outside the panel (b included), one column per thread:
+      // the block's composed interchanges (all moved rows read, then
+      // written), then U12 := inv(L11) A12 for the columns right of the panel
+      const int j1 = j0 + w;
+      {
+        const int np = s_npairs;
+        for (int j = tid; j < ncol; j += NT) {
+          if (j >= j0 && j < j1) continue;
+          if (np > 0) {
+            T val[2 * W];
+#pragma unroll
+            for (int q = 0; q < 2 * W; ++q)
+              if (q < np) val[q] = As[s_psrc[q] + j * n];
+#pragma unroll
+            for (int q = 0; q < 2 * W; ++q)
+              if (q < np) As[s_pdst[q] + j * n] = val[q];
+          }
+          if (j >= j1) {
+            T x[W];
+#pragma unroll
+            for (int q = 0; q < W; ++q) x[q] = (q < w) ? As[j0 + q + j * n] : T(0);
+#pragma unroll
+            for (int q = 0; q < W; ++q)
+#pragma unroll
+              for (int r = q + 1; r < W; ++r)
+                if (r < w) x[r] -= As[j0 + r + (j0 + q) * n] * x[q];
+#pragma unroll
+            for (int q = 1; q < W; ++q)
+              if (q < w) As[j0 + q + j * n] = x[q];
+          }
+        }
+      }
+      if (j1 >= ncol) break;
+      __syncthreads();
+      // ---- A22 -= L21 U12: lanes over rows (two 64-row halves), waves over
+      // columns, two columns per step
       if (j1 < n) {
-        T l[2][kPanelW];
+        T l[2][W];
         const int i0 = j1 + lane, i1 = j1 + 64 + lane;
 #pragma unroll
-        for (int q = 0; q < kPanelW; ++q) {
+        for (int q = 0; q < W; ++q) {
           l[0][q] = (q < w && i0 < n) ? As[i0 + (j0 + q) * n] : T(0);
           l[1][q] = (q < w && i1 < n) ? As[i1 + (j0 + q) * n] : T(0);
         }
-        for (int j = j1 + wave; j < ncol; j += NW) {
-          T u[kPanelW];
+        for (int j = j1 + wave; j < ncol; j += 2 * NW) {
+          const int jb = j + NW;
+          const bool two = jb < ncol;
+          T u[W], ub[W];
 #pragma unroll
-          for (int q = 0; q < kPanelW; ++q) u[q] = (q < w) ? As[j0 + q + j * n] : T(0);
-          if (i0 < n) {
-            T s = As[i0 + j * n];
-#pragma unroll
-            for (int q = 0; q < kPanelW; ++q) s -= l[0][q] * u[q];
-            As[i0 + j * n] = s;
+          for (int q = 0; q < W; ++q) {
+            u[q] = (q < w) ? As[j0 + q + j * n] : T(0);
+            ub[q] = (q < w && two) ? As[j0 + q + jb * n] : T(0);
           }
-          if (i1 < n) {
-            T s = As[i1 + j * n];
+          T s0 = (i0 < n) ? As[i0 + j * n] : T(0);
+          T s1 = (i1 < n) ? As[i1 + j * n] : T(0);
+          T s2 = (i0 < n && two) ? As[i0 + jb * n] : T(0);
+          T s3 = (i1 < n && two) ? As[i1 + jb * n] : T(0);
 #pragma unroll
-            for (int q = 0; q < kPanelW; ++q) s -= l[1][q] * u[q];
-            As[i1 + j * n] = s;
+          for (int q = 0; q < W; ++q) {
+            s0 -= l[0][q] * u[q];
+            s1 -= l[1][q] * u[q];
+            s2 -= l[0][q] * ub[q];
+            s3 -= l[1][q] * ub[q];
           }
+          if (i0 < n) As[i0 + j * n] = s0;
+          if (i1 < n) As[i1 + j * n] = s1;
+          if (two && i0 < n) As[i0 + jb * n] = s2;
+          if (two && i1 < n) As[i1 + jb * n] = s3;
         }
       }
       __syncthreads();
     }
+    __syncthreads();
 
-    // ---- x = inv(U) c, c = L^{-1} P b in column n (one wave; skipped on a zero pivot)
+    // ---- x = inv(U) c with c = L^{-1} P b in column n (one wave; skipped on a
+    // zero pivot, as in LAPACK's gesv): reciprocals of the diagonal first, the
+    // next column of U prefetched while the current one is applied
     const int info = s_info;
     if (Bv && info == 0 && wave == 0) {
       T c0 = (lane < n) ? As[nn + lane] : T(0);
       T c1 = (lane + 64 < n) ? As[nn + lane + 64] : T(0);
-      for (int k = n - 1; k >= 0; --k) {
-        const T ck = (k < 64) ? readlane_d(c0, k) : readlane_d(c1, k - 64);
-        const T xk = ck / As[k + k * n];
-        if (k < 64) {
-          if (lane == k) c0 = xk;
-        } else {
-          if (lane == k - 64) c1 = xk;
+      const T d0 = (lane < n) ? T(1) / As[lane + lane * n] : T(0);
+      const T d1 = (lane + 64 < n) ? T(1) / As[lane + 64 + (lane + 64) * n] : T(0);
+      int k = n - 1;
+      T u0 = (lane < k) ? As[lane + k * n] : T(0);
+      T u1 = (lane + 64 < k) ? As[lane + 64 + k * n] : T(0);
+      for (; k >= 0; --k) {
+        T u0n = T(0), u1n = T(0);
+        if (k > 0) {
+          if (lane < k - 1) u0n = As[lane + (k - 1) * n];
+          if (lane + 64 < k - 1) u1n = As[lane + 64 + (k - 1) * n];
         }
-        if (lane < k) c0 -= As[lane + k * n] * xk;
-        if (lane + 64 < k) c1 -= As[lane + 64 + k * n] * xk;
+        const bool hi = k >= 64;
+        const int kl = hi ? k - 64 : k;
+        const T xk = readlane_d(hi ? c1 : c0, kl) * readlane_d(hi ? d1 : d0, kl);
+        if (!hi && lane == kl) c0 = xk;
+        if (hi && lane == kl) c1 = xk;
+        c0 -= u0 * xk;
+        c1 -= u1 * xk;
+        u0 = u0n;
+        u1 = u1n;
       }
       if (lane < n) Bv[lane] = c0;
       if (lane + 64 < n) Bv[lane + 64] = c1;
@@ -266,11 +380,11 @@ template <typename T>
 const void* batch_kernel(int cls) {
   switch (cls) {
     case 0: return (const void*)k_batch_lu<T, 64>;
-    case 1: return (const void*)k_batch_lu<T, 128>;
-    default: return (const void*)k_batch_lu<T, 256>;
+    case 1: return (const void*)k_batch_lu<T, 256>;
+    default: return (const void*)k_batch_lu<T, 512>;
   }
 }
-inline int class_threads(int cls) { return cls == 0 ? 64 : (cls == 1 ? 128 : 256); }
+inline int class_threads(int cls) { return cls == 0 ? 64 : (cls == 1 ? 256 : 512); }
 inline int class_nmax(int cls) { return 32 * (cls + 1); }
 template <typename T>
 size_t class_lds(int cls) {
