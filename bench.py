@@ -137,7 +137,7 @@ def mixed_leg(torch, lupp, A0, n, seed, fp64_ms, runs):
             "runs": out, "best_converged": best}
 
 
-def batched_leg(torch, lupp, seed, count=20000, replays=20, dtype="f64"):
+def batched_leg(torch, lupp, seed, count=20000, replays=20, dtype="f64", graph=True):
     import synth
     npdt = np.float64 if dtype == "f64" else np.float32
     sizes = synth.batch_sizes(seed, count)
@@ -156,12 +156,14 @@ def batched_leg(torch, lupp, seed, count=20000, replays=20, dtype="f64"):
     h = lupp.Handle()
     lupp.lupp_xgesv_batched(dn, dA, dao, ipiv, p_off, dB, dbo, info, handle=h)  # workspace
     torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    dA.copy_(A0)
-    dB.copy_(B0)
-    torch.cuda.synchronize()
-    with torch.cuda.graph(g):
-        lupp.lupp_xgesv_batched(dn, dA, dao, ipiv, p_off, dB, dbo, info, handle=h)
+    g = None
+    if graph:
+        g = torch.cuda.CUDAGraph()
+        dA.copy_(A0)
+        dB.copy_(B0)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            lupp.lupp_xgesv_batched(dn, dA, dao, ipiv, p_off, dB, dbo, info, handle=h)
     times = []
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for r in range(replays + 2):
@@ -169,7 +171,10 @@ def batched_leg(torch, lupp, seed, count=20000, replays=20, dtype="f64"):
         dB.copy_(B0)
         torch.cuda.synchronize()
         e0.record()
-        g.replay()
+        if g is not None:
+            g.replay()
+        else:
+            lupp.lupp_xgesv_batched(dn, dA, dao, ipiv, p_off, dB, dbo, info, handle=h)
         e1.record()
         torch.cuda.synchronize()
         if r >= 2:
@@ -196,7 +201,7 @@ def batched_leg(torch, lupp, seed, count=20000, replays=20, dtype="f64"):
     gbs = nbytes / (ms * 1e-3) / 1e9
     out = {"workload": "%d systems, n_i ~ U{8..128}, A_i and b_i iid U(-1,1), %s, LU + solve" % (count, dtype),
            "value": round(count / (ms * 1e-3), 1), "unit": "factorizations/s", "ms": round(ms, 4),
-           "replays": replays, "min_ms": round(min(times), 4), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+           "replays": replays, "graph": bool(graph), "min_ms": round(min(times), 4), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
                         "frac": round(gbs / 8000.0, 4), "traffic": None, "bytes": nbytes},
            "check": {"nonzero_info": bad, "max_backward_error_over_n_u_sampled": worst}}
@@ -325,18 +330,21 @@ def main():
         log("cpu baseline: %s" % cpu)
 
     mixed = None
-    if not args.no_mixed and args.dtype == "f64" and not args.profile_once:
+    if not args.no_mixed and args.dtype == "f64":
         del A
         torch.cuda.empty_cache()
         log("mixed-precision leg")
-        mixed = mixed_leg(torch, lupp, A0, n, args.seed, ms_per_step,
-                          [("fp16", "gmres"), ("bf16", "gmres"), ("fp8", "gmres"), ("fp16", "classical"),
-                           ("bf16", "classical")])
+        runs = [("fp16", "gmres"), ("bf16", "gmres"), ("fp8", "gmres"), ("fp16", "classical"), ("bf16", "classical")]
+        mixed = mixed_leg(torch, lupp, A0, n, args.seed, ms_per_step, runs[:1] if args.profile_once else runs)
 
     batched = None
-    if not args.no_batched and not args.profile_once:
+    if not args.no_batched:
         log("batched leg")
-        batched = {"f64": batched_leg(torch, lupp, args.seed), "f32": batched_leg(torch, lupp, args.seed, dtype="f32")}
+        if args.profile_once:  # counter runs: eager calls, no graph replays
+            batched = {"f64": batched_leg(torch, lupp, args.seed, replays=1, graph=False)}
+        else:
+            batched = {"f64": batched_leg(torch, lupp, args.seed),
+                       "f32": batched_leg(torch, lupp, args.seed, dtype="f32")}
 
     out = {
         "metric": "LU TFLOP/s @n=32768: FP64 vs mixed+IR at FP64 backward err; batched LUs/s",
