@@ -419,7 +419,7 @@ int lupp_set_option(lupp_handle_t h, int option, int64_t value) {
       h->nb = value;
       return LUPP_OK;
     case LUPP_OPT_PANEL_LEAF:
-      if (value != 8 && value != 16 && value != 32) return -3;
+      if (value != 8 && value != 16) return -3;
       h->leaf = (int)value;
       return LUPP_OK;
     case LUPP_OPT_TIMING:

@@ -115,7 +115,11 @@ __global__ __launch_bounds__(NT) void k_panel_leaf(int64_t r, int w, T* __restri
   }
   __syncthreads();
 
-  for (int j = 0; j < w; ++j) {
+  // fully unrolled over the W columns: every register index below is a
+  // compile-time constant (no select chains over the row's registers)
+#pragma clang loop unroll(full)
+  for (int j = 0; j < W; ++j) {
+    if (j < w) {
     const int par = j & 1;
     // 1. local candidate
     double bv = -1.0;
@@ -295,6 +299,7 @@ __global__ __launch_bounds__(NT) void k_panel_leaf(int64_t r, int w, T* __restri
     }
     // s_prow/s_rowj are rewritten only after the next column's first barrier,
     // which every wave reaches after finishing this column
+    }
   }
 
   if (pend) {
@@ -344,11 +349,9 @@ namespace {
 constexpr int kLeafThreads = 256;
 // rows per thread: fewest workgroups (cheapest exchange) that keep the block
 // in registers
-int leaf_rpt(int64_t r) {
-  constexpr int NT = kLeafThreads;
-  if (r <= NT * 4) return (r <= NT) ? 1 : (r <= 2 * NT ? 2 : 4);
-  return (r <= (int64_t)16 * NT * 2) ? 2 : 4;
-}
+// rows per thread: four at every height (the leaf is one fully unrolled
+// W = 16 instantiation per precision; narrower leaves are masked)
+int leaf_rpt(int64_t) { return 4; }
 }  // namespace
 
 int panel_groups(int64_t r) {
@@ -360,7 +363,7 @@ template <typename T>
 hipError_t panel_leaf(hipStream_t s, int64_t r, int w, T* P, int64_t ld, int32_t* ipiv, int64_t k, int32_t* info,
                       LeafSlots* ws, uint32_t epoch, int64_t oc_lo, int64_t oc_hi) {
   if (w <= 0 || r <= 0) return hipSuccess;
-  if (w > kLeafMaxWidth || oc_lo > 0 || oc_hi < w) return hipErrorInvalidValue;
+  if (w > 16 || oc_lo > 0 || oc_hi < w) return hipErrorInvalidValue;
   constexpr int NT = kLeafThreads;
   const int rpt = leaf_rpt(r);
   const int64_t G64 = (r + (int64_t)NT * rpt - 1) / ((int64_t)NT * rpt);
@@ -368,14 +371,7 @@ hipError_t panel_leaf(hipStream_t s, int64_t r, int w, T* P, int64_t ld, int32_t
   const int G = (int)G64;
   const int64_t n_other = -oc_lo + (oc_hi - w);
   if (n_other > (int64_t)kMaxOther * G * NT) return hipErrorInvalidValue;
-  if (w <= 16) {
-    if (rpt == 1) return launch_leaf<T, 16, 1, NT>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch, oc_lo, oc_hi);
-    if (rpt == 2) return launch_leaf<T, 16, 2, NT>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch, oc_lo, oc_hi);
-    return launch_leaf<T, 16, 4, NT>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch, oc_lo, oc_hi);
-  }
-  if (rpt == 1) return launch_leaf<T, 32, 1, NT>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch, oc_lo, oc_hi);
-  if (rpt == 2) return launch_leaf<T, 32, 2, NT>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch, oc_lo, oc_hi);
-  return launch_leaf<T, 32, 4, NT>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch, oc_lo, oc_hi);
+  return launch_leaf<T, 16, 4, NT>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch, oc_lo, oc_hi);
 }
 
 template hipError_t panel_leaf<double>(hipStream_t, int64_t, int, double*, int64_t, int32_t*, int64_t, int32_t*,
