@@ -41,16 +41,6 @@ constexpr int kPanelW = 8;  // panel width of the per-system blocked factorizati
 
 __device__ __forceinline__ int size_class(int n) { return n <= 32 ? 0 : (n <= 64 ? 1 : (n <= 96 ? 2 : 3)); }
 
-__device__ __forceinline__ double readlane_d(double v, int k) {
-  const uint64_t u = (uint64_t)__double_as_longlong(v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, k);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), k);
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-__device__ __forceinline__ float readlane_d(float v, int k) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
-}
-
 // Sort systems into size classes; reset the queue heads.  One workgroup.
 __global__ __launch_bounds__(1024) void k_batch_bin(int32_t batch, const int32_t* __restrict__ dn,
                                                     int32_t* __restrict__ list, int32_t* __restrict__ meta,
@@ -84,45 +74,6 @@ __global__ __launch_bounds__(1024) void k_batch_bin(int32_t batch, const int32_t
       list[off[c] + atomicAdd(&cur[c], 1)] = i;
     }
   }
-}
-
-// DPP partner values inside 16-lane rows (quad_perm / row_half_mirror /
-// row_mirror), for 64-bit and 32-bit lanes
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const uint64_t u = (uint64_t)__double_as_longlong(v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)u, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
-  const uint32_t hi =
-      (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(u >> 32), (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
-}
-
-// wavefront max of doubles (NaN ignored), the same value in every lane
-__device__ __forceinline__ double wave_max_f64(double v) {
-  v = fmax(v, dpp_f64<0xB1>(v));
-  v = fmax(v, dpp_f64<0x4E>(v));
-  v = fmax(v, dpp_f64<0x141>(v));
-  v = fmax(v, dpp_f64<0x140>(v));
-  double m = readlane_d(v, 0);
-  m = fmax(m, readlane_d(v, 16));
-  m = fmax(m, readlane_d(v, 32));
-  return fmax(m, readlane_d(v, 48));
-}
-
-// wavefront min of unsigned ints, the same value in every lane
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-  v = min(v, dpp_u32<0xB1>(v));
-  v = min(v, dpp_u32<0x4E>(v));
-  v = min(v, dpp_u32<0x141>(v));
-  v = min(v, dpp_u32<0x140>(v));
-  uint32_t m = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
-  m = min(m, (uint32_t)__builtin_amdgcn_readlane((int)v, 16));
-  m = min(m, (uint32_t)__builtin_amdgcn_readlane((int)v, 32));
-  return min(m, (uint32_t)__builtin_amdgcn_readlane((int)v, 48));
 }
 
 template <typename T, int NT>

@@ -37,21 +37,24 @@ struct Mfma<float> {
 };
 
 // ---------------------------------------------------------------- workspace
-// Device-resident state of the cooperative panel kernel: one slot per
-// workgroup with its pivot candidate and the candidate's row, a copy of the
-// current diagonal row, per-workgroup progress flags and an error flag.  All
-// slot traffic uses device-coherent (agent-scope) atomic loads and stores.
+// Device-resident state of the cooperative panel kernel.  Per column and
+// workgroup a record of 64-bit words, each carrying the column's tag in its
+// upper half and 32 payload bits in its lower half: the candidate |a| (two
+// words), its row (one word) and the candidate row (two words per value); a
+// reader accepts a record word only when its tag is the current one, so no
+// separate flag or store fence is needed.  Records are double-buffered by
+// column parity.  The error flag is set when a bounded wait expires.
 constexpr int kLeafMaxGroups = 128;
-constexpr int kLeafMaxWidth = 32;
+constexpr int kLeafMaxWidth = 16;
+constexpr int kLeafRecWords = 3 + 2 * kLeafMaxWidth;  // 35 used
+constexpr int kLeafRecStride = 36;
 
 struct LeafSlots {
-  uint32_t flags[kLeafMaxGroups];                     // progress flag per workgroup
-  int32_t err;                                        // set when a bounded wait expires
+  uint32_t flags[kLeafMaxGroups];  // unused by the tagged exchange; kept zero
+  int32_t err;                     // set when a bounded wait expires
   int32_t pad_[31];
-  double cand_val[2][kLeafMaxGroups];                 // |candidate|, double-buffered by column parity
-  int64_t cand_idx[2][kLeafMaxGroups];                // candidate row (panel-local)
-  double cand_row[2][kLeafMaxGroups][kLeafMaxWidth];  // candidate row values (T stored as double)
-  double rowj[2][kLeafMaxWidth];                      // the diagonal row before the interchange
+  uint64_t rec[2][kLeafMaxGroups][kLeafRecStride];  // candidate records, by column parity
+  uint64_t rowj[2][2 * kLeafMaxWidth];              // the diagonal row before the interchange
 };
 
 // Row movement of a run of consecutive interchanges k1..k2-1 (k2 - k1 <=

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_gemm_sub(int64_t M, int
   constexpr int NT = 64 * WGM * WGN;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int FM = WTM / 16, FN = WTN / 16;
-  constexpr int PAD = 16;
+  constexpr int PAD = 16;  // 16-element k-rows (64 B in FP32) land in distinct bank groups
   constexpr int LDSA = BM + PAD, LDSB = BN + PAD;
   constexpr int EA = BM * BK / NT, EB = BK * BN / NT;
   constexpr int KA = NT / BM;  // k-rows of the A tile loaded per pass
@@ -186,7 +186,7 @@ __device__ __forceinline__ void dgemm4_body(int64_t M, int64_t N, int64_t K, con
   constexpr int NT = 64 * WGM * WGN;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int RG = WTM / 8, CG = WTN / 8;
-  constexpr int PAD = 16;
+  constexpr int PAD = 8;  // rows 1088 B apart: the four k-rows a wavefront reads hit distinct bank groups
   constexpr int LDSA = BM + PAD, LDSB = BN + PAD;
   constexpr int SA = BK * LDSA, SB = BK * LDSB;
   constexpr int EA = BM * BK / NT, EB = BK * BN / NT;
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_dgemm_sub_4x4(int64_t M
                                                                        const double* __restrict__ B, int64_t ldb,
                                                                        double* __restrict__ C, int64_t ldc,
                                                                        int tiles_m, int tiles_n) {
-  constexpr int PAD = 16;
+  constexpr int PAD = 8;  // rows 1088 B apart: the four k-rows a wavefront reads hit distinct bank groups
   __shared__ double sA[2 * BK * (BM + PAD)];
   __shared__ double sB[2 * BK * (BN + PAD)];
   const int total = tiles_m * tiles_n;

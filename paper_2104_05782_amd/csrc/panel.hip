@@ -12,10 +12,11 @@
 //      asc), so any reduction tree reproduces the sequential first-maximum
 //      scan;
 //   2. with G > 1 each workgroup publishes its candidate, the candidate's row
-//      (and, from the owner of row j, row j) with device-coherent stores,
-//      waits for their completion, and raises its own progress flag; every
-//      workgroup polls the G flags (no shared counter: no atomic contention),
-//      then reads all G candidates and candidate rows in one round trip;
+//      (and, from the owner of row j, row j) as 64-bit device-coherent words
+//      that each carry the column's tag -- no store fence, no separate flag.
+//      One wavefront polls the G three-word headers (|a|, row) until all tags
+//      are current, picks the winner, then reads the winner's row and row j
+//      (tag-checked): two light round trips;
 //   3. interchange (the two owning threads exchange whole rows), true-division
 //      scaling of column j, rank-1 update of the remaining columns.
 // The same interchange is applied to the other columns of the enclosing
@@ -45,12 +46,6 @@ __device__ __forceinline__ uint64_t ld_u64(const void* p) {
 __device__ __forceinline__ void st_f64(double* p, double v) { st_u64(p, __double_as_longlong(v)); }
 __device__ __forceinline__ double ld_f64(const double* p) { return __longlong_as_double(ld_u64(p)); }
 
-// wait until this thread's stores have completed (reached the coherence point)
-__device__ __forceinline__ void drain_stores() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0);
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
 
 // Workgroup barrier that waits only for LDS traffic.  (__syncthreads also
 // waits for every outstanding global load and store of the wave, which would
@@ -68,22 +63,25 @@ __global__ __launch_bounds__(NT) void k_panel_leaf(int64_t r, int w, T* __restri
                                                    int32_t* __restrict__ ipiv, int64_t k,
                                                    int32_t* __restrict__ info, LeafSlots* __restrict__ ws,
                                                    uint32_t epoch, int64_t oc_lo, int64_t oc_hi) {
+  static_assert(W <= kLeafMaxWidth, "leaf wider than the exchange records");
   constexpr int NW = NT / 64;
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = blockIdx.x, G = gridDim.x;
   const int64_t rbase = (int64_t)g * NT * RPT;
 
-  __shared__ T s_prow[W];
-  __shared__ T s_rowj[W];
+  // double-buffered by column parity: a buffer written for column j is read
+  // only before the first barrier of column j + 1
+  __shared__ T s_wrow[2][NW][W];  // each wavefront's candidate row
+  __shared__ T s_rowj[2][W];      // row j before the interchange
+  __shared__ T s_prow[2][W];      // the pivot row (G > 1)
   __shared__ double s_wv[2][NW];
-  __shared__ int64_t s_wi[2][NW];
-  __shared__ int64_t s_bi;
+  __shared__ uint32_t s_wi[2][NW];
+  __shared__ uint32_t s_bi[2];
   __shared__ int s_broken;
   __shared__ int32_t s_ipiv[W];
   __shared__ int32_t s_zero;
-  __shared__ double s_cv[kLeafMaxGroups];
-  __shared__ int64_t s_ci[kLeafMaxGroups];
-  __shared__ double s_crow[kLeafMaxGroups * W];
+  __shared__ uint32_t s_words[3 * kLeafMaxGroups];
 
   T a[RPT][W];
 #pragma unroll
@@ -92,7 +90,6 @@ __global__ __launch_bounds__(NT) void k_panel_leaf(int64_t r, int w, T* __restri
 #pragma unroll
     for (int c = 0; c < W; ++c) a[q][c] = (i < r && c < w) ? P[i + c * ld] : T(0);
   }
-
   // other columns of the enclosing block owned by this thread
   const int64_t n_left = -oc_lo, n_other = n_left + (oc_hi - w);
   const int64_t gt = (int64_t)g * NT + tid, gstride = (int64_t)G * NT;
@@ -120,185 +117,207 @@ __global__ __launch_bounds__(NT) void k_panel_leaf(int64_t r, int w, T* __restri
 #pragma clang loop unroll(full)
   for (int j = 0; j < W; ++j) {
     if (j < w) {
-    const int par = j & 1;
-    // 1. local candidate
-    double bv = -1.0;
-    int64_t bi = INT64_MAX;
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int64_t i = rbase + q * NT + tid;
-      T x = T(0);
-#pragma unroll
-      for (int c = 0; c < W; ++c)
-        if (c == j) x = a[q][c];
-      const double v = fabs((double)x);
-      if (i >= j && i < r && better(v, i, bv, bi)) {
-        bv = v;
-        bi = i;
-      }
-    }
-    wave_argmax(bv, bi);
-    if (lane == 0) {
-      s_wv[par][wave] = bv;
-      s_wi[par][wave] = bi;
-    }
-    lds_barrier();
-    // every thread combines the wavefront candidates itself (no extra barrier)
-    double wg_v = s_wv[par][0];
-    int64_t wg_best = s_wi[par][0];
-#pragma unroll
-    for (int q = 1; q < NW; ++q)
-      if (better(s_wv[par][q], s_wi[par][q], wg_v, wg_best)) {
-        wg_v = s_wv[par][q];
-        wg_best = s_wi[par][q];
-      }
-
-    // 2. publish and combine
-    int64_t gbest;
-    if (G == 1) {
+      const int par = j & 1;
+      // 1. this thread's candidate: the first maximal |a| among its rows >= j
+      //    (its rows increase with q), then the wavefront's, exactly: the
+      //    largest |a|, then the lowest row holding it
+      double lv = -1.0;
+      uint32_t li = kNone;
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
         const int64_t i = rbase + q * NT + tid;
-        if (i == wg_best) {
-#pragma unroll
-          for (int c = 0; c < W; ++c) s_prow[c] = a[q][c];
-        }
-        if (i == j) {
-#pragma unroll
-          for (int c = 0; c < W; ++c) s_rowj[c] = a[q][c];
+        const double v = fabs((double)a[q][j]);
+        if (i >= j && i < r && v > lv) {
+          lv = v;
+          li = (uint32_t)i;
         }
       }
-      lds_barrier();
-      gbest = wg_best;
-    } else {
-      bool wrote = false;
+      const double wm = wave_max_f64(lv);
+      const uint32_t wi = wave_min_u32((lv == wm) ? li : kNone);
+      // the wavefront's candidate row and row j go to LDS with the candidate
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
         const int64_t i = rbase + q * NT + tid;
-        if (i == wg_best && wg_best < r) {
+        if (i == (int64_t)wi) {
 #pragma unroll
-          for (int c = 0; c < W; ++c) st_f64(&ws->cand_row[par][g][c], (double)a[q][c]);
-          wrote = true;
+          for (int c = 0; c < W; ++c) s_wrow[par][wave][c] = a[q][c];
         }
         if (i == j) {
 #pragma unroll
-          for (int c = 0; c < W; ++c) st_f64(&ws->rowj[par][c], (double)a[q][c]);
-          wrote = true;
+          for (int c = 0; c < W; ++c) s_rowj[par][c] = a[q][c];
         }
       }
-      if (tid == 0) {
-        st_f64(&ws->cand_val[par][g], wg_v);
-        st_u64(&ws->cand_idx[par][g], (uint64_t)wg_best);
-        wrote = true;
+      if (lane == 0) {
+        s_wv[par][wave] = wm;
+        s_wi[par][wave] = wi;
       }
-      if (wrote) drain_stores();
       lds_barrier();
-      const uint32_t target = epoch + (uint32_t)j + 1u;
-      if (wave == 0) {
-        if (lane == 0) __hip_atomic_store(&ws->flags[g], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (!s_broken) {
-          long spins = 0;
-          for (;;) {
-            bool ok = true;
-            for (int q = lane; q < G; q += 64)
-              ok &= __hip_atomic_load(&ws->flags[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
-            if (__all(ok)) break;
-            if (++spins > kSpinLimit) {
-              if (lane == 0) {
-                __hip_atomic_store(&ws->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                s_broken = 1;
+      // 2. the workgroup's candidate (every thread, the same order)
+      double bv = s_wv[par][0];
+      uint32_t bi = s_wi[par][0];
+      int bw = 0;
+#pragma unroll
+      for (int q = 1; q < NW; ++q) {
+        const double v = s_wv[par][q];
+        const uint32_t ii = s_wi[par][q];
+        if (v > bv || (v == bv && ii < bi)) {
+          bv = v;
+          bi = ii;
+          bw = q;
+        }
+      }
+      const T* prow;
+      uint32_t pu;
+      if (G == 1) {
+        prow = s_wrow[par][bw];
+        pu = bi;
+      } else {
+        // one wavefront publishes this workgroup's tagged record (and, in
+        // workgroup 0, row j), then reads every workgroup's record until all
+        // tags are current: one round trip in the common case
+        if (wave == 0) {
+          const uint32_t tag = epoch + (uint32_t)j + 1u;
+          const uint64_t th = (uint64_t)tag << 32;
+          if (lane < kLeafRecWords) {
+            uint32_t pay;
+            if (lane < 2) {
+              const uint64_t vb = (uint64_t)__double_as_longlong(bv);
+              pay = lane == 0 ? (uint32_t)(vb >> 32) : (uint32_t)vb;
+            } else if (lane == 2) {
+              pay = bi;
+            } else {
+              const int e = lane - 3;
+              const uint64_t db = (uint64_t)__double_as_longlong((double)s_wrow[par][bw][e >> 1]);
+              pay = (e & 1) ? (uint32_t)db : (uint32_t)(db >> 32);
+            }
+            st_u64(&ws->rec[par][g][lane], th | pay);
+          }
+          if (g == 0 && lane < 2 * W) {
+            const uint64_t db = (uint64_t)__double_as_longlong((double)s_rowj[par][lane >> 1]);
+            st_u64(&ws->rowj[par][lane], th | ((lane & 1) ? (uint32_t)db : (uint32_t)(db >> 32)));
+          }
+          // (a) the G headers (|a| and row) until every tag is current
+          const int nhead = 3 * G;
+          if (!s_broken) {
+            long spins = 0;
+            for (;;) {
+              bool ok = true;
+              for (int e = lane; e < nhead; e += 64) {
+                const uint64_t v = ld_u64(&ws->rec[par][e / 3][e % 3]);
+                ok &= (uint32_t)(v >> 32) == tag;
+                s_words[e] = (uint32_t)v;
               }
-              break;
+              if (__all(ok)) break;
+              if (++spins > kSpinLimit) {
+                if (lane == 0) {
+                  __hip_atomic_store(&ws->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                  s_broken = 1;
+                }
+                break;
+              }
             }
           }
-        }
-      }
-      lds_barrier();
-      // one round trip: every candidate, every candidate row, row j
-      for (int q = tid; q < G; q += NT) {
-        s_cv[q] = ld_f64(&ws->cand_val[par][q]);
-        s_ci[q] = (int64_t)ld_u64(&ws->cand_idx[par][q]);
-      }
-      for (int e = tid; e < G * W; e += NT) s_crow[e] = ld_f64(&ws->cand_row[par][e / W][e % W]);
-      if (tid < W) s_rowj[tid] = (T)ld_f64(&ws->rowj[par][tid]);
-      lds_barrier();
-      if (wave == 0) {
-        double v = -1.0;
-        int64_t i = INT64_MAX;
-        for (int q = lane; q < G; q += 64) {
-          if (better(s_cv[q], s_ci[q], v, i)) {
-            v = s_cv[q];
-            i = s_ci[q];
+          double cv = -1.0;
+          uint32_t ci = kNone;
+          for (int q = lane; q < G; q += 64) {
+            const uint32_t* wq = &s_words[3 * q];
+            const double v = __longlong_as_double((long long)(((uint64_t)wq[0] << 32) | wq[1]));
+            const uint32_t ii = wq[2];
+            if (v > cv || (v == cv && ii < ci)) {
+              cv = v;
+              ci = ii;
+            }
           }
+          const double gm = wave_max_f64(cv);
+          const uint32_t gi = wave_min_u32((cv == gm) ? ci : kNone);
+          // the winning row identifies its workgroup
+          const int gw = (gi == kNone) ? 0 : (int)((int64_t)gi / ((int64_t)NT * RPT));
+          // (b) the winner's row and (outside workgroup 0) row j, tag-checked
+          const bool need = lane < 2 * W || (g != 0 && lane < 4 * W);
+          uint64_t rv = 0;
+          if (!s_broken) {
+            long spins = 0;
+            for (;;) {
+              bool ok = true;
+              if (need) {
+                rv = (lane < 2 * W) ? ld_u64(&ws->rec[par][gw][3 + lane]) : ld_u64(&ws->rowj[par][lane - 2 * W]);
+                ok = (uint32_t)(rv >> 32) == tag;
+              }
+              if (__all(ok)) break;
+              if (++spins > kSpinLimit) {
+                if (lane == 0) {
+                  __hip_atomic_store(&ws->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                  s_broken = 1;
+                }
+                break;
+              }
+            }
+          }
+          // two 32-bit halves per value: even lane high, odd lane low
+          const uint32_t lo = (uint32_t)__shfl_down((int)(uint32_t)rv, 1, 64);
+          if (need && (lane & 1) == 0) {
+            const double d = __longlong_as_double((long long)(((uint64_t)(uint32_t)rv << 32) | lo));
+            if (lane < 2 * W) s_prow[par][lane >> 1] = (T)d;
+            else s_rowj[par][(lane - 2 * W) >> 1] = (T)d;
+          }
+          if (lane == 0) s_bi[par] = gi;
         }
-        wave_argmax(v, i);
-        // the winning row index identifies its workgroup
-        const int gw = (i == INT64_MAX) ? 0 : (int)(i / ((int64_t)NT * RPT));
-        if (lane < W) s_prow[lane] = (T)s_crow[gw * W + lane];
-        if (lane == 0) s_bi = i;
+        lds_barrier();
+        prow = s_prow[par];
+        pu = s_bi[par];
       }
-      lds_barrier();
-      gbest = s_bi;
-    }
 
-    // 3. interchange, scale, update (a winner outside the block can only come
-    // from NaN input: keep the diagonal row then)
-    int64_t piv = gbest;
-    if (piv < j || piv >= r) piv = j;
-    const T pv = s_prow[j];
-    if (tid == 0) {
-      s_ipiv[j] = (int32_t)(k + piv + 1);
-      if (pv == T(0) && s_zero == 0) s_zero = (int32_t)(k + j + 1);
-    }
-    // the same interchange on the other columns of the enclosing block:
-    // stores of the previous step, loads of this one
-    if (pend) {
+      // 3. interchange, scale, update (a winner outside the block can only
+      // come from NaN input: keep the diagonal row then)
+      int64_t piv = (int64_t)pu;
+      if (pu == kNone || piv < j || piv >= r) piv = j;
+      const T pv = prow[j];
+      if (tid == 0) {
+        s_ipiv[j] = (int32_t)(k + piv + 1);
+        if (pv == T(0) && s_zero == 0) s_zero = (int32_t)(k + j + 1);
+      }
+      // the same interchange on the other columns of the enclosing block:
+      // stores of the previous step, loads of this one
+      if (pend) {
 #pragma unroll
-      for (int u = 0; u < kMaxOther; ++u)
-        if (own[u]) {
-          ocol[u][prj] = pvp[u];
-          ocol[u][prp] = pvj[u];
-        }
-      pend = false;
-    }
-    if (piv != j && pv != T(0)) {
+        for (int u = 0; u < kMaxOther; ++u)
+          if (own[u]) {
+            ocol[u][prj] = pvp[u];
+            ocol[u][prp] = pvj[u];
+          }
+        pend = false;
+      }
+      if (piv != j && pv != T(0)) {
 #pragma unroll
-      for (int u = 0; u < kMaxOther; ++u)
-        if (own[u]) {
-          pvj[u] = ocol[u][j];
-          pvp[u] = ocol[u][piv];
-        }
-      pend = true;
-      prj = j;
-      prp = piv;
-    }
-    if (pv != T(0)) {
+        for (int u = 0; u < kMaxOther; ++u)
+          if (own[u]) {
+            pvj[u] = ocol[u][j];
+            pvp[u] = ocol[u][piv];
+          }
+        pend = true;
+        prj = j;
+        prp = piv;
+      }
+      if (pv != T(0)) {
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int64_t i = rbase + q * NT + tid;
-        if (i == piv && piv != j) {
+        for (int q = 0; q < RPT; ++q) {
+          const int64_t i = rbase + q * NT + tid;
+          if (i == piv && piv != j) {
 #pragma unroll
-          for (int c = 0; c < W; ++c) a[q][c] = s_rowj[c];
-        } else if (i == j) {
+            for (int c = 0; c < W; ++c) a[q][c] = s_rowj[par][c];
+          } else if (i == j) {
 #pragma unroll
-          for (int c = 0; c < W; ++c) a[q][c] = s_prow[c];
-        }
-        if (i > j && i < r) {
-          T x = T(0);
+            for (int c = 0; c < W; ++c) a[q][c] = prow[c];
+          }
+          if (i > j && i < r) {
+            const T l = a[q][j] / pv;
+            a[q][j] = l;
 #pragma unroll
-          for (int c = 0; c < W; ++c)
-            if (c == j) x = a[q][c];
-          const T l = x / pv;
-#pragma unroll
-          for (int c = 0; c < W; ++c) {
-            if (c == j) a[q][c] = l;
-            if (c > j) a[q][c] = a[q][c] - l * s_prow[c];
+            for (int c = 0; c < W; ++c)
+              if (c > j) a[q][c] = a[q][c] - l * prow[c];
           }
         }
       }
-    }
-    // s_prow/s_rowj are rewritten only after the next column's first barrier,
-    // which every wave reaches after finishing this column
     }
   }
 
@@ -326,8 +345,13 @@ __global__ __launch_bounds__(NT) void k_panel_leaf(int64_t r, int w, T* __restri
   }
 }
 
+// clears every tag (tag 0 is never issued), so records left from before an
+// epoch wrap-around cannot match a new tag
 __global__ void k_reset_flags(LeafSlots* ws) {
   for (int i = threadIdx.x; i < kLeafMaxGroups; i += blockDim.x) ws->flags[i] = 0;
+  uint64_t* rec = &ws->rec[0][0][0];
+  for (int i = threadIdx.x; i < 2 * kLeafMaxGroups * kLeafRecStride; i += blockDim.x) rec[i] = 0;
+  for (int i = threadIdx.x; i < 4 * kLeafMaxWidth; i += blockDim.x) (&ws->rowj[0][0])[i] = 0;
 }
 
 template <typename T, int W, int RPT, int NT>
