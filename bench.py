@@ -217,6 +217,7 @@ def main():
     ap.add_argument("--n", type=int, default=32768)
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--nb", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0, help="widest cooperative column block (multiple of 16)")
     ap.add_argument("--seed", type=int, default=20210513)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
@@ -275,6 +276,8 @@ def main():
     h = lupp.Handle()
     if args.nb:
         h.set_option(1, args.nb)
+    if args.block:
+        h.set_option(2, args.block)
     if args.no_lookahead:
         h.set_option(4, 0)
     fn = lupp.lupp_dgetrf if args.dtype == "f64" else lupp.lupp_sgetrf

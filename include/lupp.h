@@ -53,8 +53,9 @@ enum {
 /* Options for lupp_set_option. */
 enum {
   LUPP_OPT_NB = 1,         /* outer block size b of the right-looking loop (default 256)  */
-  LUPP_OPT_PANEL_LEAF = 2, /* column width at which the recursive panel stops (8 or 16;
-                              default 16)                                                 */
+  LUPP_OPT_PANEL_LEAF = 2, /* widest column block factored in one cooperative launch
+                              (16 .. 256, a multiple of 16; default 128); wider blocks
+                              split recursively with a triangular solve and a GEMM      */
   LUPP_OPT_TIMING = 3,     /* 1: record HIP events around every phase of xGETRF (below)    */
   LUPP_OPT_LOOKAHEAD = 4,  /* 1 (default): factor the next column block on a second stream
                               while the trailing update runs; 0: one stream, in order      */

@@ -50,9 +50,10 @@ constexpr int kLeafRecWords = 3 + 2 * kLeafMaxWidth;  // 35 used
 constexpr int kLeafRecStride = 36;
 
 struct LeafSlots {
-  uint32_t flags[kLeafMaxGroups];  // unused by the tagged exchange; kept zero
+  uint32_t flags[kLeafMaxGroups];  // per-workgroup barrier tags of the column-block kernel
   int32_t err;                     // set when a bounded wait expires
-  int32_t pad_[31];
+  uint32_t uflag;                  // tag: workgroup 0 has published a chunk's U12 rows
+  int32_t pad_[30];
   uint64_t rec[2][kLeafMaxGroups][kLeafRecStride];  // candidate records, by column parity
   uint64_t rowj[2][2 * kLeafMaxWidth];              // the diagonal row before the interchange
 };
@@ -77,17 +78,20 @@ template <typename T>
 hipError_t gemm_sub(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda,
                     const T* B, int64_t ldb, T* C, int64_t ldc, int* tile_out = nullptr);
 
-// Factor the r x w column block P (leading dimension ld) whose first row and
-// column are the global row/column k: partial pivoting column by column, the
-// interchanges applied across the w columns of the block and also to the
-// columns P[:, c] for c in [oc_lo, 0) and [w, oc_hi) (the rest of the
-// enclosing column block).  Writes ipiv[k + j] = k + piv + 1 and, on the first
-// exactly zero pivot, *info.
+// Factor the r x w column block P (leading dimension ld, w <= kBlockMaxWidth,
+// r >= w) whose first row and column are the global row/column k: partial
+// pivoting column by column in one cooperative launch, the interchanges
+// applied across the w columns of the block and also to the columns P[:, c]
+// for c in [oc_lo, 0) and [w, oc_hi) (the rest of the enclosing column
+// block).  Writes ipiv[k + j] = k + piv + 1 and, on the first exactly zero
+// pivot, *info.  Uses block_tags(w) consecutive tags from epoch.
+constexpr int kBlockMaxWidth = 256;
 template <typename T>
-hipError_t panel_leaf(hipStream_t s, int64_t r, int w, T* P, int64_t ld, int32_t* ipiv, int64_t k,
-                      int32_t* info, LeafSlots* ws, uint32_t epoch, int64_t oc_lo, int64_t oc_hi);
+hipError_t panel_block(hipStream_t s, int64_t r, int w, T* P, int64_t ld, int32_t* ipiv, int64_t k,
+                       int32_t* info, LeafSlots* ws, uint32_t epoch, int64_t oc_lo, int64_t oc_hi);
+uint32_t block_tags(int w);
 
-// Number of cooperating workgroups panel_leaf uses for r rows.
+// Number of cooperating workgroups panel_block uses for r rows.
 int panel_groups(int64_t r);
 
 // Triangular solve, one thread per right-hand column kept in registers

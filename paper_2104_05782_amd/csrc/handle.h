@@ -20,7 +20,7 @@ struct lupp_handle_st {
   int device = 0;
   hipStream_t stream = nullptr;
   int64_t nb = 256;
-  int leaf = 16;
+  int block = 128;                  // widest column block factored in one cooperative launch
   lupp::LeafSlots* slots = nullptr;
   lupp::SwapPairs* pairs = nullptr;
   uint32_t epoch = 0;

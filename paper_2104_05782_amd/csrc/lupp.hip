@@ -86,24 +86,24 @@ hipError_t trsm_upper(hipStream_t s, int64_t w, int64_t ncols, const T* U, int64
   return trsm_upper<T>(s, w1, ncols, U, ldu, B, ldb);
 }
 
-// Recursive column-block factorization of columns [k, k+w), rows [k, m),
-// inside the enclosing column block [p0, p1): the leaves apply their
-// interchanges to every column of [p0, p1), so the recursion itself moves no
-// rows.  Split: factor the left half; U12 := inv(L11) * A12; A22 -= A21 * U12;
-// factor the right half (which also interchanges rows of the left half).
+// Column-block factorization of columns [k, k+w), rows [k, m), inside the
+// enclosing column block [p0, p1): blocks up to h->block columns wide are one
+// cooperative launch that also applies its interchanges to every other column
+// of [p0, p1); wider blocks split in two (left half; U12 := inv(L11) * A12;
+// A22 -= A21 * U12; right half, which also interchanges rows of the left).
 template <typename T>
 hipError_t panel(lupp_handle_t h, hipStream_t s, int64_t m, int64_t k, int64_t w, int64_t p0, int64_t p1, T* A,
                  int64_t lda, int32_t* ipiv, int32_t* info) {
-  if (w <= h->leaf) {
+  if (w <= h->block) {
     uint32_t ep;
-    LUPP_TRY(next_epoch(h, s, (int)w, &ep));
+    LUPP_TRY(next_epoch(h, s, (int)block_tags((int)w), &ep));
     const int t = timer_begin(h, LUPP_PHASE_PANEL_LEAF, s);
-    LUPP_TRY(panel_leaf<T>(s, m - k, (int)w, A + k + k * lda, lda, ipiv, k, info, h->slots, ep, p0 - k, p1 - k));
+    LUPP_TRY(panel_block<T>(s, m - k, (int)w, A + k + k * lda, lda, ipiv, k, info, h->slots, ep, p0 - k, p1 - k));
     timer_end(h, t, s, 0.0);
     return hipSuccess;
   }
   int64_t w1 = w / 2;
-  if (w1 > 8) w1 = (w1 / 8) * 8;
+  if (w1 > 16) w1 = (w1 / 16) * 16;
   const int64_t w2 = w - w1;
   LUPP_TRY(panel<T>(h, s, m, k, w1, p0, p1, A, lda, ipiv, info));
   int t = timer_begin(h, LUPP_PHASE_PANEL_TRSM, s);
@@ -333,7 +333,7 @@ int getrf_entry(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32_
   if (lda < (m > 1 ? m : 1)) return -5;
   if (!ipiv && m > 0 && n > 0) return -6;
   if (!info) return -7;
-  if (m - 0 > (int64_t)kLeafMaxGroups * 256 * 4) return LUPP_ERR_UNSUPPORTED;
+  if (m > (int64_t)kLeafMaxGroups * 1024) return LUPP_ERR_UNSUPPORTED;
   hipError_t e = ensure_workspace(h);
   if (e != hipSuccess) return LUPP_ERR_ALLOC;
   if (std::is_same<T, float>::value && h->update_prec != LUPP_PREC_FP32) {
@@ -419,8 +419,8 @@ int lupp_set_option(lupp_handle_t h, int option, int64_t value) {
       h->nb = value;
       return LUPP_OK;
     case LUPP_OPT_PANEL_LEAF:
-      if (value != 8 && value != 16) return -3;
-      h->leaf = (int)value;
+      if (value < 16 || value > lupp::kBlockMaxWidth || value % 16 != 0) return -3;
+      h->block = (int)value;
       return LUPP_OK;
     case LUPP_OPT_TIMING:
       if (value != 0 && value != 1) return -3;

@@ -427,7 +427,7 @@ void lupp_ir_opts_default(lupp_ir_opts* o, int32_t solver) {
 int lupp_dgesv_mixed(lupp_handle_t h, int64_t n, int64_t nrhs, const double* dA, int64_t lda, const double* dB,
                      int64_t ldb, double* dX, int64_t ldx, const lupp_ir_opts* opts, lupp_ir_report* rep) {
   if (!h) return -1;
-  if (n < 0 || n > (int64_t)lupp::kLeafMaxGroups * 256 * 4) return -2;
+  if (n < 0 || n > (int64_t)lupp::kLeafMaxGroups * 1024) return -2;
   if (nrhs < 0) return -3;
   if (!dA && n > 0) return -4;
   if (lda < (n > 1 ? n : 1)) return -5;

@@ -1,29 +1,34 @@
-// Column-block ("panel") factorization with partial pivoting: the leaf of the
-// recursive panel.  The paper singles this step out as the one that limits a
-// blocked LU: it works on few data and every other step waits for it
-// (Section 4.1).  Its latency is a chain of w dependent pivot decisions, each
-// a reduction over all r rows of the block.
+// Column-block ("panel") factorization with partial pivoting.  The paper
+// singles this step out as the one that limits a blocked LU: it works on few
+// data and every other step waits for it (Section 4.1).  Its latency is a
+// chain of w dependent pivot decisions, each a reduction over all r rows.
 //
-// Design (gfx950): G workgroups split the r rows; every thread keeps RPT rows
-// x W columns of the block in registers for the whole call, so the rank-1
-// updates never touch memory.  Per column j:
-//   1. each thread scans its rows; wavefront shuffles and an LDS step reduce
-//      to the workgroup's best (|a|, row) under the total order (|a| desc, row
-//      asc), so any reduction tree reproduces the sequential first-maximum
-//      scan;
-//   2. with G > 1 each workgroup publishes its candidate, the candidate's row
-//      (and, from the owner of row j, row j) as 64-bit device-coherent words
-//      that each carry the column's tag -- no store fence, no separate flag.
-//      One wavefront polls the G three-word headers (|a|, row) until all tags
-//      are current, picks the winner, then reads the winner's row and row j
-//      (tag-checked): two light round trips;
-//   3. interchange (the two owning threads exchange whole rows), true-division
-//      scaling of column j, rank-1 update of the remaining columns.
-// The same interchange is applied to the other columns of the enclosing
-// column block by threads that own one such column each; a step's loads are
-// issued as soon as the pivot is known and its stores in the next step, so
-// their latency hides behind the next pivot search.
-// Wait loops are bounded: an expired wait sets ws->err and the kernel finishes.
+// Design (gfx950): one cooperative launch factors a column block of up to 256
+// columns.  G workgroups of 1024 threads split the r rows, one row per thread.
+// The block is processed in chunks of 16 columns, left-looking:
+//   0. a grid barrier (per-workgroup tags) makes the previous chunk's stores
+//      visible everywhere;
+//   1. every thread loads its row of the chunk into registers;
+//   2. workgroup 0 forward-substitutes the chunk's rows above the diagonal
+//      (U12 := inv(L11) A12, one row per step) and publishes them; every
+//      workgroup then updates its rows below with the finished columns
+//      (A22 -= L21 U12), streaming L21 with four loads in flight per thread;
+//   3. the chunk is factored column by column with the rows in registers:
+//      each wavefront reduces its candidates exactly (largest |a|, then the
+//      lowest row, two DPP reductions); within a workgroup one barrier per
+//      column; across workgroups each publishes a record of 64-bit
+//      device-coherent words that carry the column's tag, and one wavefront
+//      polls the G three-word headers (|a|, row) until every tag is current,
+//      picks the winner, then reads the winner's row and row j (tag-checked);
+//      interchange, true-division scaling and the rank-1 update of the
+//      chunk follow in registers;
+//   4. the chunk is written back.
+// Each interchange is also applied to the other columns of the block and of
+// the enclosing column block by threads that own one such column each; a
+// step's loads are issued as soon as the pivot is known and its stores in
+// the next step.  All accesses that another workgroup may read within the
+// launch bypass the non-coherent caches (agent scope).  Waits are bounded: an
+// expired wait sets ws->err and the kernel finishes.
 #include "common.h"
 #include "wave.h"
 
@@ -31,7 +36,7 @@ namespace lupp {
 namespace {
 
 constexpr long kSpinLimit = 1L << 22;
-constexpr int kMaxOther = 4;  // other columns per thread
+constexpr int kMaxOther = 1;  // other columns per thread (enclosing block <= 1024 columns <= threads)
 
 __device__ __forceinline__ bool better(double v, int64_t i, double bv, int64_t bi) {
   return v > bv || (v == bv && i < bi);
@@ -45,6 +50,33 @@ __device__ __forceinline__ uint64_t ld_u64(const void* p) {
 }
 __device__ __forceinline__ void st_f64(double* p, double v) { st_u64(p, __double_as_longlong(v)); }
 __device__ __forceinline__ double ld_f64(const double* p) { return __longlong_as_double(ld_u64(p)); }
+__device__ __forceinline__ void st_u32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_u32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// element loads and stores that bypass the non-coherent caches
+template <typename T>
+__device__ __forceinline__ T ldc(const T* p);
+template <>
+__device__ __forceinline__ double ldc<double>(const double* p) { return ld_f64(p); }
+template <>
+__device__ __forceinline__ float ldc<float>(const float* p) { return __uint_as_float(ld_u32((const uint32_t*)p)); }
+template <typename T>
+__device__ __forceinline__ void stc(T* p, T v);
+template <>
+__device__ __forceinline__ void stc<double>(double* p, double v) { st_f64(p, v); }
+template <>
+__device__ __forceinline__ void stc<float>(float* p, float v) { st_u32((uint32_t*)p, __float_as_uint(v)); }
+
+// wait until this thread's stores have completed at the coherence point
+__device__ __forceinline__ void release_stores() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
 
 // Workgroup barrier that waits only for LDS traffic.  (__syncthreads also
@@ -58,17 +90,20 @@ __device__ __forceinline__ void lds_barrier() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-template <typename T, int W, int RPT, int NT>
-__global__ __launch_bounds__(NT) void k_panel_leaf(int64_t r, int w, T* __restrict__ P, int64_t ld,
-                                                   int32_t* __restrict__ ipiv, int64_t k,
-                                                   int32_t* __restrict__ info, LeafSlots* __restrict__ ws,
-                                                   uint32_t epoch, int64_t oc_lo, int64_t oc_hi) {
-  static_assert(W <= kLeafMaxWidth, "leaf wider than the exchange records");
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_panel_block(int64_t r, int wt, T* __restrict__ P, int64_t ld,
+                                                    int32_t* __restrict__ ipiv, int64_t k,
+                                                    int32_t* __restrict__ info, LeafSlots* __restrict__ ws,
+                                                    uint32_t epoch, int64_t oc_lo, int64_t oc_hi) {
+  constexpr int W = 16;  // chunk width
+  static_assert(W <= kLeafMaxWidth, "chunk wider than the exchange records");
   constexpr int NW = NT / 64;
+  constexpr int PF = 4;  // L loads in flight per thread in the left-looking update
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = blockIdx.x, G = gridDim.x;
-  const int64_t rbase = (int64_t)g * NT * RPT;
+  const int i = g * NT + tid;  // this thread's row (block-relative; r < 2^31)
+  const bool rok = i < r;
 
   // double-buffered by column parity: a buffer written for column j is read
   // only before the first barrier of column j + 1
@@ -79,32 +114,10 @@ __global__ __launch_bounds__(NT) void k_panel_leaf(int64_t r, int w, T* __restri
   __shared__ uint32_t s_wi[2][NW];
   __shared__ uint32_t s_bi[2];
   __shared__ int s_broken;
-  __shared__ int32_t s_ipiv[W];
+  __shared__ int32_t s_ipiv[kBlockMaxWidth];
   __shared__ int32_t s_zero;
   __shared__ uint32_t s_words[3 * kLeafMaxGroups];
-
-  T a[RPT][W];
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int64_t i = rbase + q * NT + tid;
-#pragma unroll
-    for (int c = 0; c < W; ++c) a[q][c] = (i < r && c < w) ? P[i + c * ld] : T(0);
-  }
-  // other columns of the enclosing block owned by this thread
-  const int64_t n_left = -oc_lo, n_other = n_left + (oc_hi - w);
-  const int64_t gt = (int64_t)g * NT + tid, gstride = (int64_t)G * NT;
-  T* ocol[kMaxOther];
-  bool own[kMaxOther];
-#pragma unroll
-  for (int u = 0; u < kMaxOther; ++u) {
-    const int64_t q = gt + u * gstride;
-    own[u] = q < n_other;
-    const int64_t c = (q < n_left) ? (oc_lo + q) : (w + (q - n_left));
-    ocol[u] = P + (own[u] ? c : 0) * ld;
-  }
-  bool pend = false;
-  int64_t prj = 0, prp = 0;
-  T pvj[kMaxOther], pvp[kMaxOther];
+  __shared__ T s_u[kBlockMaxWidth][W];  // the chunk's rows above the diagonal
 
   if (tid == 0) {
     s_broken = 0;
@@ -112,236 +125,355 @@ __global__ __launch_bounds__(NT) void k_panel_leaf(int64_t r, int w, T* __restri
   }
   __syncthreads();
 
-  // fully unrolled over the W columns: every register index below is a
-  // compile-time constant (no select chains over the row's registers)
-#pragma clang loop unroll(full)
-  for (int j = 0; j < W; ++j) {
-    if (j < w) {
-      const int par = j & 1;
-      // 1. this thread's candidate: the first maximal |a| among its rows >= j
-      //    (its rows increase with q), then the wavefront's, exactly: the
-      //    largest |a|, then the lowest row holding it
-      double lv = -1.0;
-      uint32_t li = kNone;
-#pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int64_t i = rbase + q * NT + tid;
-        const double v = fabs((double)a[q][j]);
-        if (i >= j && i < r && v > lv) {
-          lv = v;
-          li = (uint32_t)i;
+  // every workgroup waits until all workgroups have reached this point with
+  // their stores completed
+  auto grid_barrier = [&](uint32_t tag) {
+    release_stores();
+    __syncthreads();
+    if (wave == 0) {
+      if (lane == 0) st_u32(&ws->flags[g], tag);
+      if (!s_broken) {
+        long spins = 0;
+        for (;;) {
+          bool ok = true;
+          for (int q = lane; q < G; q += 64) ok &= ld_u32(&ws->flags[q]) >= tag;
+          if (__all(ok)) break;
+          if (++spins > kSpinLimit) {
+            if (lane == 0) {
+              __hip_atomic_store(&ws->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              s_broken = 1;
+            }
+            break;
+          }
         }
       }
-      const double wm = wave_max_f64(lv);
-      const uint32_t wi = wave_min_u32((lv == wm) ? li : kNone);
-      // the wavefront's candidate row and row j go to LDS with the candidate
+    }
+    __syncthreads();
+  };
+
+  const int nch = (wt + W - 1) / W;
+  for (int ch = 0; ch < nch; ++ch) {
+    const int c0 = ch * W;
+    const int cw = (wt - c0 < W) ? (wt - c0) : W;
+    const uint32_t tbase = epoch + 1u + (uint32_t)ch * (W + 2);
+    // ---- 0. the previous chunk's stores are visible to every workgroup
+    if (ch > 0) grid_barrier(tbase + W);
+    // ---- 1. this thread's row of the chunk
+    T a[W];
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int64_t i = rbase + q * NT + tid;
-        if (i == (int64_t)wi) {
+    for (int c = 0; c < W; ++c) a[c] = (rok && c < cw) ? ldc(P + i + (int64_t)(c0 + c) * ld) : T(0);
+
+    // ---- 2. left-looking update with the finished columns 0 .. c0-1
+    if (c0 > 0) {
+      if (g == 0) {
+        // rows 0 .. c0-1: U12 = inv(L11) A12, one row per step; row p is
+        // final when its turn comes and is broadcast through LDS
+        T lr[PF];
 #pragma unroll
-          for (int c = 0; c < W; ++c) s_wrow[par][wave][c] = a[q][c];
+        for (int u = 0; u < PF; ++u) lr[u] = (tid < c0 && u < c0) ? ldc(P + tid + (int64_t)u * ld) : T(0);
+        for (int pb = 0; pb < c0; pb += PF) {
+          T cur[PF];
+#pragma unroll
+          for (int u = 0; u < PF; ++u) cur[u] = lr[u];
+#pragma unroll
+          for (int u = 0; u < PF; ++u) {
+            const int p = pb + PF + u;
+            lr[u] = (tid < c0 && p < c0) ? ldc(P + tid + (int64_t)p * ld) : T(0);
+          }
+#pragma unroll
+          for (int u = 0; u < PF; ++u) {
+            const int p = pb + u;
+            if (p < c0) {
+              if (tid == p) {
+#pragma unroll
+                for (int c = 0; c < W; ++c) s_u[p][c] = a[c];
+              }
+              lds_barrier();
+              if (tid > p && tid < c0) {
+#pragma unroll
+                for (int c = 0; c < W; ++c) a[c] = a[c] - cur[u] * s_u[p][c];
+              }
+            }
+          }
         }
-        if (i == j) {
+        // publish U12 for the other workgroups
+        if (tid < c0) {
 #pragma unroll
-          for (int c = 0; c < W; ++c) s_rowj[par][c] = a[q][c];
+          for (int c = 0; c < W; ++c)
+            if (c < cw) stc(P + tid + (int64_t)(c0 + c) * ld, a[c]);
         }
-      }
-      if (lane == 0) {
-        s_wv[par][wave] = wm;
-        s_wi[par][wave] = wi;
-      }
-      lds_barrier();
-      // 2. the workgroup's candidate (every thread, the same order)
-      double bv = s_wv[par][0];
-      uint32_t bi = s_wi[par][0];
-      int bw = 0;
-#pragma unroll
-      for (int q = 1; q < NW; ++q) {
-        const double v = s_wv[par][q];
-        const uint32_t ii = s_wi[par][q];
-        if (v > bv || (v == bv && ii < bi)) {
-          bv = v;
-          bi = ii;
-          bw = q;
-        }
-      }
-      const T* prow;
-      uint32_t pu;
-      if (G == 1) {
-        prow = s_wrow[par][bw];
-        pu = bi;
+        release_stores();
+        __syncthreads();
+        if (tid == 0) st_u32(&ws->uflag, tbase + W + 1);
       } else {
-        // one wavefront publishes this workgroup's tagged record (and, in
-        // workgroup 0, row j), then reads every workgroup's record until all
-        // tags are current: one round trip in the common case
-        if (wave == 0) {
-          const uint32_t tag = epoch + (uint32_t)j + 1u;
-          const uint64_t th = (uint64_t)tag << 32;
-          if (lane < kLeafRecWords) {
-            uint32_t pay;
-            if (lane < 2) {
-              const uint64_t vb = (uint64_t)__double_as_longlong(bv);
-              pay = lane == 0 ? (uint32_t)(vb >> 32) : (uint32_t)vb;
-            } else if (lane == 2) {
-              pay = bi;
-            } else {
-              const int e = lane - 3;
-              const uint64_t db = (uint64_t)__double_as_longlong((double)s_wrow[par][bw][e >> 1]);
-              pay = (e & 1) ? (uint32_t)db : (uint32_t)(db >> 32);
-            }
-            st_u64(&ws->rec[par][g][lane], th | pay);
-          }
-          if (g == 0 && lane < 2 * W) {
-            const uint64_t db = (uint64_t)__double_as_longlong((double)s_rowj[par][lane >> 1]);
-            st_u64(&ws->rowj[par][lane], th | ((lane & 1) ? (uint32_t)db : (uint32_t)(db >> 32)));
-          }
-          // (a) the G headers (|a| and row) until every tag is current
-          const int nhead = 3 * G;
-          if (!s_broken) {
-            long spins = 0;
-            for (;;) {
-              bool ok = true;
-              for (int e = lane; e < nhead; e += 64) {
-                const uint64_t v = ld_u64(&ws->rec[par][e / 3][e % 3]);
-                ok &= (uint32_t)(v >> 32) == tag;
-                s_words[e] = (uint32_t)v;
+        if (wave == 0 && !s_broken) {
+          long spins = 0;
+          for (;;) {
+            const bool ok = ld_u32(&ws->uflag) >= tbase + W + 1;
+            if (__all(ok)) break;
+            if (++spins > kSpinLimit) {
+              if (lane == 0) {
+                __hip_atomic_store(&ws->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_broken = 1;
               }
-              if (__all(ok)) break;
-              if (++spins > kSpinLimit) {
-                if (lane == 0) {
-                  __hip_atomic_store(&ws->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                  s_broken = 1;
-                }
-                break;
-              }
+              break;
             }
           }
-          double cv = -1.0;
-          uint32_t ci = kNone;
-          for (int q = lane; q < G; q += 64) {
-            const uint32_t* wq = &s_words[3 * q];
-            const double v = __longlong_as_double((long long)(((uint64_t)wq[0] << 32) | wq[1]));
-            const uint32_t ii = wq[2];
-            if (v > cv || (v == cv && ii < ci)) {
-              cv = v;
-              ci = ii;
+        }
+        __syncthreads();
+        for (int e = tid; e < c0 * W; e += NT) {
+          const int pr = e / W, c = e % W;
+          s_u[pr][c] = (c < cw) ? ldc(P + pr + (int64_t)(c0 + c) * ld) : T(0);
+        }
+        __syncthreads();
+      }
+      // rows c0 .. r-1: A22 -= L21 U12
+      if (rok && i >= c0) {
+        T lr[PF];
+#pragma unroll
+        for (int u = 0; u < PF; ++u) lr[u] = (u < c0) ? ldc(P + i + (int64_t)u * ld) : T(0);
+        for (int pb = 0; pb < c0; pb += PF) {
+          T cur[PF];
+#pragma unroll
+          for (int u = 0; u < PF; ++u) cur[u] = lr[u];
+#pragma unroll
+          for (int u = 0; u < PF; ++u) {
+            const int p = pb + PF + u;
+            lr[u] = (p < c0) ? ldc(P + i + (int64_t)p * ld) : T(0);
+          }
+#pragma unroll
+          for (int u = 0; u < PF; ++u) {
+            const int p = pb + u;
+            if (p < c0) {
+#pragma unroll
+              for (int c = 0; c < W; ++c) a[c] = a[c] - cur[u] * s_u[p][c];
             }
           }
-          const double gm = wave_max_f64(cv);
-          const uint32_t gi = wave_min_u32((cv == gm) ? ci : kNone);
-          // the winning row identifies its workgroup
-          const int gw = (gi == kNone) ? 0 : (int)((int64_t)gi / ((int64_t)NT * RPT));
-          // (b) the winner's row and (outside workgroup 0) row j, tag-checked
-          const bool need = lane < 2 * W || (g != 0 && lane < 4 * W);
-          uint64_t rv = 0;
-          if (!s_broken) {
-            long spins = 0;
-            for (;;) {
-              bool ok = true;
-              if (need) {
-                rv = (lane < 2 * W) ? ld_u64(&ws->rec[par][gw][3 + lane]) : ld_u64(&ws->rowj[par][lane - 2 * W]);
-                ok = (uint32_t)(rv >> 32) == tag;
-              }
-              if (__all(ok)) break;
-              if (++spins > kSpinLimit) {
-                if (lane == 0) {
-                  __hip_atomic_store(&ws->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                  s_broken = 1;
-                }
-                break;
-              }
-            }
-          }
-          // two 32-bit halves per value: even lane high, odd lane low
-          const uint32_t lo = (uint32_t)__shfl_down((int)(uint32_t)rv, 1, 64);
-          if (need && (lane & 1) == 0) {
-            const double d = __longlong_as_double((long long)(((uint64_t)(uint32_t)rv << 32) | lo));
-            if (lane < 2 * W) s_prow[par][lane >> 1] = (T)d;
-            else s_rowj[par][(lane - 2 * W) >> 1] = (T)d;
-          }
-          if (lane == 0) s_bi[par] = gi;
+        }
+      }
+    }
+
+    // ---- 3. the chunk's columns, one pivot at a time
+    // other columns of the enclosing block owned by this thread: [oc_lo, c0)
+    // and [c0 + cw, oc_hi), relative to P
+    const int64_t n_left = (int64_t)c0 - oc_lo, n_other = n_left + (oc_hi - c0 - cw);
+    const int64_t gt = (int64_t)g * NT + tid, gstride = (int64_t)G * NT;
+    T* ocol[kMaxOther];
+    bool own[kMaxOther];
+#pragma unroll
+    for (int u = 0; u < kMaxOther; ++u) {
+      const int64_t q = gt + u * gstride;
+      own[u] = q < n_other;
+      const int64_t c = (q < n_left) ? (oc_lo + q) : (c0 + cw + (q - n_left));
+      ocol[u] = P + (own[u] ? c : 0) * ld;
+    }
+    bool pend = false;
+    int prj = 0, prp = 0;
+    T pvj[kMaxOther], pvp[kMaxOther];
+
+#pragma clang loop unroll(full)
+    for (int j = 0; j < W; ++j) {
+      if (j < cw) {
+        const int par = j & 1;
+        const int jg = c0 + j;
+        // 1. candidates: the largest |a| over rows >= jg, then the lowest row
+        const double lv = (rok && i >= jg) ? fabs((double)a[j]) : -1.0;
+        const uint32_t li = (rok && i >= jg) ? (uint32_t)i : kNone;
+        const double wm = wave_max_f64(lv);
+        const uint32_t wi = wave_min_u32((lv == wm) ? li : kNone);
+        if ((uint32_t)i == wi) {
+#pragma unroll
+          for (int c = 0; c < W; ++c) s_wrow[par][wave][c] = a[c];
+        }
+        if (i == jg) {
+#pragma unroll
+          for (int c = 0; c < W; ++c) s_rowj[par][c] = a[c];
+        }
+        if (lane == 0) {
+          s_wv[par][wave] = wm;
+          s_wi[par][wave] = wi;
         }
         lds_barrier();
-        prow = s_prow[par];
-        pu = s_bi[par];
-      }
+        // 2. the workgroup's candidate (every thread, the same order)
+        double bv = s_wv[par][0];
+        uint32_t bi = s_wi[par][0];
+        int bw = 0;
+#pragma unroll
+        for (int q = 1; q < NW; ++q) {
+          const double v = s_wv[par][q];
+          const uint32_t ii = s_wi[par][q];
+          if (v > bv || (v == bv && ii < bi)) {
+            bv = v;
+            bi = ii;
+            bw = q;
+          }
+        }
+        const T* prow;
+        uint32_t pu;
+        if (G == 1) {
+          prow = s_wrow[par][bw];
+          pu = bi;
+        } else {
+          if (wave == 0) {
+            const uint32_t tag = tbase + (uint32_t)j;
+            const uint64_t th = (uint64_t)tag << 32;
+            if (lane < kLeafRecWords) {
+              uint32_t pay;
+              if (lane < 2) {
+                const uint64_t vb = (uint64_t)__double_as_longlong(bv);
+                pay = lane == 0 ? (uint32_t)(vb >> 32) : (uint32_t)vb;
+              } else if (lane == 2) {
+                pay = bi;
+              } else {
+                const int e = lane - 3;
+                const uint64_t db = (uint64_t)__double_as_longlong((double)s_wrow[par][bw][e >> 1]);
+                pay = (e & 1) ? (uint32_t)db : (uint32_t)(db >> 32);
+              }
+              st_u64(&ws->rec[par][g][lane], th | pay);
+            }
+            if (g == 0 && lane < 2 * W) {
+              const uint64_t db = (uint64_t)__double_as_longlong((double)s_rowj[par][lane >> 1]);
+              st_u64(&ws->rowj[par][lane], th | ((lane & 1) ? (uint32_t)db : (uint32_t)(db >> 32)));
+            }
+            // (a) the G headers until every tag is current
+            const int nhead = 3 * G;
+            if (!s_broken) {
+              long spins = 0;
+              for (;;) {
+                bool ok = true;
+                for (int e = lane; e < nhead; e += 64) {
+                  const uint64_t v = ld_u64(&ws->rec[par][e / 3][e % 3]);
+                  ok &= (uint32_t)(v >> 32) == tag;
+                  s_words[e] = (uint32_t)v;
+                }
+                if (__all(ok)) break;
+                if (++spins > kSpinLimit) {
+                  if (lane == 0) {
+                    __hip_atomic_store(&ws->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    s_broken = 1;
+                  }
+                  break;
+                }
+              }
+            }
+            double cv = -1.0;
+            uint32_t ci = kNone;
+            for (int q = lane; q < G; q += 64) {
+              const uint32_t* wq = &s_words[3 * q];
+              const double v = __longlong_as_double((long long)(((uint64_t)wq[0] << 32) | wq[1]));
+              const uint32_t ii = wq[2];
+              if (v > cv || (v == cv && ii < ci)) {
+                cv = v;
+                ci = ii;
+              }
+            }
+            const double gm = wave_max_f64(cv);
+            const uint32_t gi = wave_min_u32((cv == gm) ? ci : kNone);
+            const int gw = (gi == kNone) ? 0 : (int)((int64_t)gi / NT);
+            // (b) the winner's row and (outside workgroup 0) row j, tag-checked
+            const bool need = lane < 2 * W || (g != 0 && lane < 4 * W);
+            uint64_t rv = 0;
+            if (!s_broken) {
+              long spins = 0;
+              for (;;) {
+                bool ok = true;
+                if (need) {
+                  rv = (lane < 2 * W) ? ld_u64(&ws->rec[par][gw][3 + lane]) : ld_u64(&ws->rowj[par][lane - 2 * W]);
+                  ok = (uint32_t)(rv >> 32) == tag;
+                }
+                if (__all(ok)) break;
+                if (++spins > kSpinLimit) {
+                  if (lane == 0) {
+                    __hip_atomic_store(&ws->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    s_broken = 1;
+                  }
+                  break;
+                }
+              }
+            }
+            // two 32-bit halves per value: even lane high, odd lane low
+            const uint32_t lo = (uint32_t)__shfl_down((int)(uint32_t)rv, 1, 64);
+            if (need && (lane & 1) == 0) {
+              const double d = __longlong_as_double((long long)(((uint64_t)(uint32_t)rv << 32) | lo));
+              if (lane < 2 * W) s_prow[par][lane >> 1] = (T)d;
+              else s_rowj[par][(lane - 2 * W) >> 1] = (T)d;
+            }
+            if (lane == 0) s_bi[par] = gi;
+          }
+          lds_barrier();
+          prow = s_prow[par];
+          pu = s_bi[par];
+        }
 
-      // 3. interchange, scale, update (a winner outside the block can only
-      // come from NaN input: keep the diagonal row then)
-      int64_t piv = (int64_t)pu;
-      if (pu == kNone || piv < j || piv >= r) piv = j;
-      const T pv = prow[j];
-      if (tid == 0) {
-        s_ipiv[j] = (int32_t)(k + piv + 1);
-        if (pv == T(0) && s_zero == 0) s_zero = (int32_t)(k + j + 1);
-      }
-      // the same interchange on the other columns of the enclosing block:
-      // stores of the previous step, loads of this one
-      if (pend) {
+        // 3. interchange, scale, update (a winner outside the block can only
+        // come from NaN input: keep the diagonal row then)
+        int piv = (int)pu;
+        if (pu == kNone || piv < jg || (int64_t)piv >= r) piv = jg;
+        const T pv = prow[j];
+        if (tid == 0) {
+          s_ipiv[jg] = (int32_t)(k + piv + 1);
+          if (pv == T(0) && s_zero == 0) s_zero = (int32_t)(k + jg + 1);
+        }
+        // the same interchange on the other columns: stores of the previous
+        // step, loads of this one
+        if (pend) {
 #pragma unroll
-        for (int u = 0; u < kMaxOther; ++u)
-          if (own[u]) {
-            ocol[u][prj] = pvp[u];
-            ocol[u][prp] = pvj[u];
+          for (int u = 0; u < kMaxOther; ++u)
+            if (own[u]) {
+              stc(ocol[u] + prj, pvp[u]);
+              stc(ocol[u] + prp, pvj[u]);
+            }
+          pend = false;
+        }
+        if (piv != jg && pv != T(0)) {
+#pragma unroll
+          for (int u = 0; u < kMaxOther; ++u)
+            if (own[u]) {
+              pvj[u] = ldc(ocol[u] + jg);
+              pvp[u] = ldc(ocol[u] + piv);
+            }
+          pend = true;
+          prj = jg;
+          prp = piv;
+        }
+        if (pv != T(0)) {
+          if (i == piv && piv != jg) {
+#pragma unroll
+            for (int c = 0; c < W; ++c) a[c] = s_rowj[par][c];
+          } else if (i == jg) {
+#pragma unroll
+            for (int c = 0; c < W; ++c) a[c] = prow[c];
           }
-        pend = false;
-      }
-      if (piv != j && pv != T(0)) {
-#pragma unroll
-        for (int u = 0; u < kMaxOther; ++u)
-          if (own[u]) {
-            pvj[u] = ocol[u][j];
-            pvp[u] = ocol[u][piv];
-          }
-        pend = true;
-        prj = j;
-        prp = piv;
-      }
-      if (pv != T(0)) {
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          const int64_t i = rbase + q * NT + tid;
-          if (i == piv && piv != j) {
-#pragma unroll
-            for (int c = 0; c < W; ++c) a[q][c] = s_rowj[par][c];
-          } else if (i == j) {
-#pragma unroll
-            for (int c = 0; c < W; ++c) a[q][c] = prow[c];
-          }
-          if (i > j && i < r) {
-            const T l = a[q][j] / pv;
-            a[q][j] = l;
+          if (rok && i > jg) {
+            const T l = a[j] / pv;
+            a[j] = l;
 #pragma unroll
             for (int c = 0; c < W; ++c)
-              if (c > j) a[q][c] = a[q][c] - l * prow[c];
+              if (c > j) a[c] = a[c] - l * prow[c];
           }
         }
       }
     }
-  }
-
-  if (pend) {
+    if (pend) {
 #pragma unroll
-    for (int u = 0; u < kMaxOther; ++u)
-      if (own[u]) {
-        ocol[u][prj] = pvp[u];
-        ocol[u][prp] = pvj[u];
-      }
-  }
-  lds_barrier();  // s_ipiv / s_zero complete
-  if (g == 0) {
-    for (int jj = tid; jj < w; jj += NT) ipiv[k + jj] = s_ipiv[jj];
-    if (tid == 0 && s_zero != 0 && *info == 0) *info = s_zero;
-  }
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int64_t i = rbase + q * NT + tid;
-    if (i < r) {
+      for (int u = 0; u < kMaxOther; ++u)
+        if (own[u]) {
+          stc(ocol[u] + prj, pvp[u]);
+          stc(ocol[u] + prp, pvj[u]);
+        }
+    }
+    // ---- 4. the chunk back (every row)
+    if (rok) {
 #pragma unroll
       for (int c = 0; c < W; ++c)
-        if (c < w) P[i + c * ld] = a[q][c];
+        if (c < cw) stc(P + i + (int64_t)(c0 + c) * ld, a[c]);
     }
+  }
+
+  lds_barrier();  // s_ipiv / s_zero complete
+  if (g == 0) {
+    for (int jj = tid; jj < wt; jj += NT) ipiv[k + jj] = s_ipiv[jj];
+    if (tid == 0 && s_zero != 0 && *info == 0) *info = s_zero;
   }
 }
 
@@ -349,18 +481,13 @@ __global__ __launch_bounds__(NT) void k_panel_leaf(int64_t r, int w, T* __restri
 // epoch wrap-around cannot match a new tag
 __global__ void k_reset_flags(LeafSlots* ws) {
   for (int i = threadIdx.x; i < kLeafMaxGroups; i += blockDim.x) ws->flags[i] = 0;
+  if (threadIdx.x == 0) ws->uflag = 0;
   uint64_t* rec = &ws->rec[0][0][0];
   for (int i = threadIdx.x; i < 2 * kLeafMaxGroups * kLeafRecStride; i += blockDim.x) rec[i] = 0;
   for (int i = threadIdx.x; i < 4 * kLeafMaxWidth; i += blockDim.x) (&ws->rowj[0][0])[i] = 0;
 }
 
-template <typename T, int W, int RPT, int NT>
-hipError_t launch_leaf(hipStream_t s, int G, int64_t r, int w, T* P, int64_t ld, int32_t* ipiv, int64_t k,
-                       int32_t* info, LeafSlots* ws, uint32_t epoch, int64_t oc_lo, int64_t oc_hi) {
-  hipLaunchKernelGGL((k_panel_leaf<T, W, RPT, NT>), dim3(G), dim3(NT), 0, s, r, w, P, ld, ipiv, k, info, ws, epoch,
-                     oc_lo, oc_hi);
-  return hipGetLastError();
-}
+constexpr int kBlockThreads = 1024;
 
 }  // namespace
 
@@ -369,38 +496,27 @@ hipError_t reset_flags(hipStream_t s, LeafSlots* ws) {
   return hipGetLastError();
 }
 
-namespace {
-constexpr int kLeafThreads = 256;
-// rows per thread: fewest workgroups (cheapest exchange) that keep the block
-// in registers
-// rows per thread: four at every height (the leaf is one fully unrolled
-// W = 16 instantiation per precision; narrower leaves are masked)
-int leaf_rpt(int64_t) { return 4; }
-}  // namespace
+int panel_groups(int64_t r) { return (int)((r + kBlockThreads - 1) / kBlockThreads); }
 
-int panel_groups(int64_t r) {
-  const int rpt = leaf_rpt(r);
-  return (int)((r + (int64_t)kLeafThreads * rpt - 1) / ((int64_t)kLeafThreads * rpt));
-}
+uint32_t block_tags(int w) { return (uint32_t)(((w + 15) / 16) * 18 + 2); }
 
 template <typename T>
-hipError_t panel_leaf(hipStream_t s, int64_t r, int w, T* P, int64_t ld, int32_t* ipiv, int64_t k, int32_t* info,
-                      LeafSlots* ws, uint32_t epoch, int64_t oc_lo, int64_t oc_hi) {
+hipError_t panel_block(hipStream_t s, int64_t r, int w, T* P, int64_t ld, int32_t* ipiv, int64_t k, int32_t* info,
+                       LeafSlots* ws, uint32_t epoch, int64_t oc_lo, int64_t oc_hi) {
   if (w <= 0 || r <= 0) return hipSuccess;
-  if (w > 16 || oc_lo > 0 || oc_hi < w) return hipErrorInvalidValue;
-  constexpr int NT = kLeafThreads;
-  const int rpt = leaf_rpt(r);
-  const int64_t G64 = (r + (int64_t)NT * rpt - 1) / ((int64_t)NT * rpt);
+  if (w > kBlockMaxWidth || r < w || oc_lo > 0 || oc_hi < w) return hipErrorInvalidValue;
+  const int64_t G64 = (r + kBlockThreads - 1) / kBlockThreads;
   if (G64 > kLeafMaxGroups) return hipErrorInvalidValue;
   const int G = (int)G64;
-  const int64_t n_other = -oc_lo + (oc_hi - w);
-  if (n_other > (int64_t)kMaxOther * G * NT) return hipErrorInvalidValue;
-  return launch_leaf<T, 16, 4, NT>(s, G, r, w, P, ld, ipiv, k, info, ws, epoch, oc_lo, oc_hi);
+  if (oc_hi - oc_lo > (int64_t)kMaxOther * G * kBlockThreads) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_panel_block<T, kBlockThreads>), dim3(G), dim3(kBlockThreads), 0, s, r, w, P, ld, ipiv, k,
+                     info, ws, epoch, oc_lo, oc_hi);
+  return hipGetLastError();
 }
 
-template hipError_t panel_leaf<double>(hipStream_t, int64_t, int, double*, int64_t, int32_t*, int64_t, int32_t*,
+template hipError_t panel_block<double>(hipStream_t, int64_t, int, double*, int64_t, int32_t*, int64_t, int32_t*,
+                                        LeafSlots*, uint32_t, int64_t, int64_t);
+template hipError_t panel_block<float>(hipStream_t, int64_t, int, float*, int64_t, int32_t*, int64_t, int32_t*,
                                        LeafSlots*, uint32_t, int64_t, int64_t);
-template hipError_t panel_leaf<float>(hipStream_t, int64_t, int, float*, int64_t, int32_t*, int64_t, int32_t*,
-                                      LeafSlots*, uint32_t, int64_t, int64_t);
 
 }  // namespace lupp

@@ -94,7 +94,7 @@ def test_ragged_shapes(shape, dtype):
     A = synth.uniform(7, 3, m, n)
     if dtype == "f32":
         A = A.astype(np.float32)
-    for nb, leaf in ((None, None), (64, 16), (96, 8)):
+    for nb, leaf in ((None, None), (64, 16), (96, 48), (100, None)):
         LU, ipiv, info = _gpu_factor(A, nb, leaf)
         _check_against_oracle(A, LU, ipiv, info, checks.U64 if dtype == "f64" else checks.U32,
                               tau=TAU if dtype == "f64" else 1e-4)
@@ -102,7 +102,7 @@ def test_ragged_shapes(shape, dtype):
 
 @pytest.mark.parametrize("n", [2048, 4096])
 def test_multi_group_panels(n):
-    """r > 1024 rows: the panel leaf runs with several cooperating workgroups."""
+    """r > 1024 rows: the column-block kernel runs with several cooperating workgroups."""
     announce("multi-group n=%d" % n)
     A = synth.uniform(11, 0, n, n)
     LU, ipiv, info = _gpu_factor(A)
