@@ -308,6 +308,169 @@ __device__ __forceinline__ void dgemm4_body(int64_t M, int64_t N, int64_t K, con
   }
 }
 
+// FP64 C -= A * B on v_mfma_f64_16x16x4f64.  Same pipeline as dgemm4_body
+// (double-buffered LDS, peeled K loop, accumulators from -C, interior tiles
+// unmasked); each wavefront owns a WTM x WTN tile of 16x16 products, 16
+// independent accumulators for a 64x64 tile, enough to keep the matrix core
+// busy with two wavefronts per SIMD.  The operands are passed swapped (B
+// first) so each lane holds 16 consecutive rows of a column of C.
+template <int BM, int BN, int BK, int WGM, int WGN, bool EDGE>
+__device__ __forceinline__ void dgemm16_body(int64_t M, int64_t N, int64_t K, const double* __restrict__ A,
+                                             int64_t lda, const double* __restrict__ B, int64_t ldb,
+                                             double* __restrict__ C, int64_t ldc, int64_t m0, int64_t n0,
+                                             double* sA, double* sB) {
+  typedef double T;
+  typedef Mfma<double> MF;
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int FM = WTM / 16, FN = WTN / 16;
+  constexpr int PAD = 16;  // 128-byte k-row runs, 1152 B apart: two bank passes, no extra conflict
+  constexpr int LDSA = BM + PAD, LDSB = BN + PAD;
+  constexpr int SA = BK * LDSA, SB = BK * LDSB;
+  constexpr int EA = BM * BK / NT, EB = BK * BN / NT;
+  constexpr int KA = NT / BM;
+  constexpr int NB_ = NT / BK;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+
+  const int ai = tid % BM, ak0 = tid / BM;
+  const int bk = tid % BK, bn0 = tid / BK;
+  const bool arow_ok = !EDGE || (m0 + ai) < M;
+  const T* pa = A + (arow_ok ? (m0 + ai) : (M - 1)) + (int64_t)ak0 * lda;
+  const int64_t astep = (int64_t)KA * lda;
+  bool bcol_ok[EB];
+  const T* pb[EB];
+#pragma unroll
+  for (int s = 0; s < EB; ++s) {
+    const int64_t gn = n0 + bn0 + NB_ * s;
+    bcol_ok[s] = !EDGE || gn < N;
+    pb[s] = B + (bcol_ok[s] ? gn : (N - 1)) * ldb + bk;
+  }
+
+  T ra[EA], rb[EB];
+  auto gload = [&](int64_t k0) {
+    if (!EDGE) {
+      const T* q = pa + k0 * lda;
+#pragma unroll
+      for (int s = 0; s < EA; ++s) ra[s] = q[s * astep];
+#pragma unroll
+      for (int s = 0; s < EB; ++s) rb[s] = pb[s][k0];
+    } else {
+#pragma unroll
+      for (int s = 0; s < EA; ++s) {
+        const int64_t gk = k0 + ak0 + KA * s;
+        const int64_t gkc = gk < K ? gk : K - 1;
+        const T v = pa[(gkc - ak0) * lda];
+        ra[s] = (arow_ok && gk < K) ? v : T(0);
+      }
+      const int64_t gk = k0 + bk;
+      const bool kok = gk < K;
+      const int64_t off = (kok ? gk : K - 1) - bk;
+#pragma unroll
+      for (int s = 0; s < EB; ++s) {
+        const T v = pb[s][off];
+        rb[s] = (kok && bcol_ok[s]) ? v : T(0);
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+    T* a = sA + buf * SA + ak0 * LDSA + ai;
+    T* b = sB + buf * SB + bk * LDSB + bn0;
+#pragma unroll
+    for (int s = 0; s < EA; ++s) a[s * KA * LDSA] = ra[s];
+#pragma unroll
+    for (int s = 0; s < EB; ++s) b[s * NB_] = rb[s];
+  };
+
+  const int lr = lane & 15, lk = lane >> 4;
+  // accumulators from -C: lane holds rows lr of the 16x16 tile, column col(lane, q)
+  typename MF::v4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    const int64_t row = m0 + wm * WTM + i * 16 + lr;
+    const int64_t rowc = (!EDGE || row < M) ? row : M - 1;
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t col = n0 + wn * WTN + j * 16 + MF::col(lane, q);
+        const int64_t colc = (!EDGE || col < N) ? col : N - 1;
+        const T v = C[rowc + colc * ldc];
+        acc[i][j][q] = (!EDGE || (row < M && col < N)) ? -v : T(0);
+      }
+  }
+
+  auto compute = [&](int buf) {
+    const T* as = sA + buf * SA + lk * LDSA + wm * WTM + lr;
+    const T* bs = sB + buf * SB + lk * LDSB + wn * WTN + lr;
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      T af[FM], bf[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) af[i] = as[kk * 4 * LDSA + i * 16];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) bf[j] = bs[kk * 4 * LDSB + j * 16];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = MF::mma(bf[j], af[i], acc[i][j]);
+    }
+  };
+
+  const int KT = (int)((K + BK - 1) / BK);
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt + 1 < KT; ++kt) {
+    gload((int64_t)(kt + 1) * BK);
+    compute(kt & 1);
+    sstore((kt + 1) & 1);
+    __syncthreads();
+  }
+  compute((KT - 1) & 1);
+
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    const int64_t row = m0 + wm * WTM + i * 16 + lr;
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t col = n0 + wn * WTN + j * 16 + MF::col(lane, q);
+        if (!EDGE || (row < M && col < N)) C[row + col * ldc] = -acc[i][j][q];
+      }
+  }
+}
+
+template <int BM, int BN, int BK, int WGM, int WGN, int MINB>
+__global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_dgemm_sub_16(int64_t M, int64_t N, int64_t K,
+                                                                      const double* __restrict__ A, int64_t lda,
+                                                                      const double* __restrict__ B, int64_t ldb,
+                                                                      double* __restrict__ C, int64_t ldc,
+                                                                      int tiles_m, int tiles_n) {
+  constexpr int PAD = 16;
+  __shared__ double sA[2 * BK * (BM + PAD)];
+  __shared__ double sB[2 * BK * (BN + PAD)];
+  const int total = tiles_m * tiles_n;
+  const int per_xcd = (total + kXcds - 1) / kXcds;
+  const int bid = blockIdx.x;
+  const int t = (bid % kXcds) * per_xcd + bid / kXcds;
+  if (t >= total) return;
+  const int group_size = kGroupM * tiles_n;
+  const int group = t / group_size;
+  const int first_m = group * kGroupM;
+  const int gm = min(tiles_m - first_m, kGroupM);
+  const int within = t - group * group_size;
+  const int tm = first_m + within % gm;
+  const int tn = within / gm;
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  if (m0 + BM <= M && n0 + BN <= N && K % BK == 0)
+    dgemm16_body<BM, BN, BK, WGM, WGN, false>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sA, sB);
+  else
+    dgemm16_body<BM, BN, BK, WGM, WGN, true>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sA, sB);
+}
+
 template <int BM, int BN, int BK, int WGM, int WGN, int MINB>
 __global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_dgemm_sub_4x4(int64_t M, int64_t N, int64_t K,
                                                                        const double* __restrict__ A, int64_t lda,
@@ -352,6 +515,18 @@ hipError_t launch(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, in
 }
 
 template <int BM, int BN, int BK, int WGM, int WGN, int MINB>
+hipError_t launch_d16(hipStream_t s, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
+                      int64_t ldb, double* C, int64_t ldc) {
+  const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
+  if (tm * tn > (int64_t)1 << 30) return hipErrorInvalidValue;
+  const int total = (int)(tm * tn);
+  const int per_xcd = (total + kXcds - 1) / kXcds;
+  hipLaunchKernelGGL((k_dgemm_sub_16<BM, BN, BK, WGM, WGN, MINB>), dim3(per_xcd * kXcds), dim3(64 * WGM * WGN), 0,
+                     s, M, N, K, A, lda, B, ldb, C, ldc, (int)tm, (int)tn);
+  return hipGetLastError();
+}
+
+template <int BM, int BN, int BK, int WGM, int WGN, int MINB>
 hipError_t launch_d4(hipStream_t s, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
                      int64_t ldb, double* C, int64_t ldc) {
   const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
@@ -380,7 +555,7 @@ hipError_t gemm_sub(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, 
   if constexpr (sizeof(T) == 8) {
     if (big_tiles >= 512) {
       tile = 1;
-      return launch_d4<128, 128, 16, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
+      return launch_d16<128, 128, 8, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
     }
     tile = 2;
     return launch_d4<64, 64, 16, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
