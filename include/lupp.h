@@ -59,10 +59,16 @@ enum {
   LUPP_OPT_TIMING = 3,     /* 1: record HIP events around every phase of xGETRF (below)    */
   LUPP_OPT_LOOKAHEAD = 4,  /* 1 (default): factor the next column block on a second stream
                               while the trailing update runs; 0: one stream, in order      */
-  LUPP_OPT_UPDATE_PREC = 5 /* lupp_sgetrf only: format of the operands of the trailing
+  LUPP_OPT_UPDATE_PREC = 5, /* lupp_sgetrf only: format of the operands of the trailing
                               update A22 -= A21*U12, one of LUPP_PREC_* (default FP32).  The
                               column-block factorization and U12 stay FP32; the products are
                               accumulated in FP32 and A22 is stored in FP32.               */
+  LUPP_OPT_DEFER_SWAPS = 6 /* 1 (default): the interchanges of every step reach the finished
+                              columns on its left once, at the end, composed into one row
+                              permutation per column block (same result, one pass instead
+                              of one per step; needs a workspace of about 2*m*n/nb bytes,
+                              nb <= 512 and m - nb <= 32768 for FP64 or 65536 for FP32,
+                              otherwise ignored); 0: at every step, as in LAPACK            */
 };
 
 /* Operand formats of the trailing update (LUPP_OPT_UPDATE_PREC) and of the

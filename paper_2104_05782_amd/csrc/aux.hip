@@ -90,77 +90,84 @@ __global__ __launch_bounds__(256) void k_trsm_leaf(int w, int64_t ncols, const T
   }
 }
 
-// One wavefront replays interchanges k1..k2-1 on row labels.  Rows k1..k2-1
-// are tracked in s_cont; rows below k2 that are hit are appended to a short
-// list and found again by a ballot over it.
-__global__ __launch_bounds__(64) void k_swap_pairs(const int32_t* __restrict__ ipiv, int64_t k1, int64_t k2,
-                                                   int64_t m, SwapPairs* __restrict__ out) {
-  __shared__ int32_t s_piv[kMaxSwaps];
-  __shared__ int32_t s_cont[kMaxSwaps];
-  __shared__ int32_t s_erow[kMaxSwaps];
-  __shared__ int32_t s_econt[kMaxSwaps];
-  const int lane = threadIdx.x;
+// Composition of the interchanges k1..k2-1 (row i with row p_i >= i, in
+// order) into one permutation of the rows they touch, one thread per
+// interchange, no replay.  Row k1+i is final once interchange i is done, and
+// before it holds C(i): the original content of the last row j < i that sent
+// its content into row k1+i (p_j = k1+i), followed recursively, or its own
+// original content if there is none.  Interchange i brings into row k1+i what
+// row p_i holds at that time: C(L) for the last j = L < i with p_j = p_i, or
+// p_i's original content.  A row below k2 ends with C(j) of the last j that
+// sent content into it.  The chains of C are resolved by pointer jumping.
+__global__ __launch_bounds__(kMaxSwaps) void k_swap_pairs(const int32_t* __restrict__ ipiv, int64_t k1, int64_t k2,
+                                                          int64_t m, SwapPairs* __restrict__ out) {
+  __shared__ int32_t s_p[kMaxSwaps];
+  __shared__ int32_t s_root[kMaxSwaps];
+  __shared__ int32_t s_wext[kMaxSwaps / 64];
+  const int i = threadIdx.x;
   const int S = (int)(k2 - k1);
-  for (int i = lane; i < S; i += 64) {
-    s_piv[i] = ipiv[k1 + i] - 1;
-    s_cont[i] = (int32_t)(k1 + i);
+  const bool act = i < S;
+  const int32_t self = (int32_t)(k1 + i);
+  int32_t p = self;
+  if (act) {
+    const int64_t v = (int64_t)ipiv[k1 + i] - 1;
+    if (v > k1 + i && v < m) p = (int32_t)v;  // otherwise no interchange (or a NaN-born index)
+    s_p[i] = p;
   }
   __syncthreads();
-  int n_ext = 0;
-  for (int i = 0; i < S; ++i) {
-    const int64_t p = s_piv[i];
-    const int64_t row = k1 + i;
-    if (p <= row || p >= m) continue;  // no interchange (or NaN-born index)
-    if (p < k2) {
-      if (lane == 0) {
-        const int32_t t = s_cont[i];
-        s_cont[i] = s_cont[p - k1];
-        s_cont[p - k1] = t;
-      }
-    } else {
-      int found = -1;
-      for (int e0 = 0; e0 < n_ext; e0 += 64) {
-        const int e = e0 + lane;
-        const unsigned long long hit = __ballot(e < n_ext && s_erow[e] == (int32_t)p);
-        if (hit) {
-          found = e0 + __ffsll((long long)hit) - 1;
-          break;
-        }
-      }
-      if (found < 0) {
-        found = n_ext++;
-        if (lane == 0) {
-          s_erow[found] = (int32_t)p;
-          s_econt[found] = (int32_t)p;
-        }
-      }
-      if (lane == 0) {
-        const int32_t t = s_cont[i];
-        s_cont[i] = s_econt[found];
-        s_econt[found] = t;
-      }
+  int prev_b = -1, last_p = -1;
+  bool later_p = false;
+  for (int j = 0; j < S; ++j) {
+    const int32_t q = s_p[j];
+    if (j < i) {
+      if (q == self) prev_b = j;
+      if (q == p) last_p = j;
+    } else if (j > i && q == p) {
+      later_p = true;
     }
-    __builtin_amdgcn_s_waitcnt(0);  // lane 0's LDS writes precede the next replay step
-    __builtin_amdgcn_wave_barrier();
   }
-  for (int i = lane; i < S; i += 64) {
-    out->dst[i] = (int32_t)(k1 + i);
-    out->src[i] = s_cont[i];
+  if (act) s_root[i] = prev_b < 0 ? i : prev_b;
+  __syncthreads();
+  for (int step = 1; step < S; step *= 2) {
+    int r = 0;
+    if (act) r = s_root[s_root[i]];
+    __syncthreads();
+    if (act) s_root[i] = r;
+    __syncthreads();
   }
-  for (int e = lane; e < n_ext; e += 64) {
-    out->dst[S + e] = s_erow[e];
-    out->src[S + e] = s_econt[e];
+  // compaction of the rows below k2, in the order of their last interchange
+  const bool ext = act && p >= k2 && !later_p;
+  const unsigned long long bal = __ballot(ext);
+  const int lane = i & 63, wave = i >> 6;
+  if (lane == 0) s_wext[wave] = __popcll(bal);
+  __syncthreads();
+  int base = 0, total = 0;
+  for (int w = 0; w < kMaxSwaps / 64; ++w) {
+    const int c = s_wext[w];
+    if (w < wave) base += c;
+    total += c;
   }
-  if (lane == 0) out->count = S + n_ext;
+  if (act) {
+    const int32_t fin = last_p >= 0 ? (int32_t)(k1 + s_root[last_p]) : p;
+    out->dst[i] = self;
+    out->src[i] = fin;
+    if (ext) {
+      const int pos = S + base + __popcll(bal & ((1ull << lane) - 1ull));
+      out->dst[pos] = p;
+      out->src[pos] = (int32_t)(k1 + s_root[i]);
+    }
+  }
+  if (i == 0) out->count = S + total;
 }
 
-// Gather/scatter of a composed row permutation on a band of 64 columns per
-// workgroup, 8 columns at a time.
-template <typename T>
+// Gather/scatter of a composed row permutation on a band of CB columns per
+// workgroup, CC columns at a time (narrow bands for narrow ranges, so that
+// enough workgroups run).
+template <typename T, int CB, int CC>
 __global__ __launch_bounds__(256) void k_apply_pairs(T* __restrict__ A, int64_t lda, int64_t c0, int64_t c1,
                                                      int64_t skip0, int64_t skip1,
                                                      const SwapPairs* __restrict__ pairs) {
-  constexpr int CB = 64, CC = 8, QP = (2 * kMaxSwaps) / 256;
+  constexpr int QP = (2 * kMaxSwaps) / 256;
   __shared__ int32_t s_dst[2 * kMaxSwaps];
   __shared__ int32_t s_src[2 * kMaxSwaps];
   const int tid = threadIdx.x;
@@ -198,6 +205,73 @@ __global__ __launch_bounds__(256) void k_apply_pairs(T* __restrict__ A, int64_t 
       }
     }
     __syncthreads();
+  }
+}
+
+// B := inv(L) * B for a unit lower triangle of order w <= 256, one launch:
+// each workgroup owns 16 right-hand columns, held in registers (thread
+// (r, c) keeps rows r, r+16, ... of column c).  The triangle is processed in
+// 16-column chunks staged through LDS: the chunk's diagonal block is solved by
+// every thread of a column (16 values, redundantly, no cross-lane traffic),
+// then the rows below are updated with it.  Row i accumulates
+// b_i - sum_j l_ij x_j in increasing j, as plain forward substitution does.
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsm_lower_band(int w, int64_t ncols, const T* __restrict__ L, int64_t ldl,
+                                                         T* __restrict__ B, int64_t ldb) {
+  constexpr int NC = 16, CH = 16, MAXW = kTrsmBandMaxW, NQ = MAXW / CH;
+  __shared__ T sL[CH][MAXW];
+  __shared__ T sX[NC][CH + 1];
+  const int tid = threadIdx.x;
+  const int r = tid & 15, cl = tid >> 4;
+  const int64_t c = (int64_t)blockIdx.x * NC + cl;
+  const bool cok = c < ncols;
+  T* bc = B + (cok ? c : 0) * ldb;
+  T x[NQ];
+#pragma unroll
+  for (int t = 0; t < NQ; ++t) {
+    const int i = t * CH + r;
+    x[t] = (cok && i < w) ? bc[i] : T(0);
+  }
+  const int nq = (w + CH - 1) / CH;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    if (q < nq) {
+      const int j0 = q * CH;
+#pragma unroll
+      for (int kk = 0; kk < CH; ++kk) {
+        const int j = j0 + kk;
+        sL[kk][tid] = (tid >= j0 && tid < w && j < w) ? L[tid + (int64_t)j * ldl] : T(0);
+      }
+      sX[cl][r] = x[q];
+      __syncthreads();
+      T xs[CH];
+#pragma unroll
+      for (int i = 0; i < CH; ++i) xs[i] = sX[cl][i];
+#pragma unroll
+      for (int kk = 0; kk < CH; ++kk)
+#pragma unroll
+        for (int i = kk + 1; i < CH; ++i) xs[i] = xs[i] - sL[kk][j0 + i] * xs[kk];
+      T mine = xs[0];
+#pragma unroll
+      for (int i = 1; i < CH; ++i)
+        if (r == i) mine = xs[i];
+      x[q] = mine;
+#pragma unroll
+      for (int t = q + 1; t < NQ; ++t) {
+        if (t < nq) {
+#pragma unroll
+          for (int kk = 0; kk < CH; ++kk) x[t] = x[t] - sL[kk][t * CH + r] * xs[kk];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (cok) {
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) {
+      const int i = t * CH + r;
+      if (i < w) bc[i] = x[t];
+    }
   }
 }
 
@@ -261,13 +335,76 @@ __global__ __launch_bounds__(64) void k_trsm_small(int w, int64_t ncols, const T
     for (int i = 0; i < w; ++i) col[i] = sX[i * 64 + tid];
 }
 
+// One workgroup walks the steps backwards, keeping g (gather map of the steps
+// after the current block) and its inverse: composing h_s on the left of g
+// changes g only where g(i) is a destination of step s, found through the
+// inverse.  A snapshot of g over the block's rows is stored per block.
+__global__ __launch_bounds__(kLeftGatherThreads) void k_left_maps(const SwapPairs* __restrict__ pairs, int64_t J,
+                                                                  int64_t m, int64_t nb, int32_t* __restrict__ g,
+                                                                  int32_t* __restrict__ ginv,
+                                                                  int32_t* __restrict__ gmap) {
+  const int tid = threadIdx.x;
+  for (int64_t i = tid; i < m; i += kLeftGatherThreads) {
+    g[i] = (int32_t)i;
+    ginv[i] = (int32_t)i;
+  }
+  __syncthreads();
+  for (int64_t j = J - 2; j >= 0; --j) {
+    const SwapPairs* sp = pairs + (j + 1);
+    const int P = sp->count;
+    int32_t d = 0, sr = 0, at = 0;
+    const bool has = tid < P;
+    if (has) {
+      d = sp->dst[tid];
+      sr = sp->src[tid];
+      at = ginv[d];
+    }
+    __syncthreads();
+    if (has) {
+      g[at] = sr;
+      ginv[sr] = at;
+    }
+    __syncthreads();
+    const int64_t r0 = (j + 1) * nb;
+    int32_t* out = gmap + left_map_offset(j, m, nb);
+    for (int64_t i = tid; i < m - r0; i += kLeftGatherThreads) out[i] = g[r0 + i];
+  }
+}
+
+// One workgroup per finished column: every row of the block's segment is read
+// (through the map) into registers before any is written back in order.
+template <typename T, int R>
+__global__ __launch_bounds__(kLeftGatherThreads) void k_left_gather(T* __restrict__ A, int64_t lda, int64_t m,
+                                                                    int64_t nb, const int32_t* __restrict__ gmap) {
+  const int64_t c = blockIdx.x;
+  const int64_t j = c / nb;
+  const int64_t r0 = (j + 1) * nb;
+  const int len = (int)(m - r0);
+  const int32_t* map = gmap + left_map_offset(j, m, nb);
+  T* col = A + c * lda;
+  T* dst = col + r0;
+  const int tid = threadIdx.x;
+  T v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = tid + r * kLeftGatherThreads;
+    if (i < len) v[r] = col[(uint32_t)map[i]];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = tid + r * kLeftGatherThreads;
+    if (i < len) dst[(uint32_t)i] = v[r];
+  }
+}
+
 __global__ void k_set_int(int32_t* p, int32_t v) { *p = v; }
 
 }  // namespace
 
 hipError_t swap_pairs(hipStream_t s, const int32_t* ipiv, int64_t k1, int64_t k2, int64_t m, SwapPairs* pairs) {
   if (k2 - k1 > kMaxSwaps || k2 < k1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_swap_pairs, dim3(1), dim3(64), 0, s, ipiv, k1, k2, m, pairs);
+  hipLaunchKernelGGL(k_swap_pairs, dim3(1), dim3(kMaxSwaps), 0, s, ipiv, k1, k2, m, pairs);
   return hipGetLastError();
 }
 
@@ -280,8 +417,56 @@ hipError_t apply_pairs(hipStream_t s, T* A, int64_t lda, int64_t c0, int64_t c1,
   if (skip1 < skip0) skip1 = skip0;
   const int64_t width = (c1 - c0) - (skip1 - skip0);
   if (width <= 0) return hipSuccess;
-  const int64_t blocks = (width + 63) / 64;
-  hipLaunchKernelGGL(k_apply_pairs<T>, dim3((unsigned)blocks), dim3(256), 0, s, A, lda, c0, c1, skip0, skip1, pairs);
+  if (width >= 64 * 1024) {
+    hipLaunchKernelGGL((k_apply_pairs<T, 64, 8>), dim3((unsigned)((width + 63) / 64)), dim3(256), 0, s, A, lda, c0,
+                       c1, skip0, skip1, pairs);
+  } else if (width >= 8 * 512) {
+    hipLaunchKernelGGL((k_apply_pairs<T, 8, 8>), dim3((unsigned)((width + 7) / 8)), dim3(256), 0, s, A, lda, c0, c1,
+                       skip0, skip1, pairs);
+  } else {
+    hipLaunchKernelGGL((k_apply_pairs<T, 2, 2>), dim3((unsigned)((width + 1) / 2)), dim3(256), 0, s, A, lda, c0, c1,
+                       skip0, skip1, pairs);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t trsm_lower_band(hipStream_t s, int64_t w, int64_t ncols, const T* L, int64_t ldl, T* B, int64_t ldb) {
+  if (w <= 0 || ncols <= 0) return hipSuccess;
+  if (w > kTrsmBandMaxW) return hipErrorInvalidValue;
+  const int64_t blocks = (ncols + 15) / 16;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_trsm_lower_band<T>, dim3((unsigned)blocks), dim3(256), 0, s, (int)w, ncols, L, ldl, B, ldb);
+  return hipGetLastError();
+}
+
+template hipError_t trsm_lower_band<double>(hipStream_t, int64_t, int64_t, const double*, int64_t, double*, int64_t);
+template hipError_t trsm_lower_band<float>(hipStream_t, int64_t, int64_t, const float*, int64_t, float*, int64_t);
+
+hipError_t left_maps(hipStream_t s, const SwapPairs* pairs, int64_t J, int64_t m, int64_t nb, int32_t* g,
+                     int32_t* gmap) {
+  if (J < 2) return hipSuccess;
+  hipLaunchKernelGGL(k_left_maps, dim3(1), dim3(kLeftGatherThreads), 0, s, pairs, J, m, nb, g, g + m, gmap);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t left_gather(hipStream_t s, T* A, int64_t lda, int64_t m, int64_t nb, int64_t J, const int32_t* gmap) {
+  if (J < 2) return hipSuccess;
+  const int64_t rows = m - nb;
+  if (rows <= 0) return hipSuccess;
+  if (rows > left_gather_max_rows(sizeof(T))) return hipErrorInvalidValue;
+  const int64_t cols = (J - 1) * nb;
+  if (cols > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)cols), block(kLeftGatherThreads);
+  if (rows <= 8 * kLeftGatherThreads)
+    hipLaunchKernelGGL((k_left_gather<T, 8>), grid, block, 0, s, A, lda, m, nb, gmap);
+  else if (rows <= 16 * kLeftGatherThreads)
+    hipLaunchKernelGGL((k_left_gather<T, 16>), grid, block, 0, s, A, lda, m, nb, gmap);
+  else if (rows <= 32 * kLeftGatherThreads)
+    hipLaunchKernelGGL((k_left_gather<T, 32>), grid, block, 0, s, A, lda, m, nb, gmap);
+  else if constexpr (sizeof(T) == 4)
+    hipLaunchKernelGGL((k_left_gather<T, 64>), grid, block, 0, s, A, lda, m, nb, gmap);
   return hipGetLastError();
 }
 
@@ -341,6 +526,8 @@ hipError_t set_int(hipStream_t s, int32_t* p, int32_t v) {
   return hipGetLastError();
 }
 
+template hipError_t left_gather<double>(hipStream_t, double*, int64_t, int64_t, int64_t, int64_t, const int32_t*);
+template hipError_t left_gather<float>(hipStream_t, float*, int64_t, int64_t, int64_t, int64_t, const int32_t*);
 template hipError_t laswp<double>(hipStream_t, double*, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t,
                                   const int32_t*, int64_t, int64_t, SwapPairs*);
 template hipError_t laswp<float>(hipStream_t, float*, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t,

@@ -116,6 +116,34 @@ template <typename T>
 hipError_t laswp(hipStream_t s, T* A, int64_t lda, int64_t m, int64_t c0, int64_t c1, int64_t skip0, int64_t skip1,
                  const int32_t* ipiv, int64_t k1, int64_t k2, SwapPairs* pairs);
 
+// Deferred interchanges of the finished columns.  Block j (columns
+// [j*nb, (j+1)*nb), j < J-1) is left alone by the later steps j+1..J-1 of the
+// loop; its rows [(j+1)*nb, m) are permuted once, at the end, by the
+// composition of those steps' pairs: row i receives the row gmap_j(i), where
+// gmap_j = h_{j+1} o ... o h_{J-1} and h_s maps dst -> src of step s's pairs.
+// The maps of all blocks are stored back to back: block j's starts at
+// j*m - nb*j*(j+1)/2 and has m - (j+1)*nb entries.
+constexpr int kLeftGatherThreads = 1024;
+// rows of a column held in registers by one workgroup: 32 (FP64) or 64 (FP32) per thread
+__host__ __device__ inline int64_t left_gather_max_rows(size_t elem) {
+  return (elem == 8 ? 32 : 64) * (int64_t)kLeftGatherThreads;
+}
+__host__ __device__ inline int64_t left_map_offset(int64_t j, int64_t m, int64_t nb) { return j * m - nb * j * (j + 1) / 2; }
+__host__ __device__ inline int64_t left_map_entries(int64_t J, int64_t m, int64_t nb) { return J < 2 ? 0 : left_map_offset(J - 1, m, nb); }
+// pairs[s], s < J: the composed pairs of step s.  g: 2*m ints of scratch.
+hipError_t left_maps(hipStream_t s, const SwapPairs* pairs, int64_t J, int64_t m, int64_t nb, int32_t* g,
+                     int32_t* gmap);
+// Columns [0, (J-1)*nb) of A: rows [(j+1)*nb, m) of block j gathered by gmap_j
+// (m - nb <= left_gather_max_rows(sizeof(T))).
+template <typename T>
+hipError_t left_gather(hipStream_t s, T* A, int64_t lda, int64_t m, int64_t nb, int64_t J, const int32_t* gmap);
+
+// B (w x ncols) := inv(L) * B, L unit lower triangular of order w <= kTrsmBandMaxW,
+// in one launch (16 columns per workgroup).
+constexpr int kTrsmBandMaxW = 256;
+template <typename T>
+hipError_t trsm_lower_band(hipStream_t s, int64_t w, int64_t ncols, const T* L, int64_t ldl, T* B, int64_t ldb);
+
 // Triangular solve on a w x ncols block (w <= 64): lower=true solves with a
 // unit lower triangle (forward), lower=false with a non-unit upper triangle.
 template <typename T>

@@ -553,12 +553,12 @@ hipError_t gemm_sub(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, 
   }
   const int64_t big_tiles = ((M + 127) / 128) * ((N + 127) / 128);
   if constexpr (sizeof(T) == 8) {
-    if (big_tiles >= 512) {
+    if (big_tiles >= 256) {
       tile = 1;
       return launch_d16<128, 128, 8, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
     }
     tile = 2;
-    return launch_d4<64, 64, 16, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
+    return launch_d16<64, 64, 8, 2, 2, 4>(s, M, N, K, A, lda, B, ldb, C, ldc);
   } else {
     if (big_tiles >= 512) {
       tile = 1;

@@ -23,6 +23,11 @@ struct lupp_handle_st {
   int block = 128;                  // widest column block factored in one cooperative launch
   lupp::LeafSlots* slots = nullptr;
   lupp::SwapPairs* pairs = nullptr;
+  // deferred interchanges of the finished columns: per-step pairs, the gather
+  // maps of all blocks, and 2*m ints of scratch (one allocation, grown on demand)
+  void* defer_buf = nullptr;
+  size_t defer_bytes = 0;
+  int defer = 1;                    // defer the finished columns' interchanges when the workspace allows
   uint32_t epoch = 0;
   bool timing = false;
   std::vector<lupp::TimingRecord> records;  // events are created once and reused
@@ -55,6 +60,10 @@ inline int hip_status(hipError_t e) { return e == hipSuccess ? LUPP_OK : LUPP_ER
 // Handle workspace of the factorization (slots, swap pairs, lookahead streams).
 hipError_t ensure_workspace(lupp_handle_t h);
 // Scale workspace of the low-precision update for an m x n factorization.
+// Workspace of the deferred interchanges for an m x n factorization with the
+// handle's nb; false when the deferral does not apply (the interchanges are
+// then applied to the finished columns at every step).
+bool ensure_defer(lupp_handle_t h, int64_t m, int64_t n, size_t elem);
 hipError_t ensure_lp_scale(lupp_handle_t h, int64_t m, int64_t n);
 // Flags of the one-launch triangular solve for n rows.
 hipError_t ensure_trsv(lupp_handle_t h, int64_t n);

@@ -69,7 +69,7 @@ void timer_end(lupp_handle_t h, int idx, hipStream_t st, double flops, bool big 
 // B (w x ncols) := inv(L) * B with L unit lower triangular (w x w).
 template <typename T>
 hipError_t trsm_lower_unit(hipStream_t s, int64_t w, int64_t ncols, const T* L, int64_t ldl, T* B, int64_t ldb) {
-  if (w <= 64) return trsm_small<T>(s, true, w, ncols, L, ldl, B, ldb);
+  if (w <= kTrsmBandMaxW) return trsm_lower_band<T>(s, w, ncols, L, ldl, B, ldb);
   const int64_t w1 = w / 2;
   LUPP_TRY(trsm_lower_unit<T>(s, w1, ncols, L, ldl, B, ldb));
   LUPP_TRY(gemm_sub<T>(s, w - w1, ncols, w1, L + w1, ldl, B, ldb, B + w1, ldb));
@@ -107,10 +107,7 @@ hipError_t panel(lupp_handle_t h, hipStream_t s, int64_t m, int64_t k, int64_t w
   const int64_t w2 = w - w1;
   LUPP_TRY(panel<T>(h, s, m, k, w1, p0, p1, A, lda, ipiv, info));
   int t = timer_begin(h, LUPP_PHASE_PANEL_TRSM, s);
-  if (w1 <= 64)
-    LUPP_TRY(trsm_small<T>(s, true, w1, w2, A + k + k * lda, lda, A + k + (k + w1) * lda, lda));
-  else
-    LUPP_TRY(trsm_lower_unit<T>(s, w1, w2, A + k + k * lda, lda, A + k + (k + w1) * lda, lda));
+  LUPP_TRY(trsm_lower_unit<T>(s, w1, w2, A + k + k * lda, lda, A + k + (k + w1) * lda, lda));
   timer_end(h, t, s, (double)w1 * (double)w1 * (double)w2);
   t = timer_begin(h, LUPP_PHASE_PANEL_GEMM, s);
   LUPP_TRY(gemm_sub<T>(s, m - k - w1, w2, w1, A + (k + w1) + k * lda, lda, A + k + (k + w1) * lda, lda,
@@ -161,55 +158,88 @@ hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32
   const int64_t p = m < n ? m : n;
   if (p == 0) return hipSuccess;
   const bool la = h->lookahead && h->side && h->bulk;
+  const int64_t J = (p + h->nb - 1) / h->nb;
+  const bool defer = ensure_defer(h, m, n, sizeof(T));
+  SwapPairs* step_pairs = defer ? (SwapPairs*)h->defer_buf : nullptr;
   LUPP_TRY(factor_block<T>(h, s, m, 0, (p < h->nb) ? p : h->nb, A, lda, ipiv, info));
   for (int64_t k = 0; k < p; k += h->nb) {
     const int64_t b = (p - k < h->nb) ? (p - k) : h->nb;
     const int64_t kn = k + b;
     const int64_t bn = (kn < p) ? ((p - kn < h->nb) ? (p - kn) : h->nb) : 0;
-    // interchanges of this block on every column outside it
+    const int64_t nr = n - kn;                    // columns right of the block
+    const int64_t mr = m - kn;                    // rows below it
+    const int64_t n1 = (nr > 0 && mr > 0) ? bn : 0;  // the next block's columns
+    // The block's interchanges, composed once into pairs, go to the next
+    // block's columns here, to the other columns on the right together with
+    // their update below, and to the finished columns on the left either now
+    // or (deferred) once at the end.
+    const bool composed = b <= kMaxSwaps;
+    SwapPairs* sp = defer ? step_pairs + k / h->nb : h->pairs;
     int t = timer_begin(h, LUPP_PHASE_LASWP, s);
-    LUPP_TRY(laswp<T>(s, A, lda, m, 0, n, k, k + b, ipiv, k, k + b, h->pairs));
+    if (composed) {
+      LUPP_TRY(swap_pairs(s, ipiv, k, kn, m, sp));
+      if (!defer) LUPP_TRY(apply_pairs<T>(s, A, lda, 0, k, 0, 0, sp, 2 * b));
+      LUPP_TRY(apply_pairs<T>(s, A, lda, kn, kn + n1, 0, 0, sp, 2 * b));
+    } else {
+      LUPP_TRY(laswp<T>(s, A, lda, m, 0, n, k, kn, ipiv, k, kn, nullptr));
+    }
     timer_end(h, t, s, 0.0);
-    if (kn < n) {
-      const int64_t nr = n - kn;
+    if (nr <= 0) continue;
+    if (n1 > 0) {
       t = timer_begin(h, LUPP_PHASE_TRSM, s);
-      LUPP_TRY(trsm_lower_unit<T>(s, b, nr, A + k + k * lda, lda, A + k + kn * lda, lda));
-      timer_end(h, t, s, (double)b * (double)b * (double)nr);
-      const int64_t mr = m - kn;
+      LUPP_TRY(trsm_lower_unit<T>(s, b, n1, A + k + k * lda, lda, A + k + kn * lda, lda));
+      timer_end(h, t, s, (double)b * (double)b * (double)n1);
       // columns of the next block first, so that it can be factored early
-      const int64_t n1 = (mr > 0) ? bn : 0;
-      if (n1 > 0) {
-        t = timer_begin(h, LUPP_PHASE_UPDATE, s);
-        LUPP_TRY(update<T>(h, s, 0, mr, n1, b, A + kn + k * lda, lda, A + k + kn * lda, lda, A + kn + kn * lda, lda));
-        timer_end(h, t, s, 2.0 * (double)mr * (double)n1 * (double)b);
+      t = timer_begin(h, LUPP_PHASE_UPDATE, s);
+      LUPP_TRY(update<T>(h, s, 0, mr, n1, b, A + kn + k * lda, lda, A + k + kn * lda, lda, A + kn + kn * lda, lda));
+      timer_end(h, t, s, 2.0 * (double)mr * (double)n1 * (double)b);
+    }
+    // overlap only when the next block's cooperative factorization fits in
+    // the reserved CUs (one workgroup per CU at most)
+    const bool overlap = la && n1 > 0 && panel_groups(mr) <= h->panel_cus && nr > n1;
+    hipStream_t su = s;
+    if (overlap) {
+      LUPP_TRY(hipEventRecord(h->ev_cols, s));
+      LUPP_TRY(hipStreamWaitEvent(h->side, h->ev_cols, 0));
+      LUPP_TRY(hipStreamWaitEvent(h->bulk, h->ev_cols, 0));
+      LUPP_TRY(factor_block<T>(h, h->side, m, kn, bn, A, lda, ipiv, info));
+      LUPP_TRY(hipEventRecord(h->ev_panel, h->side));
+      su = h->bulk;
+    }
+    if (nr > n1) {
+      const int64_t c1 = kn + n1, nc = nr - n1;
+      if (composed) {
+        t = timer_begin(h, LUPP_PHASE_LASWP, su);
+        LUPP_TRY(apply_pairs<T>(su, A, lda, c1, n, 0, 0, sp, 2 * b));
+        timer_end(h, t, su, 0.0);
       }
-      // overlap only when the next block's cooperative factorization fits in
-      // the reserved CUs (one workgroup per CU at most)
-      const bool overlap = la && n1 > 0 && panel_groups(mr) <= h->panel_cus && nr > n1;
-      hipStream_t su = s;
-      if (overlap) {
-        LUPP_TRY(hipEventRecord(h->ev_cols, s));
-        LUPP_TRY(hipStreamWaitEvent(h->side, h->ev_cols, 0));
-        LUPP_TRY(hipStreamWaitEvent(h->bulk, h->ev_cols, 0));
-        LUPP_TRY(factor_block<T>(h, h->side, m, kn, bn, A, lda, ipiv, info));
-        LUPP_TRY(hipEventRecord(h->ev_panel, h->side));
-        su = h->bulk;
-      }
-      if (mr > 0 && nr > n1) {
+      t = timer_begin(h, LUPP_PHASE_TRSM, su);
+      LUPP_TRY(trsm_lower_unit<T>(su, b, nc, A + k + k * lda, lda, A + k + c1 * lda, lda));
+      timer_end(h, t, su, (double)b * (double)b * (double)nc);
+      if (mr > 0) {
         int tile = -1;
         t = timer_begin(h, LUPP_PHASE_UPDATE, su);
-        LUPP_TRY(update<T>(h, su, 1, mr, nr - n1, b, A + kn + k * lda, lda, A + k + (kn + n1) * lda, lda,
-                           A + kn + (kn + n1) * lda, lda, &tile));
-        timer_end(h, t, su, 2.0 * (double)mr * (double)(nr - n1) * (double)b, tile == 1);
-      }
-      if (overlap) {
-        LUPP_TRY(hipEventRecord(h->ev_bulk, h->bulk));
-        LUPP_TRY(hipStreamWaitEvent(s, h->ev_bulk, 0));
-        LUPP_TRY(hipStreamWaitEvent(s, h->ev_panel, 0));
-      } else if (n1 > 0) {
-        LUPP_TRY(factor_block<T>(h, s, m, kn, bn, A, lda, ipiv, info));
+        LUPP_TRY(update<T>(h, su, 1, mr, nc, b, A + kn + k * lda, lda, A + k + c1 * lda, lda, A + kn + c1 * lda,
+                           lda, &tile));
+        timer_end(h, t, su, 2.0 * (double)mr * (double)nc * (double)b, tile == 1);
       }
     }
+    if (overlap) {
+      LUPP_TRY(hipEventRecord(h->ev_bulk, h->bulk));
+      LUPP_TRY(hipStreamWaitEvent(s, h->ev_bulk, 0));
+      LUPP_TRY(hipStreamWaitEvent(s, h->ev_panel, 0));
+    } else if (n1 > 0) {
+      LUPP_TRY(factor_block<T>(h, s, m, kn, bn, A, lda, ipiv, info));
+    }
+  }
+  if (defer && J >= 2) {
+    // every later step's interchanges on the finished blocks, one pass
+    const int t = timer_begin(h, LUPP_PHASE_LASWP, s);
+    int32_t* g = (int32_t*)((char*)h->defer_buf + (size_t)J * sizeof(SwapPairs));
+    int32_t* gmap = g + 2 * m;
+    LUPP_TRY(left_maps(s, step_pairs, J, m, h->nb, g, gmap));
+    LUPP_TRY(left_gather<T>(s, A, lda, m, h->nb, J, gmap));
+    timer_end(h, t, s, 0.0);
   }
   return hipSuccess;
 }
@@ -284,6 +314,30 @@ hipError_t ensure_trsv(lupp_handle_t h, int64_t n) {
   }
   t.epoch = 0;
   return hipSuccess;
+}
+
+bool ensure_defer(lupp_handle_t h, int64_t m, int64_t n, size_t elem) {
+  const int64_t p = m < n ? m : n;
+  const int64_t nb = h->nb;
+  const int64_t J = (p + nb - 1) / nb;
+  if (!h->defer || J < 2 || nb > kMaxSwaps || m - nb > left_gather_max_rows(elem) || (J - 1) * nb > 0x7fffffff)
+    return false;
+  const size_t bytes = (size_t)J * sizeof(SwapPairs) + sizeof(int32_t) * (size_t)(2 * m + left_map_entries(J, m, nb));
+  if (bytes > ((size_t)1 << 30)) return false;
+  if (bytes > h->defer_bytes) {
+    if (h->defer_buf) {
+      if (hipStreamSynchronize(h->stream) != hipSuccess) return false;
+      (void)hipFree(h->defer_buf);
+      h->defer_buf = nullptr;
+      h->defer_bytes = 0;
+    }
+    if (hipMalloc(&h->defer_buf, bytes) != hipSuccess) {
+      h->defer_buf = nullptr;
+      return false;
+    }
+    h->defer_bytes = bytes;
+  }
+  return true;
 }
 
 hipError_t ensure_workspace(lupp_handle_t h) {
@@ -397,6 +451,7 @@ int lupp_destroy(lupp_handle_t h) {
   if (h->side) (void)hipStreamDestroy(h->side);
   if (h->bulk) (void)hipStreamDestroy(h->bulk);
   if (h->slots) (void)hipFree(h->slots);
+  if (h->defer_buf) (void)hipFree(h->defer_buf);
   if (h->lp_scale[0]) (void)hipFree(h->lp_scale[0]);
   if (h->trsv.flags) (void)hipFree(h->trsv.flags);
   lupp::free_mixed(h);
@@ -433,6 +488,10 @@ int lupp_set_option(lupp_handle_t h, int option, int64_t value) {
     case LUPP_OPT_UPDATE_PREC:
       if (value < LUPP_PREC_FP32 || value > LUPP_PREC_FP8_E4M3) return -3;
       h->update_prec = (int)value;
+      return LUPP_OK;
+    case LUPP_OPT_DEFER_SWAPS:
+      if (value != 0 && value != 1) return -3;
+      h->defer = (int)value;
       return LUPP_OK;
     default:
       return -2;

@@ -187,3 +187,97 @@ def test_getrs_multi_rhs(dtype):
     for j in range(nrhs):
         assert checks.backward_error(A.astype(np.float64), X[:, j].astype(np.float64),
                                      B[:, j].astype(np.float64)) <= 8 * n * u
+
+
+def _factor_opts(A, **opts):
+    h = lupp.Handle()
+    for k, v in opts.items():
+        h.set_option({"nb": 1, "leaf": 2, "lookahead": 4, "defer": lupp._binding.OPT_DEFER_SWAPS}[k], v)
+    dA = to_dev(A)
+    ipiv, info = lupp.getrf(dA, handle=h)
+    h.sync()
+    torch.cuda.synchronize()
+    out = to_host(dA), ipiv.cpu().numpy(), int(info.item())
+    h.close()
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape,nb", [((1500, 1500), None), ((2000, 700), 64), ((700, 2000), 96),
+                                      ((3000, 1000), 128), ((1031, 1031), 100)])
+def test_deferred_interchanges_bit_identical(shape, nb, dtype):
+    """The finished columns' interchanges applied once at the end (composed per
+    column block) give exactly the factors of the per-step application."""
+    m, n = shape
+    announce("defer vs per-step %dx%d nb=%s %s" % (m, n, nb, dtype))
+    A = synth.uniform(9, 1, m, n)
+    if dtype == "f32":
+        A = A.astype(np.float32)
+    kw = {"nb": nb} if nb else {}
+    LU1, p1, i1 = _factor_opts(A, defer=1, **kw)
+    LU0, p0, i0 = _factor_opts(A, defer=0, **kw)
+    assert i1 == i0 and np.array_equal(p1, p0)
+    assert np.array_equal(LU1, LU0)
+    _check_against_oracle(A, LU1, p1, i1, checks.U64 if dtype == "f64" else checks.U32,
+                          tau=TAU if dtype == "f64" else 1e-4)
+
+
+@pytest.mark.parametrize("dtype,m", [("f64", 33300), ("f32", 33300)])
+def test_tall_deferral_limits(dtype, m):
+    """m - nb above the in-register column length of the deferred gather
+    (FP64: per-step interchanges instead) and the widest FP32 gather."""
+    n = 520
+    announce("tall %dx%d %s" % (m, n, dtype))
+    A = synth.uniform(10, 2, m, n)
+    if dtype == "f32":
+        A = A.astype(np.float32)
+    LU, ipiv, info = _factor_opts(A)
+    _check_against_oracle(A, LU, ipiv, info, checks.U64 if dtype == "f64" else checks.U32,
+                          tau=TAU if dtype == "f64" else 1e-4, nthreads=16)
+
+
+def test_wide_block_uncomposed_interchanges():
+    """nb above the composed-run limit (512): the per-column interchange path."""
+    n = 1400
+    announce("nb=600 n=%d" % n)
+    A = synth.uniform(10, 3, n, n)
+    LU, ipiv, info = _factor_opts(A, nb=600)
+    _check_against_oracle(A, LU, ipiv, info, checks.U64)
+
+
+def _replay(ipiv, B):
+    """Interchanges applied one by one, in order (the definition of row
+    interchange with a 1-based pivot vector)."""
+    X = B.copy()
+    for i, p in enumerate(ipiv):
+        p -= 1
+        if p != i:
+            X[[i, p]] = X[[p, i]]
+    return X
+
+
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_composed_interchanges_bit_exact(nrhs):
+    """getrs with L = U = I returns P*B: the composed runs of up to 512
+    interchanges must equal the sequential replay bit for bit, for pivot
+    vectors with long chains, repeated targets and rows inside the run."""
+    n = 1500
+    announce("composed interchanges n=%d nrhs=%d" % (n, nrhs))
+    rng = np.random.default_rng(77)
+    cases = {
+        "random": np.array([rng.integers(i, n) for i in range(n)]),
+        "last_row": np.full(n, n - 1),
+        "next_row": np.minimum(np.arange(n) + 1, n - 1),
+        "identity": np.arange(n),
+        "block_end": np.array([min(((i // 512) + 1) * 512 - 1, n - 1) for i in range(n)]),
+        "few_targets": np.array([max(i, [600, 601, 1499][i % 3]) for i in range(n)]),
+    }
+    I = np.eye(n)
+    dI = to_dev(I)
+    for name, piv0 in cases.items():
+        ipiv = (piv0 + 1).astype(np.int32)
+        B = rng.standard_normal((n, nrhs))
+        dB = to_dev(B)
+        lupp.getrs(dI, torch.from_numpy(ipiv).cuda(), dB)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(dB), _replay(ipiv, B)), name
