@@ -116,7 +116,6 @@ __global__ __launch_bounds__(NT) void k_panel_block(int64_t r, int wt, T* __rest
   __shared__ int s_broken;
   __shared__ int32_t s_ipiv[kBlockMaxWidth];
   __shared__ int32_t s_zero;
-  __shared__ uint32_t s_words[3 * kLeafMaxGroups];
   __shared__ T s_u[kBlockMaxWidth][W];  // the chunk's rows above the diagonal
 
   if (tid == 0) {
@@ -280,7 +279,9 @@ __global__ __launch_bounds__(NT) void k_panel_block(int64_t r, int wt, T* __rest
         const double lv = (rok && i >= jg) ? fabs((double)a[j]) : -1.0;
         const uint32_t li = (rok && i >= jg) ? (uint32_t)i : kNone;
         const double wm = wave_max_f64(lv);
-        const uint32_t wi = wave_min_u32((lv == wm) ? li : kNone);
+        // rows grow with the lane: the lowest lane holding the maximum has the lowest row
+        const uint64_t hit = __ballot(li != kNone && lv == wm);
+        const uint32_t wi = hit ? (uint32_t)__builtin_amdgcn_readlane((int)li, (int)__builtin_ctzll(hit)) : kNone;
         if ((uint32_t)i == wi) {
 #pragma unroll
           for (int c = 0; c < W; ++c) s_wrow[par][wave][c] = a[c];
@@ -294,19 +295,33 @@ __global__ __launch_bounds__(NT) void k_panel_block(int64_t r, int wt, T* __rest
           s_wi[par][wave] = wi;
         }
         lds_barrier();
-        // 2. the workgroup's candidate (every thread, the same order)
-        double bv = s_wv[par][0];
-        uint32_t bi = s_wi[par][0];
-        int bw = 0;
-#pragma unroll
-        for (int q = 1; q < NW; ++q) {
-          const double v = s_wv[par][q];
-          const uint32_t ii = s_wi[par][q];
-          if (v > bv || (v == bv && ii < bi)) {
-            bv = v;
-            bi = ii;
-            bw = q;
+        // 2. the workgroup's candidate (every thread, the same order): each
+        // 16-lane row of a wavefront reads the NW wavefront candidates and
+        // reduces them with four DPP steps
+        double bv;
+        uint32_t bi;
+        int bw;
+        {
+          static_assert(NW <= 16, "one wavefront candidate per lane of a 16-lane row");
+          const int q = lane & 15;
+          uint32_t khi = 0, klo = 0, kidx = kNone;
+          if (q < NW) {
+            const double v = s_wv[par][q];
+            const uint32_t ii = s_wi[par][q];
+            if (ii != kNone && v >= 0.0) {
+              const uint64_t vb = (uint64_t)__double_as_longlong(v);
+              khi = (uint32_t)(vb >> 32);
+              klo = (uint32_t)vb;
+              kidx = ii;
+            }
           }
+          dpp_step<0xB1>(khi, klo, kidx);
+          dpp_step<0x4E>(khi, klo, kidx);
+          dpp_step<0x141>(khi, klo, kidx);
+          dpp_step<0x140>(khi, klo, kidx);
+          bi = kidx;
+          bv = (kidx == kNone) ? -1.0 : __longlong_as_double((long long)(((uint64_t)khi << 32) | klo));
+          bw = (kidx == kNone) ? 0 : (int)((kidx - (uint32_t)g * NT) / 64u);
         }
         const T* prow;
         uint32_t pu;
@@ -335,16 +350,29 @@ __global__ __launch_bounds__(NT) void k_panel_block(int64_t r, int wt, T* __rest
               const uint64_t db = (uint64_t)__double_as_longlong((double)s_rowj[par][lane >> 1]);
               st_u64(&ws->rowj[par][lane], th | ((lane & 1) ? (uint32_t)db : (uint32_t)(db >> 32)));
             }
-            // (a) the G headers until every tag is current
-            const int nhead = 3 * G;
+            // (a) the G headers until every tag is current: lane q holds the
+            // three header words of workgroup q (and then of q + 64), loaded
+            // together, and keeps the better candidate
+            uint32_t khi = 0, klo = 0, kidx = kNone;
             if (!s_broken) {
               long spins = 0;
               for (;;) {
                 bool ok = true;
-                for (int e = lane; e < nhead; e += 64) {
-                  const uint64_t v = ld_u64(&ws->rec[par][e / 3][e % 3]);
-                  ok &= (uint32_t)(v >> 32) == tag;
-                  s_words[e] = (uint32_t)v;
+                khi = 0;
+                klo = 0;
+                kidx = kNone;
+                for (int q = lane; q < G; q += 64) {
+                  const uint64_t h0 = ld_u64(&ws->rec[par][q][0]);
+                  const uint64_t h1 = ld_u64(&ws->rec[par][q][1]);
+                  const uint64_t h2 = ld_u64(&ws->rec[par][q][2]);
+                  ok &= (uint32_t)(h0 >> 32) == tag && (uint32_t)(h1 >> 32) == tag && (uint32_t)(h2 >> 32) == tag;
+                  const uint32_t chi = (uint32_t)h0, clo = (uint32_t)h1, cidx = (uint32_t)h2;
+                  const double v = __longlong_as_double((long long)(((uint64_t)chi << 32) | clo));
+                  if (cidx != kNone && v >= 0.0 && key_better(chi, clo, cidx, khi, klo, kidx)) {
+                    khi = chi;
+                    klo = clo;
+                    kidx = cidx;
+                  }
                 }
                 if (__all(ok)) break;
                 if (++spins > kSpinLimit) {
@@ -356,19 +384,10 @@ __global__ __launch_bounds__(NT) void k_panel_block(int64_t r, int wt, T* __rest
                 }
               }
             }
-            double cv = -1.0;
-            uint32_t ci = kNone;
-            for (int q = lane; q < G; q += 64) {
-              const uint32_t* wq = &s_words[3 * q];
-              const double v = __longlong_as_double((long long)(((uint64_t)wq[0] << 32) | wq[1]));
-              const uint32_t ii = wq[2];
-              if (v > cv || (v == cv && ii < ci)) {
-                cv = v;
-                ci = ii;
-              }
-            }
-            const double gm = wave_max_f64(cv);
-            const uint32_t gi = wave_min_u32((cv == gm) ? ci : kNone);
+            double gv = kidx == kNone ? -1.0 : __longlong_as_double((long long)(((uint64_t)khi << 32) | klo));
+            int64_t gi64 = kidx == kNone ? INT64_MAX : (int64_t)kidx;
+            wave_argmax(gv, gi64);
+            const uint32_t gi = (gi64 == INT64_MAX) ? kNone : (uint32_t)gi64;
             const int gw = (gi == kNone) ? 0 : (int)((int64_t)gi / NT);
             // (b) the winner's row and (outside workgroup 0) row j, tag-checked
             const bool need = lane < 2 * W || (g != 0 && lane < 4 * W);
