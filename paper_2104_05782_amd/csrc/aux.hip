@@ -208,73 +208,6 @@ __global__ __launch_bounds__(256) void k_apply_pairs(T* __restrict__ A, int64_t 
   }
 }
 
-// B := inv(L) * B for a unit lower triangle of order w <= 256, one launch:
-// each workgroup owns 16 right-hand columns, held in registers (thread
-// (r, c) keeps rows r, r+16, ... of column c).  The triangle is processed in
-// 16-column chunks staged through LDS: the chunk's diagonal block is solved by
-// every thread of a column (16 values, redundantly, no cross-lane traffic),
-// then the rows below are updated with it.  Row i accumulates
-// b_i - sum_j l_ij x_j in increasing j, as plain forward substitution does.
-template <typename T>
-__global__ __launch_bounds__(256) void k_trsm_lower_band(int w, int64_t ncols, const T* __restrict__ L, int64_t ldl,
-                                                         T* __restrict__ B, int64_t ldb) {
-  constexpr int NC = 16, CH = 16, MAXW = kTrsmBandMaxW, NQ = MAXW / CH;
-  __shared__ T sL[CH][MAXW];
-  __shared__ T sX[NC][CH + 1];
-  const int tid = threadIdx.x;
-  const int r = tid & 15, cl = tid >> 4;
-  const int64_t c = (int64_t)blockIdx.x * NC + cl;
-  const bool cok = c < ncols;
-  T* bc = B + (cok ? c : 0) * ldb;
-  T x[NQ];
-#pragma unroll
-  for (int t = 0; t < NQ; ++t) {
-    const int i = t * CH + r;
-    x[t] = (cok && i < w) ? bc[i] : T(0);
-  }
-  const int nq = (w + CH - 1) / CH;
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    if (q < nq) {
-      const int j0 = q * CH;
-#pragma unroll
-      for (int kk = 0; kk < CH; ++kk) {
-        const int j = j0 + kk;
-        sL[kk][tid] = (tid >= j0 && tid < w && j < w) ? L[tid + (int64_t)j * ldl] : T(0);
-      }
-      sX[cl][r] = x[q];
-      __syncthreads();
-      T xs[CH];
-#pragma unroll
-      for (int i = 0; i < CH; ++i) xs[i] = sX[cl][i];
-#pragma unroll
-      for (int kk = 0; kk < CH; ++kk)
-#pragma unroll
-        for (int i = kk + 1; i < CH; ++i) xs[i] = xs[i] - sL[kk][j0 + i] * xs[kk];
-      T mine = xs[0];
-#pragma unroll
-      for (int i = 1; i < CH; ++i)
-        if (r == i) mine = xs[i];
-      x[q] = mine;
-#pragma unroll
-      for (int t = q + 1; t < NQ; ++t) {
-        if (t < nq) {
-#pragma unroll
-          for (int kk = 0; kk < CH; ++kk) x[t] = x[t] - sL[kk][t * CH + r] * xs[kk];
-        }
-      }
-      __syncthreads();
-    }
-  }
-  if (cok) {
-#pragma unroll
-    for (int t = 0; t < NQ; ++t) {
-      const int i = t * CH + r;
-      if (i < w) bc[i] = x[t];
-    }
-  }
-}
-
 // One thread per right-hand column, the triangle in LDS (read as broadcasts),
 // no barrier inside the substitution.  The column is solved in chunks of 16
 // rows: a chunk lives in registers, finished rows in LDS (each lane its own
@@ -430,18 +363,6 @@ hipError_t apply_pairs(hipStream_t s, T* A, int64_t lda, int64_t c0, int64_t c1,
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t trsm_lower_band(hipStream_t s, int64_t w, int64_t ncols, const T* L, int64_t ldl, T* B, int64_t ldb) {
-  if (w <= 0 || ncols <= 0) return hipSuccess;
-  if (w > kTrsmBandMaxW) return hipErrorInvalidValue;
-  const int64_t blocks = (ncols + 15) / 16;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_trsm_lower_band<T>, dim3((unsigned)blocks), dim3(256), 0, s, (int)w, ncols, L, ldl, B, ldb);
-  return hipGetLastError();
-}
-
-template hipError_t trsm_lower_band<double>(hipStream_t, int64_t, int64_t, const double*, int64_t, double*, int64_t);
-template hipError_t trsm_lower_band<float>(hipStream_t, int64_t, int64_t, const float*, int64_t, float*, int64_t);
 
 hipError_t left_maps(hipStream_t s, const SwapPairs* pairs, int64_t J, int64_t m, int64_t nb, int32_t* g,
                      int32_t* gmap) {

@@ -1,6 +1,5 @@
-// Trailing-update GEMM  C -= A * B  on MFMA (FP64: v_mfma_f64_4x4x4f64 for
-// the large tiles, FP32: v_mfma_f32_16x16x4f32), column-major operands of any
-// shape.
+// Trailing-update GEMM  C -= A * B  on MFMA (FP64: v_mfma_f64_16x16x4f64,
+// FP32: v_mfma_f32_16x16x4f32), column-major operands of any shape.
 //
 // This is the update A22 := A22 - A21 * U12 of the right-looking step, the
 // operation the paper identifies as the dominant cost of a blocked
@@ -13,9 +12,10 @@
 // LDS tiles (one barrier per step; the next step's global loads are issued
 // before the current step's MFMAs).  Edge tiles clamp their load addresses
 // into the matrix and zero the loaded value instead of branching, so every
-// load is unconditional.  The accumulators are loaded from C at the start and
-// A is negated while it is staged, so the MFMAs accumulate C - A*B directly
-// and the epilogue is a plain store (no read-modify-write latency at the end).
+// load is unconditional.  The accumulators are loaded from C at the start
+// (FP32: A negated while it is staged, so the MFMAs accumulate C - A*B;
+// FP64: from -C, accumulating A*B - C, stored negated), so the epilogue is a
+// plain store (no read-modify-write latency at the end).
 // Tiles are mapped XCD-aware: consecutive workgroup ids land on different XCDs
 // (round robin), so the id is first split into (xcd, slot) and each XCD walks
 // its own contiguous band of tiles in groups of 8 tile-rows, keeping the A
@@ -165,155 +165,12 @@ __global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_gemm_sub(int64_t M, int
   }
 }
 
-// FP64 variant on v_mfma_f64_4x4x4f64 (four independent 4x4x4 products per
-// instruction).  Lane L = x + 4b + 16y of an instruction holds A_b(x, y),
-// B_b(y, x) and C_b(y, x), b = 0..3.  The four blocks are arranged 2 x 2
-// (rb = b & 1 picks rows, cb = b >> 1 columns), so one instruction updates an
-// 8 x 8 piece of C, and a 64 x 64 wave tile needs 8 + 8 operand registers per
-// K-step of 4 for its 64 instructions.
-//
-// The K loop is peeled so that the next step's global loads are issued
-// unconditionally at the top of each iteration and consumed only by the LDS
-// stores at its bottom: the loads' latency overlaps the MFMAs.  Interior tiles
-// (the vast majority) run without any bounds masking; edge tiles clamp their
-// addresses and zero the values.
-template <int BM, int BN, int BK, int WGM, int WGN, bool EDGE>
-__device__ __forceinline__ void dgemm4_body(int64_t M, int64_t N, int64_t K, const double* __restrict__ A,
-                                            int64_t lda, const double* __restrict__ B, int64_t ldb,
-                                            double* __restrict__ C, int64_t ldc, int64_t m0, int64_t n0,
-                                            double* sA, double* sB) {
-  typedef double T;
-  constexpr int NT = 64 * WGM * WGN;
-  constexpr int WTM = BM / WGM, WTN = BN / WGN;
-  constexpr int RG = WTM / 8, CG = WTN / 8;
-  constexpr int PAD = 8;  // rows 1088 B apart: the four k-rows a wavefront reads hit distinct bank groups
-  constexpr int LDSA = BM + PAD, LDSB = BN + PAD;
-  constexpr int SA = BK * LDSA, SB = BK * LDSB;
-  constexpr int EA = BM * BK / NT, EB = BK * BN / NT;
-  constexpr int KA = NT / BM;
-  constexpr int NB_ = NT / BK;
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave % WGM, wn = wave / WGM;
-
-  // global load pointers: A rows ai, k-rows ak0 + KA*s; B k-row bk, columns bn0 + NB_*s
-  const int ai = tid % BM, ak0 = tid / BM;
-  const int bk = tid % BK, bn0 = tid / BK;
-  const bool arow_ok = !EDGE || (m0 + ai) < M;
-  const T* pa = A + (arow_ok ? (m0 + ai) : (M - 1)) + (int64_t)ak0 * lda;
-  const int64_t astep = (int64_t)KA * lda;
-  bool bcol_ok[EB];
-  const T* pb[EB];
-#pragma unroll
-  for (int s = 0; s < EB; ++s) {
-    const int64_t gn = n0 + bn0 + NB_ * s;
-    bcol_ok[s] = !EDGE || gn < N;
-    pb[s] = B + (bcol_ok[s] ? gn : (N - 1)) * ldb + bk;
-  }
-
-  T ra[EA], rb[EB];
-  auto gload = [&](int64_t k0) {
-    if (!EDGE) {
-      const T* q = pa + k0 * lda;
-#pragma unroll
-      for (int s = 0; s < EA; ++s) ra[s] = q[s * astep];
-#pragma unroll
-      for (int s = 0; s < EB; ++s) rb[s] = pb[s][k0];
-    } else {
-#pragma unroll
-      for (int s = 0; s < EA; ++s) {
-        const int64_t gk = k0 + ak0 + KA * s;
-        const int64_t gkc = gk < K ? gk : K - 1;
-        const T v = pa[(gkc - ak0) * lda];
-        ra[s] = (arow_ok && gk < K) ? v : T(0);
-      }
-      const int64_t gk = k0 + bk;
-      const bool kok = gk < K;
-      const int64_t off = (kok ? gk : K - 1) - bk;
-#pragma unroll
-      for (int s = 0; s < EB; ++s) {
-        const T v = pb[s][off];
-        rb[s] = (kok && bcol_ok[s]) ? v : T(0);
-      }
-    }
-  };
-  auto sstore = [&](int buf) {
-    T* a = sA + buf * SA + ak0 * LDSA + ai;
-    T* b = sB + buf * SB + bk * LDSB + bn0;
-#pragma unroll
-    for (int s = 0; s < EA; ++s) a[s * KA * LDSA] = ra[s];
-#pragma unroll
-    for (int s = 0; s < EB; ++s) b[s * NB_] = rb[s];
-  };
-
-  const int x = lane & 3, blk = (lane >> 2) & 3, y = lane >> 4;
-  const int rb_ = blk & 1, cb_ = blk >> 1;
-
-  // the accumulators start from -C (clamped addresses, zero outside), the
-  // MFMAs add A*B and the epilogue stores the negation: C - A*B exactly as if
-  // A had been negated, without any arithmetic between the loads and the LDS
-  T acc[RG][CG];
-#pragma unroll
-  for (int i = 0; i < RG; ++i) {
-    const int64_t row = m0 + wm * WTM + i * 8 + rb_ * 4 + y;
-    const int64_t rowc = (!EDGE || row < M) ? row : M - 1;
-#pragma unroll
-    for (int j = 0; j < CG; ++j) {
-      const int64_t col = n0 + wn * WTN + j * 8 + cb_ * 4 + x;
-      const int64_t colc = (!EDGE || col < N) ? col : N - 1;
-      const T v = C[rowc + colc * ldc];
-      acc[i][j] = (!EDGE || (row < M && col < N)) ? -v : T(0);
-    }
-  }
-
-  const int arow = wm * WTM + rb_ * 4 + x;
-  const int bcol = wn * WTN + cb_ * 4 + x;
-  auto compute = [&](int buf) {
-    const T* as = sA + buf * SA + y * LDSA + arow;
-    const T* bs = sB + buf * SB + y * LDSB + bcol;
-#pragma unroll
-    for (int kk = 0; kk < BK / 4; ++kk) {
-      T af[RG], bf[CG];
-#pragma unroll
-      for (int i = 0; i < RG; ++i) af[i] = as[kk * 4 * LDSA + i * 8];
-#pragma unroll
-      for (int j = 0; j < CG; ++j) bf[j] = bs[kk * 4 * LDSB + j * 8];
-#pragma unroll
-      for (int i = 0; i < RG; ++i)
-#pragma unroll
-        for (int j = 0; j < CG; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
-    }
-  };
-
-  const int KT = (int)((K + BK - 1) / BK);
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int kt = 0; kt + 1 < KT; ++kt) {
-    gload((int64_t)(kt + 1) * BK);
-    compute(kt & 1);
-    sstore((kt + 1) & 1);
-    __syncthreads();
-  }
-  compute((KT - 1) & 1);
-
-#pragma unroll
-  for (int i = 0; i < RG; ++i) {
-    const int64_t row = m0 + wm * WTM + i * 8 + rb_ * 4 + y;
-#pragma unroll
-    for (int j = 0; j < CG; ++j) {
-      const int64_t col = n0 + wn * WTN + j * 8 + cb_ * 4 + x;
-      if (!EDGE || (row < M && col < N)) C[row + col * ldc] = -acc[i][j];
-    }
-  }
-}
-
-// FP64 C -= A * B on v_mfma_f64_16x16x4f64.  Same pipeline as dgemm4_body
-// (double-buffered LDS, peeled K loop, accumulators from -C, interior tiles
-// unmasked); each wavefront owns a WTM x WTN tile of 16x16 products, 16
-// independent accumulators for a 64x64 tile, enough to keep the matrix core
-// busy with two wavefronts per SIMD.  The operands are passed swapped (B
-// first) so each lane holds 16 consecutive rows of a column of C.
+// FP64 C -= A * B on v_mfma_f64_16x16x4f64: double-buffered LDS, peeled K
+// loop, accumulators started from -C, interior tiles unmasked.  Each
+// wavefront owns a WTM x WTN tile of 16x16 products (16 independent
+// accumulators for a 64x64 tile, enough to keep the matrix core busy with two
+// wavefronts per SIMD).  The operands are passed swapped (B first), so each
+// lane holds 16 consecutive rows of a column of C and the stores coalesce.
 template <int BM, int BN, int BK, int WGM, int WGN, bool EDGE>
 __device__ __forceinline__ void dgemm16_body(int64_t M, int64_t N, int64_t K, const double* __restrict__ A,
                                              int64_t lda, const double* __restrict__ B, int64_t ldb,
@@ -471,35 +328,6 @@ __global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_dgemm_sub_16(int64_t M,
     dgemm16_body<BM, BN, BK, WGM, WGN, true>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sA, sB);
 }
 
-template <int BM, int BN, int BK, int WGM, int WGN, int MINB>
-__global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_dgemm_sub_4x4(int64_t M, int64_t N, int64_t K,
-                                                                       const double* __restrict__ A, int64_t lda,
-                                                                       const double* __restrict__ B, int64_t ldb,
-                                                                       double* __restrict__ C, int64_t ldc,
-                                                                       int tiles_m, int tiles_n) {
-  constexpr int PAD = 8;  // rows 1088 B apart: the four k-rows a wavefront reads hit distinct bank groups
-  __shared__ double sA[2 * BK * (BM + PAD)];
-  __shared__ double sB[2 * BK * (BN + PAD)];
-  const int total = tiles_m * tiles_n;
-  const int per_xcd = (total + kXcds - 1) / kXcds;
-  const int bid = blockIdx.x;
-  const int t = (bid % kXcds) * per_xcd + bid / kXcds;
-  if (t >= total) return;
-  const int group_size = kGroupM * tiles_n;
-  const int group = t / group_size;
-  const int first_m = group * kGroupM;
-  const int gm = min(tiles_m - first_m, kGroupM);
-  const int within = t - group * group_size;
-  const int tm = first_m + within % gm;
-  const int tn = within / gm;
-  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
-  const bool interior = (m0 + BM <= M) && (n0 + BN <= N) && (K % BK == 0);
-  if (interior)
-    dgemm4_body<BM, BN, BK, WGM, WGN, false>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sA, sB);
-  else
-    dgemm4_body<BM, BN, BK, WGM, WGN, true>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sA, sB);
-}
-
 namespace {
 
 template <typename T, int BM, int BN, int BK, int WGM, int WGN, int MINB>
@@ -522,18 +350,6 @@ hipError_t launch_d16(hipStream_t s, int64_t M, int64_t N, int64_t K, const doub
   const int total = (int)(tm * tn);
   const int per_xcd = (total + kXcds - 1) / kXcds;
   hipLaunchKernelGGL((k_dgemm_sub_16<BM, BN, BK, WGM, WGN, MINB>), dim3(per_xcd * kXcds), dim3(64 * WGM * WGN), 0,
-                     s, M, N, K, A, lda, B, ldb, C, ldc, (int)tm, (int)tn);
-  return hipGetLastError();
-}
-
-template <int BM, int BN, int BK, int WGM, int WGN, int MINB>
-hipError_t launch_d4(hipStream_t s, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
-                     int64_t ldb, double* C, int64_t ldc) {
-  const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
-  if (tm * tn > (int64_t)1 << 30) return hipErrorInvalidValue;
-  const int total = (int)(tm * tn);
-  const int per_xcd = (total + kXcds - 1) / kXcds;
-  hipLaunchKernelGGL((k_dgemm_sub_4x4<BM, BN, BK, WGM, WGN, MINB>), dim3(per_xcd * kXcds), dim3(64 * WGM * WGN), 0,
                      s, M, N, K, A, lda, B, ldb, C, ldc, (int)tm, (int)tn);
   return hipGetLastError();
 }

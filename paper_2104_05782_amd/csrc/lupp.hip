@@ -190,9 +190,11 @@ hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32
       LUPP_TRY(trsm_lower_unit<T>(s, b, n1, A + k + k * lda, lda, A + k + kn * lda, lda));
       timer_end(h, t, s, (double)b * (double)b * (double)n1);
       // columns of the next block first, so that it can be factored early
+      int tile = -1;
       t = timer_begin(h, LUPP_PHASE_UPDATE, s);
-      LUPP_TRY(update<T>(h, s, 0, mr, n1, b, A + kn + k * lda, lda, A + k + kn * lda, lda, A + kn + kn * lda, lda));
-      timer_end(h, t, s, 2.0 * (double)mr * (double)n1 * (double)b);
+      LUPP_TRY(update<T>(h, s, 0, mr, n1, b, A + kn + k * lda, lda, A + k + kn * lda, lda, A + kn + kn * lda, lda,
+                         &tile));
+      timer_end(h, t, s, 2.0 * (double)mr * (double)n1 * (double)b, tile == 1);
     }
     // overlap only when the next block's cooperative factorization fits in
     // the reserved CUs (one workgroup per CU at most)
