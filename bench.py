@@ -137,6 +137,78 @@ def mixed_leg(torch, lupp, A0, n, seed, fp64_ms, runs):
             "runs": out, "best_converged": best}
 
 
+def large_leg(torch, lupp, n, seed):
+    """FP8-update GMRES-IR solve against plain FP64 LUPP + solve at a large n,
+    on the diagonally dominant recipe drawn on the device (torch's seeded
+    generator: U(-0.5,0.5), then a_ii := sum_j |a_ij|), b iid U(-1,1)."""
+    g = torch.Generator(device="cuda").manual_seed(seed + 65536)
+    A0 = torch.empty((n, n), dtype=torch.float64, device="cuda").t()
+    A0.uniform_(-0.5, 0.5, generator=g)
+    d = A0.abs().sum(dim=1)
+    A0.diagonal().copy_(d)
+    del d
+    b = torch.empty((n, 1), dtype=torch.float64, device="cuda").uniform_(-1.0, 1.0, generator=g)
+    flops = 2.0 / 3.0 * float(n) ** 3
+
+    def eta(x):
+        r = b[:, 0] - torch.mv(A0, x)
+        den = A0.abs().sum(dim=1).max() * x.abs().max() + b.abs().max()
+        return float(r.abs().max() / den)
+
+    # plain FP64: factorization, then the solve (workspace set up by a small call first)
+    h = lupp.Handle()
+    small = torch.eye(64, dtype=torch.float64, device="cuda").t()  # column-major
+    ip_s = torch.empty(64, dtype=torch.int32, device="cuda")
+    in_s = torch.empty(1, dtype=torch.int32, device="cuda")
+    lupp.lupp_dgetrf(small, ip_s, in_s, handle=h)
+    A = torch.empty_like(A0.t()).t()  # column-major working copy
+    A.copy_(A0)
+    ipiv = torch.empty(n, dtype=torch.int32, device="cuda")
+    info = torch.empty(1, dtype=torch.int32, device="cuda")
+    x = b.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lupp.lupp_dgetrf(A, ipiv, info, handle=h)
+    h.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lupp.lupp_dgetrs(A, ipiv, x, handle=h)
+    h.sync()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fp64 = {"factor_ms": round((t1 - t0) * 1e3, 2), "solve_ms": round((t2 - t1) * 1e3, 2),
+            "wall_ms": round((t2 - t0) * 1e3, 2), "tflops": round(flops / (t1 - t0) / 1e12, 3),
+            "info": int(info.item()), "backward_error": eta(x[:, 0])}
+    log("large FP64: %s" % fp64)
+    h.close()
+    del A, x, ipiv, info
+    torch.cuda.empty_cache()
+
+    X = torch.empty((1, n), dtype=torch.float64, device="cuda").t()
+    h = lupp.Handle()
+    opts = lupp.ir_opts("gmres", factor_prec="fp8")
+    lupp.lupp_dgesv_mixed(A0, b, X, opts, handle=h)  # allocates the FP32 workspace: untimed
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = lupp.lupp_dgesv_mixed(A0, b, X, opts, handle=h)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    h.close()
+    mixed = {"factor_prec": "fp8", "solver": "gmres", "status": rep["status_name"], "iters": rep["iters"],
+             "inner_iters": rep["inner_iters"], "backward_error": rep["backward_error"],
+             "backward_error_check": eta(X[:, 0]), "factor_ms": round(rep["factor_ms"], 2),
+             "refine_ms": round(rep["refine_ms"], 2), "wall_ms": round(ms, 2),
+             "effective_tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+             "speedup_vs_fp64_solve": round(fp64["wall_ms"] / ms, 3)}
+    log("large mixed: %s" % mixed)
+    del A0, b, X
+    torch.cuda.empty_cache()
+    return {"workload": "diag-dominant n=%d (U(-0.5,0.5), a_ii = row abs-sum, drawn on the device from seed %d), "
+                        "b iid U(-1,1); FP8 (e4m3, per-block power-of-two scales) updates + FP64 GMRES-IR to 1e-14 "
+                        "vs plain FP64 LUPP + solve" % (n, seed + 65536),
+            "n": n, "fp64": fp64, "mixed": mixed}
+
+
 def batched_leg(torch, lupp, seed, count=20000, replays=20, dtype="f64", graph=True):
     import synth
     npdt = np.float64 if dtype == "f64" else np.float32
@@ -224,6 +296,8 @@ def main():
     ap.add_argument("--no-lookahead", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solve leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched small-systems leg")
+    ap.add_argument("--no-large", action="store_true", help="skip the large mixed-precision leg")
+    ap.add_argument("--large-n", type=int, default=65536)
     ap.add_argument("--profile-once", action="store_true",
                     help="counter runs: factor once without a pristine device copy, after a 1 GiB "
                          "device-to-device copy that calibrates the byte counters")
@@ -349,6 +423,13 @@ def main():
             batched = {"f64": batched_leg(torch, lupp, args.seed),
                        "f32": batched_leg(torch, lupp, args.seed, dtype="f32")}
 
+    large = None
+    if not args.no_large and not args.profile_once and args.dtype == "f64":
+        A = A0 = None  # release the headline size's matrices
+        torch.cuda.empty_cache()
+        log("large mixed-precision leg (n=%d)" % args.large_n)
+        large = large_leg(torch, lupp, args.large_n, args.seed)
+
     out = {
         "metric": "LU TFLOP/s @n=32768: FP64 vs mixed+IR at FP64 backward err; batched LUs/s",
         "value": round(value, 3),
@@ -372,6 +453,7 @@ def main():
         "check": check,
         "mixed": mixed,
         "batched": batched,
+        "large": large,
     }
     print(json.dumps(out), flush=True)
     h.close()
