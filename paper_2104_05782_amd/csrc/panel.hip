@@ -117,6 +117,7 @@ __global__ __launch_bounds__(NT) void k_panel_block(int64_t r, int wt, T* __rest
   __shared__ int32_t s_ipiv[kBlockMaxWidth];
   __shared__ int32_t s_zero;
   __shared__ T s_u[kBlockMaxWidth][W];  // the chunk's rows above the diagonal
+  __shared__ T s_lp[2][W][kBlockMaxWidth];  // workgroup 0: 16-column panels of L11, double-buffered
 
   if (tid == 0) {
     s_broken = 0;
@@ -165,35 +166,72 @@ __global__ __launch_bounds__(NT) void k_panel_block(int64_t r, int wt, T* __rest
     // ---- 2. left-looking update with the finished columns 0 .. c0-1
     if (c0 > 0) {
       if (g == 0) {
-        // rows 0 .. c0-1: U12 = inv(L11) A12, one row per step; row p is
-        // final when its turn comes and is broadcast through LDS
-        T lr[PF];
+        // rows 0 .. c0-1: U12 = inv(L11) A12 in 16-row blocks.  Panel b of
+        // L11 (rows 16b .. c0-1, columns 16b .. 16b+15) is staged in LDS, the
+        // next one's loads in flight meanwhile; 16 lanes solve the block's
+        // rows column-wise (x_i -= l_ik x_k in increasing k), then every row
+        // below subtracts the block's contribution in increasing k, so each
+        // row sees its terms in the order of plain forward substitution.
+        // The barriers wait for LDS traffic only, not for the loads in flight.
+        constexpr int PL = (W * kBlockMaxWidth) / NT;  // panel elements per thread
+        const int nbk = c0 / 16;
+        T pl[PL];
+        auto issue = [&](int b) {
 #pragma unroll
-        for (int u = 0; u < PF; ++u) lr[u] = (tid < c0 && u < c0) ? ldc(P + tid + (int64_t)u * ld) : T(0);
-        for (int pb = 0; pb < c0; pb += PF) {
-          T cur[PF];
-#pragma unroll
-          for (int u = 0; u < PF; ++u) cur[u] = lr[u];
-#pragma unroll
-          for (int u = 0; u < PF; ++u) {
-            const int p = pb + PF + u;
-            lr[u] = (tid < c0 && p < c0) ? ldc(P + tid + (int64_t)p * ld) : T(0);
+          for (int q = 0; q < PL; ++q) {
+            const int e = tid + q * NT;
+            const int kk = e / kBlockMaxWidth, row = 16 * b + (e % kBlockMaxWidth);
+            pl[q] = (row < c0) ? ldc(P + row + (int64_t)(16 * b + kk) * ld) : T(0);
           }
+        };
+        auto place = [&](int buf) {
 #pragma unroll
-          for (int u = 0; u < PF; ++u) {
-            const int p = pb + u;
-            if (p < c0) {
-              if (tid == p) {
+          for (int q = 0; q < PL; ++q) {
+            const int e = tid + q * NT;
+            s_lp[buf][e / kBlockMaxWidth][e % kBlockMaxWidth] = pl[q];
+          }
+        };
+        issue(0);
+        if (tid < c0) {
 #pragma unroll
-                for (int c = 0; c < W; ++c) s_u[p][c] = a[c];
-              }
-              lds_barrier();
-              if (tid > p && tid < c0) {
+          for (int c = 0; c < W; ++c) s_u[tid][c] = a[c];
+        }
+        place(0);
+        lds_barrier();
+        for (int bb = 0; bb < nbk; ++bb) {
+          const int buf = bb & 1, row0 = 16 * bb;
+          if (bb + 1 < nbk) issue(bb + 1);
+          if (tid < 16 * W) {
+            // thread (ii, c) = (tid & 15, tid >> 4) holds row row0+ii of column
+            // c; step kk broadcasts row kk inside the 16-lane row
+            const int ii = tid & 15, c = tid >> 4;
+            T x = s_u[row0 + ii][c];
+            static_for<0, 16>([&](auto kc) {
+              constexpr int kk = decltype(kc)::value;
+              const T xk = row_bcast<kk>(x);
+              const T nx = x - s_lp[buf][kk][ii] * xk;
+              x = (ii > kk) ? nx : x;
+            });
+            s_u[row0 + ii][c] = x;
+          }
+          lds_barrier();
+          if (tid >= row0 + 16 && tid < c0) {
 #pragma unroll
-                for (int c = 0; c < W; ++c) a[c] = a[c] - cur[u] * s_u[p][c];
-              }
+            for (int kk = 0; kk < 16; ++kk) {
+              const T l = s_lp[buf][kk][tid - row0];
+#pragma unroll
+              for (int c = 0; c < W; ++c) a[c] = a[c] - l * s_u[row0 + kk][c];
+              __builtin_amdgcn_sched_barrier(0);
             }
+#pragma unroll
+            for (int c = 0; c < W; ++c) s_u[tid][c] = a[c];
           }
+          if (bb + 1 < nbk) place(buf ^ 1);
+          lds_barrier();
+        }
+        if (tid < c0) {
+#pragma unroll
+          for (int c = 0; c < W; ++c) a[c] = s_u[tid][c];
         }
         // publish U12 for the other workgroups
         if (tid < c0) {

@@ -2,33 +2,11 @@
 // w <= 256) for many right-hand columns in one launch: U12 := inv(L11) * A12
 // of the right-looking step (the paper's TRSM, Section 3.2), and the same
 // inside the recursive column-block factorization.
-#include <type_traits>
-
 #include "common.h"
+#include "wave.h"
 
 namespace lupp {
 namespace {
-
-// Lane k's value in every lane of its 16-lane row (DPP row broadcast).
-template <int K>
-__device__ __forceinline__ double row_bcast(double v) {
-  const uint64_t u = (uint64_t)__double_as_longlong(v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, 0x150 + K, 0xF, 0xF, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), 0x150 + K, 0xF, 0xF, false);
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-template <int K>
-__device__ __forceinline__ float row_bcast(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + K, 0xF, 0xF, false));
-}
-
-template <int K, int N, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (K < N) {
-    f(std::integral_constant<int, K>());
-    static_for<K + 1, N>(f);
-  }
-}
 
 // B := inv(L) * B for a unit lower triangle of order w <= 256, one launch.
 // Lane (r, grp) of a wavefront holds rows r, r+16, ..., r+240 of CPT

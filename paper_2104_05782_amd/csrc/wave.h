@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lupp {
 
 // Wavefront argmax of (|a|, row) under the total order (|a| desc, row asc).
@@ -110,6 +112,27 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
   m = min(m, (uint32_t)__builtin_amdgcn_readlane((int)v, 16));
   m = min(m, (uint32_t)__builtin_amdgcn_readlane((int)v, 32));
   return min(m, (uint32_t)__builtin_amdgcn_readlane((int)v, 48));
+}
+
+// Lane k's value in every lane of its 16-lane row (DPP row broadcast).
+template <int K>
+__device__ __forceinline__ double row_bcast(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, 0x150 + K, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), 0x150 + K, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+template <int K>
+__device__ __forceinline__ float row_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + K, 0xF, 0xF, false));
+}
+
+template <int K, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (K < N) {
+    f(std::integral_constant<int, K>());
+    static_for<K + 1, N>(f);
+  }
 }
 
 }  // namespace lupp
