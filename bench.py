@@ -387,7 +387,7 @@ def main():
     achieved = (fl / (ms * 1e-3) / 1e12) if ms > 0 else 0.0
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": None,
-                "kernel": ("k_dgemm_sub_16<128,128,8,2,2,2>" if args.dtype == "f64" else "k_gemm_sub<float,128,128,16,2,2,2>"),
+                "kernel": ("k_dgemm_sub_16<128,128,8,2,2,2,0>" if args.dtype == "f64" else "k_gemm_sub<float,128,128,16,2,2,2>"),
                 "launches_per_step": c // max(1, args.steps),
                 "avg_launch_ms": round(ms / max(1, c), 4),
                 "flops_per_launch": fl / max(1, c)}

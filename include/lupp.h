@@ -63,12 +63,17 @@ enum {
                               update A22 -= A21*U12, one of LUPP_PREC_* (default FP32).  The
                               column-block factorization and U12 stay FP32; the products are
                               accumulated in FP32 and A22 is stored in FP32.               */
-  LUPP_OPT_DEFER_SWAPS = 6 /* 1 (default): the interchanges of every step reach the finished
+  LUPP_OPT_DEFER_SWAPS = 6, /* 1 (default): the interchanges of every step reach the finished
                               columns on its left once, at the end, composed into one row
                               permutation per column block (same result, one pass instead
                               of one per step; needs a workspace of about 2*m*n/nb bytes,
                               nb <= 512 and m - nb <= 32768 for FP64 or 65536 for FP32,
                               otherwise ignored); 0: at every step, as in LAPACK            */
+  LUPP_OPT_SPLIT_UPDATE = 7 /* 1 (default, with lookahead): once the next column block is
+                              factored, its CUs take the last columns of the remaining
+                              update (sized from the measured panel time and GEMM rate, so
+                              that both shares end together); 0: the bulk CUs take it all.
+                              FP64/FP32 results are identical either way                 */
 };
 
 /* Operand formats of the trailing update (LUPP_OPT_UPDATE_PREC) and of the

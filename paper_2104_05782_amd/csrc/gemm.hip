@@ -300,7 +300,9 @@ __device__ __forceinline__ void dgemm16_body(int64_t M, int64_t N, int64_t K, co
   }
 }
 
-template <int BM, int BN, int BK, int WGM, int WGN, int MINB>
+// ROLE only names the launch: 0 for updates on the main and bulk streams, 1
+// for the share of the remaining-columns update run on the panel's CUs.
+template <int BM, int BN, int BK, int WGM, int WGN, int MINB, int ROLE>
 __global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_dgemm_sub_16(int64_t M, int64_t N, int64_t K,
                                                                       const double* __restrict__ A, int64_t lda,
                                                                       const double* __restrict__ B, int64_t ldb,
@@ -342,14 +344,14 @@ hipError_t launch(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, in
   return hipGetLastError();
 }
 
-template <int BM, int BN, int BK, int WGM, int WGN, int MINB>
+template <int BM, int BN, int BK, int WGM, int WGN, int MINB, int ROLE = 0>
 hipError_t launch_d16(hipStream_t s, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
                       int64_t ldb, double* C, int64_t ldc) {
   const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
   if (tm * tn > (int64_t)1 << 30) return hipErrorInvalidValue;
   const int total = (int)(tm * tn);
   const int per_xcd = (total + kXcds - 1) / kXcds;
-  hipLaunchKernelGGL((k_dgemm_sub_16<BM, BN, BK, WGM, WGN, MINB>), dim3(per_xcd * kXcds), dim3(64 * WGM * WGN), 0,
+  hipLaunchKernelGGL((k_dgemm_sub_16<BM, BN, BK, WGM, WGN, MINB, ROLE>), dim3(per_xcd * kXcds), dim3(64 * WGM * WGN), 0,
                      s, M, N, K, A, lda, B, ldb, C, ldc, (int)tm, (int)tn);
   return hipGetLastError();
 }
@@ -358,7 +360,7 @@ hipError_t launch_d16(hipStream_t s, int64_t M, int64_t N, int64_t K, const doub
 
 template <typename T>
 hipError_t gemm_sub(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B,
-                    int64_t ldb, T* C, int64_t ldc, int* tile_out) {
+                    int64_t ldb, T* C, int64_t ldc, int* tile_out, bool side) {
   int dummy;
   int& tile = tile_out ? *tile_out : dummy;
   tile = -1;
@@ -369,8 +371,9 @@ hipError_t gemm_sub(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, 
   }
   const int64_t big_tiles = ((M + 127) / 128) * ((N + 127) / 128);
   if constexpr (sizeof(T) == 8) {
-    if (big_tiles >= 256) {
+    if (big_tiles >= 256 || (side && big_tiles >= 32)) {
       tile = 1;
+      if (side) return launch_d16<128, 128, 8, 2, 2, 2, 1>(s, M, N, K, A, lda, B, ldb, C, ldc);
       return launch_d16<128, 128, 8, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
     }
     tile = 2;
@@ -386,8 +389,8 @@ hipError_t gemm_sub(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, 
 }
 
 template hipError_t gemm_sub<double>(hipStream_t, int64_t, int64_t, int64_t, const double*, int64_t,
-                                     const double*, int64_t, double*, int64_t, int*);
+                                     const double*, int64_t, double*, int64_t, int*, bool);
 template hipError_t gemm_sub<float>(hipStream_t, int64_t, int64_t, int64_t, const float*, int64_t,
-                                    const float*, int64_t, float*, int64_t, int*);
+                                    const float*, int64_t, float*, int64_t, int*, bool);
 
 }  // namespace lupp

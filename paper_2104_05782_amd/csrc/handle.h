@@ -36,12 +36,24 @@ struct lupp_handle_st {
   hipStream_t side = nullptr;       // panel stream, restricted to panel_cus CUs
   hipStream_t bulk = nullptr;       // trailing-update stream, restricted to the other CUs
   int panel_cus = 0;                // CUs reserved for the panel while they overlap
+  int ncu = 0;                      // compute units of the device
   hipEvent_t ev_cols = nullptr;     // next block's columns updated (main -> side, bulk)
   hipEvent_t ev_panel = nullptr;    // next block factored (side -> main)
   hipEvent_t ev_bulk = nullptr;     // bulk update done (bulk -> main)
+  hipEvent_t ev_trsm = nullptr;     // remaining columns interchanged and solved (bulk -> side)
+  // split of the remaining-columns update between the bulk CUs and the panel's
+  // CUs once the panel is done: sized from the panel time and the per-CU GEMM
+  // rate, both measured on earlier steps (events read only once complete)
+  int split = 1;
+  hipEvent_t tm_ev[2][4] = {};      // per slot: panel start/end, bulk update start/end
+  double tm_flops[2] = {0.0, 0.0};  // flops of that bulk update
+  bool tm_pending[2] = {false, false};
+  int tm_slot = 0;
+  double est_panel_ms = -1.0;       // measured column-block time (ms), < 0 before the first
+  double est_rate = -1.0;           // measured bulk GEMM flops per ms per CU, < 0 before the first
   int update_prec = 0;              // LUPP_PREC_* of sgetrf's trailing update
-  int* lp_scale[2] = {nullptr, nullptr};  // block exponents: next-block and bulk updates
-  int64_t lp_scale_cap = 0;         // ints in each of lp_scale[0], lp_scale[1]
+  int* lp_scale[3] = {nullptr, nullptr, nullptr};  // block exponents: next-block, bulk and side updates
+  int64_t lp_scale_cap = 0;         // ints in each of lp_scale[0..2]
   lupp::TrsvState trsv{};           // one-launch triangular solve state (flags on demand)
   lupp::MixedWs* mixed = nullptr;   // workspace of lupp_dgesv_mixed
   lupp::BatchWs* batch = nullptr;   // workspace and streams of the batched path

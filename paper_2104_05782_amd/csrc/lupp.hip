@@ -119,7 +119,8 @@ hipError_t panel(lupp_handle_t h, hipStream_t s, int64_t m, int64_t k, int64_t w
 // Trailing update C -= A * B of the outer loop: FP64 and FP32 on the MFMA GEMM
 // of the working precision, or (FP32 factorization with a low-precision update
 // format) on the low-precision GEMM; `which` selects the scale workspace of
-// the two updates that may run concurrently (next block, bulk).
+// the updates that may run concurrently (0: next block, 1: bulk, 2: the
+// bulk's share on the panel's CUs).
 template <typename T>
 hipError_t update(lupp_handle_t h, hipStream_t s, int which, int64_t M, int64_t N, int64_t K, const T* A,
                   int64_t lda, const T* B, int64_t ldb, T* C, int64_t ldc, int* tile = nullptr) {
@@ -129,7 +130,48 @@ hipError_t update(lupp_handle_t h, hipStream_t s, int which, int64_t M, int64_t 
       return gemm_lp_sub(s, h->update_prec, M, N, K, A, lda, B, ldb, C, ldc, h->lp_scale[which]);
     }
   }
-  return gemm_sub<T>(s, M, N, K, A, lda, B, ldb, C, ldc, tile);
+  return gemm_sub<T>(s, M, N, K, A, lda, B, ldb, C, ldc, tile, which == 2);
+}
+
+// Reads the panel and bulk-update times of an earlier step once its events
+// have completed (never waits), and keeps running estimates.
+void harvest_split_timings(lupp_handle_t h) {
+  for (int o = 0; o < 2; ++o) {
+    if (!h->tm_pending[o]) continue;
+    const hipError_t q1 = hipEventQuery(h->tm_ev[o][1]);
+    const hipError_t q3 = hipEventQuery(h->tm_ev[o][3]);
+    (void)hipGetLastError();  // a not-ready query is not an error of the factorization
+    if (q1 != hipSuccess || q3 != hipSuccess) continue;
+    float pm = 0.f, bm = 0.f;
+    if (hipEventElapsedTime(&pm, h->tm_ev[o][0], h->tm_ev[o][1]) == hipSuccess &&
+        hipEventElapsedTime(&bm, h->tm_ev[o][2], h->tm_ev[o][3]) == hipSuccess && bm > 0.f) {
+      h->est_panel_ms = h->est_panel_ms < 0 ? pm : 0.5 * (h->est_panel_ms + pm);
+      const double rate = h->tm_flops[o] / ((double)bm * (double)(h->ncu - h->panel_cus));
+      h->est_rate = h->est_rate < 0 ? rate : 0.5 * (h->est_rate + rate);
+    }
+    (void)hipGetLastError();
+    h->tm_pending[o] = false;
+  }
+}
+
+// Columns of the remaining-columns update (nc columns, M x nc x K) to run on
+// the panel's CUs after the panel, so that both shares end together: with
+// bulk CUs B, panel CUs S, panel time P and per-CU rate R, the bulk share f
+// of the W flops solves f W / (B R) = P + (1 - f) W / (S R).  Zero when the
+// panel alone outlasts the whole update.
+int64_t side_columns(lupp_handle_t h, int64_t M, int64_t nc, int64_t K, bool fp64) {
+  const double B = (double)(h->ncu - h->panel_cus), S = (double)h->panel_cus;
+  if (B <= 0 || S <= 0) return 0;
+  const double P = h->est_panel_ms >= 0 ? h->est_panel_ms : (fp64 ? 2.3 : 1.8) * (double)K / 256.0;
+  double R = h->est_rate;
+  if (R <= 0) R = fp64 ? 2.0e8 : (h->update_prec != LUPP_PREC_FP32 ? 6.0e8 : 3.0e8);
+  const double W = 2.0 * (double)M * (double)nc * (double)K;
+  if (W / (B * R) <= P) return 0;
+  const double f = (P * R + W / S) / (W * (1.0 / B + 1.0 / S));
+  int64_t ns = (int64_t)((1.0 - f) * (double)nc);
+  ns = (ns / 128) * 128;
+  if (ns < 256 || ns > nc - 128) return 0;
+  return ns;
 }
 
 // Column block [k, k+b): factor it on stream st, with its phase timing.
@@ -200,12 +242,18 @@ hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32
     // the reserved CUs (one workgroup per CU at most)
     const bool overlap = la && n1 > 0 && panel_groups(mr) <= h->panel_cus && nr > n1;
     hipStream_t su = s;
+    int slot = -1;  // timing slot of this step's panel and bulk update, if measured
     if (overlap) {
       LUPP_TRY(hipEventRecord(h->ev_cols, s));
       LUPP_TRY(hipStreamWaitEvent(h->side, h->ev_cols, 0));
       LUPP_TRY(hipStreamWaitEvent(h->bulk, h->ev_cols, 0));
+      if (h->split) {
+        harvest_split_timings(h);
+        if (!h->tm_pending[h->tm_slot]) slot = h->tm_slot;
+      }
+      if (slot >= 0) LUPP_TRY(hipEventRecord(h->tm_ev[slot][0], h->side));
       LUPP_TRY(factor_block<T>(h, h->side, m, kn, bn, A, lda, ipiv, info));
-      LUPP_TRY(hipEventRecord(h->ev_panel, h->side));
+      if (slot >= 0) LUPP_TRY(hipEventRecord(h->tm_ev[slot][1], h->side));
       su = h->bulk;
     }
     if (nr > n1) {
@@ -219,14 +267,37 @@ hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32
       LUPP_TRY(trsm_lower_unit<T>(su, b, nc, A + k + k * lda, lda, A + k + c1 * lda, lda));
       timer_end(h, t, su, (double)b * (double)b * (double)nc);
       if (mr > 0) {
+        // the bulk CUs take the first columns; once the next block is
+        // factored, the panel's CUs take the last ones
+        const int64_t nside = (overlap && h->split) ? side_columns(h, mr, nc, b, sizeof(T) == 8) : 0;
+        const int64_t nbulk = nc - nside;
+        if (nside > 0) {
+          LUPP_TRY(hipEventRecord(h->ev_trsm, su));
+          LUPP_TRY(hipStreamWaitEvent(h->side, h->ev_trsm, 0));
+        }
         int tile = -1;
+        if (slot >= 0) LUPP_TRY(hipEventRecord(h->tm_ev[slot][2], su));
         t = timer_begin(h, LUPP_PHASE_UPDATE, su);
-        LUPP_TRY(update<T>(h, su, 1, mr, nc, b, A + kn + k * lda, lda, A + k + c1 * lda, lda, A + kn + c1 * lda,
+        LUPP_TRY(update<T>(h, su, 1, mr, nbulk, b, A + kn + k * lda, lda, A + k + c1 * lda, lda, A + kn + c1 * lda,
                            lda, &tile));
-        timer_end(h, t, su, 2.0 * (double)mr * (double)nc * (double)b, tile == 1);
+        timer_end(h, t, su, 2.0 * (double)mr * (double)nbulk * (double)b, tile == 1);
+        if (slot >= 0) {
+          LUPP_TRY(hipEventRecord(h->tm_ev[slot][3], su));
+          h->tm_flops[slot] = 2.0 * (double)mr * (double)nbulk * (double)b;
+          h->tm_pending[slot] = true;
+          h->tm_slot ^= 1;
+        }
+        if (nside > 0) {
+          const int64_t c2 = c1 + nbulk;
+          t = timer_begin(h, LUPP_PHASE_UPDATE, h->side);
+          LUPP_TRY(update<T>(h, h->side, 2, mr, nside, b, A + kn + k * lda, lda, A + k + c2 * lda, lda,
+                             A + kn + c2 * lda, lda));
+          timer_end(h, t, h->side, 2.0 * (double)mr * (double)nside * (double)b);
+        }
       }
     }
     if (overlap) {
+      LUPP_TRY(hipEventRecord(h->ev_panel, h->side));
       LUPP_TRY(hipEventRecord(h->ev_bulk, h->bulk));
       LUPP_TRY(hipStreamWaitEvent(s, h->ev_bulk, 0));
       LUPP_TRY(hipStreamWaitEvent(s, h->ev_panel, 0));
@@ -281,13 +352,15 @@ hipError_t ensure_lp_scale(lupp_handle_t h, int64_t m, int64_t n) {
   if (need <= h->lp_scale_cap) return hipSuccess;
   LUPP_TRY(hipStreamSynchronize(h->stream));
   if (h->bulk) LUPP_TRY(hipStreamSynchronize(h->bulk));
+  if (h->side) LUPP_TRY(hipStreamSynchronize(h->side));
   if (h->lp_scale[0]) (void)hipFree(h->lp_scale[0]);
-  h->lp_scale[0] = h->lp_scale[1] = nullptr;
+  h->lp_scale[0] = h->lp_scale[1] = h->lp_scale[2] = nullptr;
   h->lp_scale_cap = 0;
   void* p = nullptr;
-  LUPP_TRY(hipMalloc(&p, (size_t)need * 2 * sizeof(int)));
+  LUPP_TRY(hipMalloc(&p, (size_t)need * 3 * sizeof(int)));
   h->lp_scale[0] = (int*)p;
   h->lp_scale[1] = (int*)p + need;
+  h->lp_scale[2] = (int*)p + 2 * need;
   h->lp_scale_cap = need;
   return hipSuccess;
 }
@@ -373,8 +446,13 @@ hipError_t ensure_workspace(lupp_handle_t h) {
   if (hipExtStreamCreateWithCUMask(&h->bulk, (uint32_t)mbulk.size(), mbulk.data()) != hipSuccess) h->bulk = nullptr;
   if (!h->side || !h->bulk || hipEventCreateWithFlags(&h->ev_cols, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_bulk, hipEventDisableTiming) != hipSuccess)
+      hipEventCreateWithFlags(&h->ev_bulk, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_trsm, hipEventDisableTiming) != hipSuccess)
     h->lookahead = 0;
+  h->ncu = ncu;
+  for (int o = 0; o < 2; ++o)
+    for (int e = 0; e < 4; ++e)
+      if (hipEventCreate(&h->tm_ev[o][e]) != hipSuccess) h->split = 0;
   return hipSuccess;
 }
 
@@ -450,6 +528,10 @@ int lupp_destroy(lupp_handle_t h) {
   if (h->ev_cols) (void)hipEventDestroy(h->ev_cols);
   if (h->ev_panel) (void)hipEventDestroy(h->ev_panel);
   if (h->ev_bulk) (void)hipEventDestroy(h->ev_bulk);
+  if (h->ev_trsm) (void)hipEventDestroy(h->ev_trsm);
+  for (int o = 0; o < 2; ++o)
+    for (int e = 0; e < 4; ++e)
+      if (h->tm_ev[o][e]) (void)hipEventDestroy(h->tm_ev[o][e]);
   if (h->side) (void)hipStreamDestroy(h->side);
   if (h->bulk) (void)hipStreamDestroy(h->bulk);
   if (h->slots) (void)hipFree(h->slots);
@@ -494,6 +576,10 @@ int lupp_set_option(lupp_handle_t h, int option, int64_t value) {
     case LUPP_OPT_DEFER_SWAPS:
       if (value != 0 && value != 1) return -3;
       h->defer = (int)value;
+      return LUPP_OK;
+    case LUPP_OPT_SPLIT_UPDATE:
+      if (value != 0 && value != 1) return -3;
+      h->split = (int)value;
       return LUPP_OK;
     default:
       return -2;

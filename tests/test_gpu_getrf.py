@@ -281,3 +281,71 @@ def test_composed_interchanges_bit_exact(nrhs):
         lupp.getrs(dI, torch.from_numpy(ipiv).cuda(), dB)
         torch.cuda.synchronize()
         assert np.array_equal(to_host(dB), _replay(ipiv, B)), name
+
+
+def _probe_residual(A0, LU, ipiv, nprobe=4, seed=3):
+    """max over probes of ||P A x - L (U x)||_inf / (n ||A||_inf ||x||_inf) on the GPU (FP64)."""
+    n = A0.shape[0]
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    L = torch.tril(LU, -1) + torch.eye(n, dtype=LU.dtype, device="cuda")
+    U = torch.triu(LU)
+    perm = torch.arange(n, device="cuda")
+    piv = ipiv.long() - 1
+    p_host = perm.cpu().numpy()
+    for i, p in enumerate(piv.cpu().numpy()):
+        p_host[i], p_host[p] = p_host[p], p_host[i]
+    P = torch.from_numpy(p_host).cuda()
+    anorm = A0.abs().sum(dim=1).max()
+    worst = 0.0
+    for _ in range(nprobe):
+        x = torch.rand(n, 1, generator=g, dtype=A0.dtype, device="cuda") * 2 - 1
+        r = (A0 @ x)[P] - L @ (U @ x)
+        worst = max(worst, float(r.abs().max() / (n * anorm * x.abs().max())))
+    return worst
+
+
+def _factor_dev(A0, **opts):
+    h = lupp.Handle()
+    for k, v in opts.items():
+        h.set_option({"nb": 1, "timing": 3, "split": lupp._binding.OPT_SPLIT_UPDATE,
+                      "prec": lupp._binding.OPT_UPDATE_PREC}[k], v)
+    A = torch.empty_like(A0.t()).t()
+    A.copy_(A0)
+    ipiv = torch.empty(A0.shape[0], dtype=torch.int32, device="cuda")
+    info = torch.empty(1, dtype=torch.int32, device="cuda")
+    (lupp.lupp_dgetrf if A0.dtype == torch.float64 else lupp.lupp_sgetrf)(A, ipiv, info, handle=h)
+    h.sync()
+    updates = h.timing_summary("update")[0] if opts.get("timing") else None
+    h.close()
+    return A, ipiv, int(info.item()), updates
+
+
+def test_split_update_bit_identical():
+    """n = 16384: the remaining-columns update shared with the panel's CUs
+    gives the same factors bit for bit, and the split does happen."""
+    n = 16384
+    announce("split update n=%d fp64" % n)
+    g = torch.Generator(device="cuda").manual_seed(41)
+    A0 = torch.empty((n, n), dtype=torch.float64, device="cuda").t()
+    A0.uniform_(-1.0, 1.0, generator=g)
+    A1, p1, i1, u1 = _factor_dev(A0, split=1, timing=1)
+    A2, p2, i2, u2 = _factor_dev(A0, split=0, timing=1)
+    assert i1 == i2 == 0
+    assert u1 > u2, (u1, u2)  # extra launches on the panel's CUs
+    assert torch.equal(p1, p2)
+    assert torch.equal(A1, A2)
+    assert _probe_residual(A0, A1, p1) < 10 * checks.U64
+
+
+def test_split_update_low_precision():
+    """The same split with BF16 updates (each share scales its own blocks):
+    a valid factorization within the update format's residual bound."""
+    n = 16384
+    announce("split update n=%d bf16 updates" % n)
+    g = torch.Generator(device="cuda").manual_seed(42)
+    A0 = torch.empty((n, n), dtype=torch.float32, device="cuda").t()
+    A0.uniform_(-1.0, 1.0, generator=g)
+    A1, p1, i1, _ = _factor_dev(A0, split=1, prec=lupp.PREC["bf16"])
+    assert i1 == 0
+    assert float(torch.tril(A1, -1).abs().max()) <= 1.0
+    assert _probe_residual(A0.double(), A1.double(), p1) < 10 * 2.0 ** -8
