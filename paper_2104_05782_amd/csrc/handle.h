@@ -36,6 +36,9 @@ struct lupp_handle_st {
   hipStream_t side = nullptr;       // panel stream, restricted to panel_cus CUs
   hipStream_t bulk = nullptr;       // trailing-update stream, restricted to the other CUs
   int panel_cus = 0;                // CUs reserved for the panel while they overlap
+  hipStream_t side2 = nullptr;      // the same pair for panels of up to 64 workgroups
+  hipStream_t bulk2 = nullptr;
+  int panel_cus2 = 0;
   int ncu = 0;                      // compute units of the device
   hipEvent_t ev_cols = nullptr;     // next block's columns updated (main -> side, bulk)
   hipEvent_t ev_panel = nullptr;    // next block factored (side -> main)
@@ -47,9 +50,10 @@ struct lupp_handle_st {
   int split = 1;
   hipEvent_t tm_ev[2][4] = {};      // per slot: panel start/end, bulk update start/end
   double tm_flops[2] = {0.0, 0.0};  // flops of that bulk update
+  int tm_pair[2] = {0, 0};          // stream pair of that step (0: 32 panel CUs, 1: 64)
   bool tm_pending[2] = {false, false};
   int tm_slot = 0;
-  double est_panel_ms = -1.0;       // measured column-block time (ms), < 0 before the first
+  double est_panel_ms[2] = {-1.0, -1.0};  // measured column-block time (ms) per pair, < 0 before the first
   double est_rate = -1.0;           // measured bulk GEMM flops per ms per CU, < 0 before the first
   int update_prec = 0;              // LUPP_PREC_* of sgetrf's trailing update
   int* lp_scale[3] = {nullptr, nullptr, nullptr};  // block exponents: next-block, bulk and side updates

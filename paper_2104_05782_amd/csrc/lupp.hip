@@ -25,6 +25,7 @@ namespace lupp {
 namespace {
 
 constexpr int kLookaheadPanelCUs = 32;
+constexpr int kLookaheadPanelCUs2 = 64;  // second pair, for panels of 33 to 64 workgroups
 
 // Epoch of the panel kernel's progress flags: every launch uses flag values
 // above all values written before; the flags are cleared before wrap-around.
@@ -145,8 +146,10 @@ void harvest_split_timings(lupp_handle_t h) {
     float pm = 0.f, bm = 0.f;
     if (hipEventElapsedTime(&pm, h->tm_ev[o][0], h->tm_ev[o][1]) == hipSuccess &&
         hipEventElapsedTime(&bm, h->tm_ev[o][2], h->tm_ev[o][3]) == hipSuccess && bm > 0.f) {
-      h->est_panel_ms = h->est_panel_ms < 0 ? pm : 0.5 * (h->est_panel_ms + pm);
-      const double rate = h->tm_flops[o] / ((double)bm * (double)(h->ncu - h->panel_cus));
+      const int pr = h->tm_pair[o];
+      h->est_panel_ms[pr] = h->est_panel_ms[pr] < 0 ? pm : 0.5 * (h->est_panel_ms[pr] + pm);
+      const int pcus = pr == 0 ? h->panel_cus : h->panel_cus2;
+      const double rate = h->tm_flops[o] / ((double)bm * (double)(h->ncu - pcus));
       h->est_rate = h->est_rate < 0 ? rate : 0.5 * (h->est_rate + rate);
     }
     (void)hipGetLastError();
@@ -159,10 +162,12 @@ void harvest_split_timings(lupp_handle_t h) {
 // bulk CUs B, panel CUs S, panel time P and per-CU rate R, the bulk share f
 // of the W flops solves f W / (B R) = P + (1 - f) W / (S R).  Zero when the
 // panel alone outlasts the whole update.
-int64_t side_columns(lupp_handle_t h, int64_t M, int64_t nc, int64_t K, bool fp64) {
-  const double B = (double)(h->ncu - h->panel_cus), S = (double)h->panel_cus;
+int64_t side_columns(lupp_handle_t h, int pair, int64_t M, int64_t nc, int64_t K, bool fp64) {
+  const int pcus = pair == 0 ? h->panel_cus : h->panel_cus2;
+  const double B = (double)(h->ncu - pcus), S = (double)pcus;
   if (B <= 0 || S <= 0) return 0;
-  const double P = h->est_panel_ms >= 0 ? h->est_panel_ms : (fp64 ? 2.3 : 1.8) * (double)K / 256.0;
+  const double P =
+      h->est_panel_ms[pair] >= 0 ? h->est_panel_ms[pair] : (fp64 ? 2.3 : 1.8) * (pair + 1) * (double)K / 256.0;
   double R = h->est_rate;
   if (R <= 0) R = fp64 ? 2.0e8 : (h->update_prec != LUPP_PREC_FP32 ? 6.0e8 : 3.0e8);
   const double W = 2.0 * (double)M * (double)nc * (double)K;
@@ -240,21 +245,26 @@ hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32
     }
     // overlap only when the next block's cooperative factorization fits in
     // the reserved CUs (one workgroup per CU at most)
-    const bool overlap = la && n1 > 0 && panel_groups(mr) <= h->panel_cus && nr > n1;
+    // a pair of streams whose panel CUs hold the next block's cooperative
+    // factorization (one workgroup per CU at most)
+    const int G = panel_groups(mr);
+    const int pair = (G <= h->panel_cus) ? 0 : (h->side2 && h->bulk2 && G <= h->panel_cus2) ? 1 : -1;
+    const bool overlap = la && n1 > 0 && pair >= 0 && nr > n1;
+    hipStream_t sside = pair == 1 ? h->side2 : h->side, sbulk = pair == 1 ? h->bulk2 : h->bulk;
     hipStream_t su = s;
     int slot = -1;  // timing slot of this step's panel and bulk update, if measured
     if (overlap) {
       LUPP_TRY(hipEventRecord(h->ev_cols, s));
-      LUPP_TRY(hipStreamWaitEvent(h->side, h->ev_cols, 0));
-      LUPP_TRY(hipStreamWaitEvent(h->bulk, h->ev_cols, 0));
+      LUPP_TRY(hipStreamWaitEvent(sside, h->ev_cols, 0));
+      LUPP_TRY(hipStreamWaitEvent(sbulk, h->ev_cols, 0));
       if (h->split) {
         harvest_split_timings(h);
         if (!h->tm_pending[h->tm_slot]) slot = h->tm_slot;
       }
-      if (slot >= 0) LUPP_TRY(hipEventRecord(h->tm_ev[slot][0], h->side));
-      LUPP_TRY(factor_block<T>(h, h->side, m, kn, bn, A, lda, ipiv, info));
-      if (slot >= 0) LUPP_TRY(hipEventRecord(h->tm_ev[slot][1], h->side));
-      su = h->bulk;
+      if (slot >= 0) LUPP_TRY(hipEventRecord(h->tm_ev[slot][0], sside));
+      LUPP_TRY(factor_block<T>(h, sside, m, kn, bn, A, lda, ipiv, info));
+      if (slot >= 0) LUPP_TRY(hipEventRecord(h->tm_ev[slot][1], sside));
+      su = sbulk;
     }
     if (nr > n1) {
       const int64_t c1 = kn + n1, nc = nr - n1;
@@ -269,11 +279,11 @@ hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32
       if (mr > 0) {
         // the bulk CUs take the first columns; once the next block is
         // factored, the panel's CUs take the last ones
-        const int64_t nside = (overlap && h->split) ? side_columns(h, mr, nc, b, sizeof(T) == 8) : 0;
+        const int64_t nside = (overlap && h->split) ? side_columns(h, pair, mr, nc, b, sizeof(T) == 8) : 0;
         const int64_t nbulk = nc - nside;
         if (nside > 0) {
           LUPP_TRY(hipEventRecord(h->ev_trsm, su));
-          LUPP_TRY(hipStreamWaitEvent(h->side, h->ev_trsm, 0));
+          LUPP_TRY(hipStreamWaitEvent(sside, h->ev_trsm, 0));
         }
         int tile = -1;
         if (slot >= 0) LUPP_TRY(hipEventRecord(h->tm_ev[slot][2], su));
@@ -284,21 +294,22 @@ hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32
         if (slot >= 0) {
           LUPP_TRY(hipEventRecord(h->tm_ev[slot][3], su));
           h->tm_flops[slot] = 2.0 * (double)mr * (double)nbulk * (double)b;
+          h->tm_pair[slot] = pair;
           h->tm_pending[slot] = true;
           h->tm_slot ^= 1;
         }
         if (nside > 0) {
           const int64_t c2 = c1 + nbulk;
-          t = timer_begin(h, LUPP_PHASE_UPDATE, h->side);
-          LUPP_TRY(update<T>(h, h->side, 2, mr, nside, b, A + kn + k * lda, lda, A + k + c2 * lda, lda,
+          t = timer_begin(h, LUPP_PHASE_UPDATE, sside);
+          LUPP_TRY(update<T>(h, sside, 2, mr, nside, b, A + kn + k * lda, lda, A + k + c2 * lda, lda,
                              A + kn + c2 * lda, lda));
-          timer_end(h, t, h->side, 2.0 * (double)mr * (double)nside * (double)b);
+          timer_end(h, t, sside, 2.0 * (double)mr * (double)nside * (double)b);
         }
       }
     }
     if (overlap) {
-      LUPP_TRY(hipEventRecord(h->ev_panel, h->side));
-      LUPP_TRY(hipEventRecord(h->ev_bulk, h->bulk));
+      LUPP_TRY(hipEventRecord(h->ev_panel, sside));
+      LUPP_TRY(hipEventRecord(h->ev_bulk, sbulk));
       LUPP_TRY(hipStreamWaitEvent(s, h->ev_bulk, 0));
       LUPP_TRY(hipStreamWaitEvent(s, h->ev_panel, 0));
     } else if (n1 > 0) {
@@ -353,6 +364,8 @@ hipError_t ensure_lp_scale(lupp_handle_t h, int64_t m, int64_t n) {
   LUPP_TRY(hipStreamSynchronize(h->stream));
   if (h->bulk) LUPP_TRY(hipStreamSynchronize(h->bulk));
   if (h->side) LUPP_TRY(hipStreamSynchronize(h->side));
+  if (h->bulk2) LUPP_TRY(hipStreamSynchronize(h->bulk2));
+  if (h->side2) LUPP_TRY(hipStreamSynchronize(h->side2));
   if (h->lp_scale[0]) (void)hipFree(h->lp_scale[0]);
   h->lp_scale[0] = h->lp_scale[1] = h->lp_scale[2] = nullptr;
   h->lp_scale_cap = 0;
@@ -444,6 +457,16 @@ hipError_t ensure_workspace(lupp_handle_t h) {
   }
   if (hipExtStreamCreateWithCUMask(&h->side, (uint32_t)mside.size(), mside.data()) != hipSuccess) h->side = nullptr;
   if (hipExtStreamCreateWithCUMask(&h->bulk, (uint32_t)mbulk.size(), mbulk.data()) != hipSuccess) h->bulk = nullptr;
+  if (ncu >= 2 * kLookaheadPanelCUs2) {
+    std::vector<uint32_t> m2s((ncu + 31) / 32, 0u), m2b((ncu + 31) / 32, 0u);
+    for (int c = 0; c < ncu; ++c) {
+      if (c < kLookaheadPanelCUs2) m2s[c / 32] |= 1u << (c % 32);
+      else m2b[c / 32] |= 1u << (c % 32);
+    }
+    if (hipExtStreamCreateWithCUMask(&h->side2, (uint32_t)m2s.size(), m2s.data()) != hipSuccess) h->side2 = nullptr;
+    if (hipExtStreamCreateWithCUMask(&h->bulk2, (uint32_t)m2b.size(), m2b.data()) != hipSuccess) h->bulk2 = nullptr;
+    if (h->side2 && h->bulk2) h->panel_cus2 = kLookaheadPanelCUs2;
+  }
   if (!h->side || !h->bulk || hipEventCreateWithFlags(&h->ev_cols, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_bulk, hipEventDisableTiming) != hipSuccess ||
@@ -525,6 +548,8 @@ int lupp_destroy(lupp_handle_t h) {
   }
   if (h->side) (void)hipStreamSynchronize(h->side);
   if (h->bulk) (void)hipStreamSynchronize(h->bulk);
+  if (h->side2) (void)hipStreamSynchronize(h->side2);
+  if (h->bulk2) (void)hipStreamSynchronize(h->bulk2);
   if (h->ev_cols) (void)hipEventDestroy(h->ev_cols);
   if (h->ev_panel) (void)hipEventDestroy(h->ev_panel);
   if (h->ev_bulk) (void)hipEventDestroy(h->ev_bulk);
@@ -534,6 +559,8 @@ int lupp_destroy(lupp_handle_t h) {
       if (h->tm_ev[o][e]) (void)hipEventDestroy(h->tm_ev[o][e]);
   if (h->side) (void)hipStreamDestroy(h->side);
   if (h->bulk) (void)hipStreamDestroy(h->bulk);
+  if (h->side2) (void)hipStreamDestroy(h->side2);
+  if (h->bulk2) (void)hipStreamDestroy(h->bulk2);
   if (h->slots) (void)hipFree(h->slots);
   if (h->defer_buf) (void)hipFree(h->defer_buf);
   if (h->lp_scale[0]) (void)hipFree(h->lp_scale[0]);
@@ -591,6 +618,8 @@ int lupp_sync(lupp_handle_t h) {
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e == hipSuccess && h->side) e = hipStreamSynchronize(h->side);
   if (e == hipSuccess && h->bulk) e = hipStreamSynchronize(h->bulk);
+  if (e == hipSuccess && h->side2) e = hipStreamSynchronize(h->side2);
+  if (e == hipSuccess && h->bulk2) e = hipStreamSynchronize(h->bulk2);
   if (e != hipSuccess) return lupp::hip_status(e);
   if (h->slots) {
     int32_t err = 0;
@@ -614,6 +643,8 @@ int lupp_timing_summary(lupp_handle_t h, int phase, int64_t* count, double* ms, 
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e == hipSuccess && h->side) e = hipStreamSynchronize(h->side);
   if (e == hipSuccess && h->bulk) e = hipStreamSynchronize(h->bulk);
+  if (e == hipSuccess && h->side2) e = hipStreamSynchronize(h->side2);
+  if (e == hipSuccess && h->bulk2) e = hipStreamSynchronize(h->bulk2);
   if (e != hipSuccess) return lupp::hip_status(e);
   *count = 0;
   *ms = 0.0;

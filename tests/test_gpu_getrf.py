@@ -349,3 +349,43 @@ def test_split_update_low_precision():
     assert i1 == 0
     assert float(torch.tril(A1, -1).abs().max()) <= 1.0
     assert _probe_residual(A0.double(), A1.double(), p1) < 10 * 2.0 ** -8
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_lookahead_wide_panel_pair_bit_identical(dtype):
+    """m = 40000: the next block's factorization needs 40 workgroups, so it
+    runs beside the update on the 64-CU stream pair; the factors equal those
+    of the in-order single-stream run bit for bit."""
+    m, n = 40000, 1280
+    announce("wide panel pair %dx%d %s" % (m, n, dtype))
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    g = torch.Generator(device="cuda").manual_seed(43)
+    A0 = torch.empty((n, m), dtype=tdt, device="cuda").t()
+    A0.uniform_(-1.0, 1.0, generator=g)
+    outs = []
+    for la in (1, 0):
+        h = lupp.Handle()
+        h.set_option(4, la)
+        A = torch.empty_like(A0.t()).t()
+        A.copy_(A0)
+        ipiv = torch.empty(n, dtype=torch.int32, device="cuda")
+        info = torch.empty(1, dtype=torch.int32, device="cuda")
+        (lupp.lupp_dgetrf if dtype == "f64" else lupp.lupp_sgetrf)(A, ipiv, info, handle=h)
+        h.sync()
+        h.close()
+        outs.append((A, ipiv, int(info.item())))
+    (A1, p1, i1), (A2, p2, i2) = outs
+    assert i1 == i2 == 0
+    assert torch.equal(p1, p2) and torch.equal(A1, A2)
+    # L U reproduces the interchanged rows (probe vectors, FP64)
+    L = torch.tril(A1.double(), -1)
+    L[:n, :n] += torch.eye(n, dtype=torch.float64, device="cuda")
+    U = torch.triu(A1.double()[:n, :n])
+    perm = np.arange(m)
+    for i, p in enumerate(p1.cpu().numpy() - 1):
+        perm[i], perm[p] = perm[p], perm[i]
+    P = torch.from_numpy(perm).cuda()
+    x = torch.rand(n, 1, generator=g, dtype=tdt, device="cuda").double() * 2 - 1
+    r = (A0.double() @ x)[P] - L @ (U @ x)
+    u = checks.U64 if dtype == "f64" else checks.U32
+    assert float(r.abs().max() / (m * A0.double().abs().sum(dim=1).max() * x.abs().max())) < 10 * u
