@@ -73,6 +73,19 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, const T* __restrict__ A
   T acc = T(0);
   // dependencies: blocks [0, b) (lower) or (b, nblk) (upper), in order
   const int64_t ndep = LOWER ? b : (nblk - 1 - b);
+  // The last dependency (the adjacent block) is on the critical path: its
+  // matrix tile does not depend on the flag, so this wave's 16 columns of it
+  // are loaded now; after the flag only x is read.
+  T apf[16];
+  const int64_t lastd = ndep - 1;
+  if (ndep > 0) {
+    const int64_t c0 = (LOWER ? lastd : (nblk - 1 - lastd)) * TB + wave * 16;
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) {
+      const int64_t c = c0 + cc;
+      apf[cc] = (c < n && rok) ? A[row + c * lda] : T(0);
+    }
+  }
   int64_t done = 0;
   long spins = 0;
   while (done < ndep) {
@@ -97,7 +110,7 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, const T* __restrict__ A
         continue;
       }
     }
-    for (int64_t d = done; d < done + nready && d < ndep; ++d) {
+    for (int64_t d = done; d < done + nready && d < lastd; ++d) {
       const int64_t blk = LOWER ? d : (nblk - 1 - d);
       const int64_t c0 = blk * TB;
       // this wave's 16 columns of the 64x64 tile
@@ -109,6 +122,14 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, const T* __restrict__ A
     }
     done += nready;
     __syncthreads();
+  }
+  if (ndep > 0) {
+    const int64_t c0 = (LOWER ? lastd : (nblk - 1 - lastd)) * TB + wave * 16;
+    T xv[16];
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) xv[cc] = (c0 + cc < n) ? ld_coh(&x[c0 + cc]) : T(0);
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) acc = acc - apf[cc] * xv[cc];
   }
   s_part[wave][lane] = acc;
   __syncthreads();
