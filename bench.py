@@ -32,6 +32,9 @@ The JSON line carries:
               between replays, outside the timed interval), against the HBM
               roofline of the call's algorithmic bytes (A and b read, the factors and x
               written, pivots written, sizes and offsets read)
+  large       n = 65536 (diagonally dominant recipe drawn on the device): plain FP64
+              factorization + solve against the FP8-update GMRES-IR solve (wall
+              times, effective TFLOP/s, backward errors)
 """
 from __future__ import annotations
 
@@ -294,6 +297,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-lookahead", action="store_true")
+    ap.add_argument("--no-split", action="store_true",
+                    help="no share of the remaining-columns update on the panel's CUs (every launch shape then follows "
+                         "from n and nb alone)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solve leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched small-systems leg")
     ap.add_argument("--no-large", action="store_true", help="skip the large mixed-precision leg")
@@ -354,6 +360,8 @@ def main():
         h.set_option(2, args.block)
     if args.no_lookahead:
         h.set_option(4, 0)
+    if args.no_split:
+        h.set_option(7, 0)
     fn = lupp.lupp_dgetrf if args.dtype == "f64" else lupp.lupp_sgetrf
 
     def step():
