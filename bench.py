@@ -453,7 +453,7 @@ def main():
         "data": "synthetic: A iid U(-1,1) from seed %d (Philox-4x64-10)" % args.seed,
         "config": {"workload": "plain blocked LUPP FP64 n=%d" % n if args.dtype == "f64"
                    else "plain blocked LUPP FP32 n=%d" % n,
-                   "n": n, "nb": args.nb or 256, "lookahead": 0 if args.no_lookahead else 1,
+                   "n": n, "nb": args.nb or 512, "lookahead": 0 if args.no_lookahead else 1,
                    "flops_per_step": flops, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

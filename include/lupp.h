@@ -52,7 +52,7 @@ enum {
 
 /* Options for lupp_set_option. */
 enum {
-  LUPP_OPT_NB = 1,         /* outer block size b of the right-looking loop (default 256)  */
+  LUPP_OPT_NB = 1,         /* outer block size b of the right-looking loop (default 512)  */
   LUPP_OPT_PANEL_LEAF = 2, /* widest column block factored in one cooperative launch
                               (16 .. 256, a multiple of 16; default 128); wider blocks
                               split recursively with a triangular solve and a GEMM      */

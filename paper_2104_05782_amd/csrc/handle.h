@@ -19,7 +19,7 @@ struct BatchWs;
 struct lupp_handle_st {
   int device = 0;
   hipStream_t stream = nullptr;
-  int64_t nb = 256;
+  int64_t nb = 512;
   int block = 128;                  // widest column block factored in one cooperative launch
   lupp::LeafSlots* slots = nullptr;
   lupp::SwapPairs* pairs = nullptr;
