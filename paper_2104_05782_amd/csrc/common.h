@@ -73,12 +73,13 @@ struct SwapPairs {
 // ---------------------------------------------------------------- launchers
 // C[M x N] -= A[M x K] * B[K x N], column-major (A, B and C must not overlap).
 // *tile_out (optional) receives the tile configuration used: 0 = 128x32,
-// 1 = 128x128, 2 = 64x64, -1 = nothing launched.  side: the launch is the
-// share of an update run on the panel's CUs (a separately named FP64 kernel,
-// 128x128 tiles down to 32 tiles).
+// 1 = 128x128, 2 = 64x64, -1 = nothing launched.  role: 0 a trailing update,
+// 1 the share of an update run on the panel's CUs (128x128 tiles down to 32
+// tiles), 2 a product inside the column-block or triangular-solve recursion;
+// the FP64 kernel is named by it.
 template <typename T>
 hipError_t gemm_sub(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda,
-                    const T* B, int64_t ldb, T* C, int64_t ldc, int* tile_out = nullptr, bool side = false);
+                    const T* B, int64_t ldb, T* C, int64_t ldc, int* tile_out = nullptr, int role = 2);
 
 // Factor the r x w column block P (leading dimension ld, w <= kBlockMaxWidth,
 // r >= w) whose first row and column are the global row/column k: partial

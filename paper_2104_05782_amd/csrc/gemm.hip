@@ -300,8 +300,10 @@ __device__ __forceinline__ void dgemm16_body(int64_t M, int64_t N, int64_t K, co
   }
 }
 
-// ROLE only names the launch: 0 for updates on the main and bulk streams, 1
-// for the share of the remaining-columns update run on the panel's CUs.
+// ROLE only names the launch: 0 for the trailing updates on the main and bulk
+// streams, 1 for the share of the remaining-columns update run on the panel's
+// CUs, 2 for the products inside the column-block and triangular-solve
+// recursions.
 template <int BM, int BN, int BK, int WGM, int WGN, int MINB, int ROLE>
 __global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_dgemm_sub_16(int64_t M, int64_t N, int64_t K,
                                                                       const double* __restrict__ A, int64_t lda,
@@ -360,7 +362,7 @@ hipError_t launch_d16(hipStream_t s, int64_t M, int64_t N, int64_t K, const doub
 
 template <typename T>
 hipError_t gemm_sub(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B,
-                    int64_t ldb, T* C, int64_t ldc, int* tile_out, bool side) {
+                    int64_t ldb, T* C, int64_t ldc, int* tile_out, int role) {
   int dummy;
   int& tile = tile_out ? *tile_out : dummy;
   tile = -1;
@@ -371,9 +373,10 @@ hipError_t gemm_sub(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, 
   }
   const int64_t big_tiles = ((M + 127) / 128) * ((N + 127) / 128);
   if constexpr (sizeof(T) == 8) {
-    if (big_tiles >= 256 || (side && big_tiles >= 32)) {
+    if (big_tiles >= 256 || (role == 1 && big_tiles >= 32)) {
       tile = 1;
-      if (side) return launch_d16<128, 128, 8, 2, 2, 2, 1>(s, M, N, K, A, lda, B, ldb, C, ldc);
+      if (role == 1) return launch_d16<128, 128, 8, 2, 2, 2, 1>(s, M, N, K, A, lda, B, ldb, C, ldc);
+      if (role == 2) return launch_d16<128, 128, 8, 2, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
       return launch_d16<128, 128, 8, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
     }
     tile = 2;
@@ -389,8 +392,8 @@ hipError_t gemm_sub(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, 
 }
 
 template hipError_t gemm_sub<double>(hipStream_t, int64_t, int64_t, int64_t, const double*, int64_t,
-                                     const double*, int64_t, double*, int64_t, int*, bool);
+                                     const double*, int64_t, double*, int64_t, int*, int);
 template hipError_t gemm_sub<float>(hipStream_t, int64_t, int64_t, int64_t, const float*, int64_t,
-                                    const float*, int64_t, float*, int64_t, int*, bool);
+                                    const float*, int64_t, float*, int64_t, int*, int);
 
 }  // namespace lupp

@@ -131,7 +131,7 @@ hipError_t update(lupp_handle_t h, hipStream_t s, int which, int64_t M, int64_t 
       return gemm_lp_sub(s, h->update_prec, M, N, K, A, lda, B, ldb, C, ldc, h->lp_scale[which]);
     }
   }
-  return gemm_sub<T>(s, M, N, K, A, lda, B, ldb, C, ldc, tile, which == 2);
+  return gemm_sub<T>(s, M, N, K, A, lda, B, ldb, C, ldc, tile, which == 2 ? 1 : 0);
 }
 
 // Reads the panel and bulk-update times of an earlier step once its events
