@@ -304,7 +304,7 @@ __device__ __forceinline__ void dgemm16_body(int64_t M, int64_t N, int64_t K, co
 // streams, 1 for the share of the remaining-columns update run on the panel's
 // CUs, 2 for the products inside the column-block and triangular-solve
 // recursions.
-template <int BM, int BN, int BK, int WGM, int WGN, int MINB, int ROLE>
+template <int BM, int BN, int BK, int WGM, int WGN, int MINB, int ROLE, int GM = kGroupM>
 __global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_dgemm_sub_16(int64_t M, int64_t N, int64_t K,
                                                                       const double* __restrict__ A, int64_t lda,
                                                                       const double* __restrict__ B, int64_t ldb,
@@ -318,10 +318,10 @@ __global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_dgemm_sub_16(int64_t M,
   const int bid = blockIdx.x;
   const int t = (bid % kXcds) * per_xcd + bid / kXcds;
   if (t >= total) return;
-  const int group_size = kGroupM * tiles_n;
+  const int group_size = GM * tiles_n;
   const int group = t / group_size;
-  const int first_m = group * kGroupM;
-  const int gm = min(tiles_m - first_m, kGroupM);
+  const int first_m = group * GM;
+  const int gm = min(tiles_m - first_m, GM);
   const int within = t - group * group_size;
   const int tm = first_m + within % gm;
   const int tn = within / gm;
@@ -346,14 +346,14 @@ hipError_t launch(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, in
   return hipGetLastError();
 }
 
-template <int BM, int BN, int BK, int WGM, int WGN, int MINB, int ROLE = 0>
+template <int BM, int BN, int BK, int WGM, int WGN, int MINB, int ROLE = 0, int GM = kGroupM>
 hipError_t launch_d16(hipStream_t s, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
                       int64_t ldb, double* C, int64_t ldc) {
   const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
   if (tm * tn > (int64_t)1 << 30) return hipErrorInvalidValue;
   const int total = (int)(tm * tn);
   const int per_xcd = (total + kXcds - 1) / kXcds;
-  hipLaunchKernelGGL((k_dgemm_sub_16<BM, BN, BK, WGM, WGN, MINB, ROLE>), dim3(per_xcd * kXcds), dim3(64 * WGM * WGN), 0,
+  hipLaunchKernelGGL((k_dgemm_sub_16<BM, BN, BK, WGM, WGN, MINB, ROLE, GM>), dim3(per_xcd * kXcds), dim3(64 * WGM * WGN), 0,
                      s, M, N, K, A, lda, B, ldb, C, ldc, (int)tm, (int)tn);
   return hipGetLastError();
 }
