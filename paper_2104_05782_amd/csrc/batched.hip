@@ -1,22 +1,24 @@
 // Batched LU with partial pivoting and solve for many small systems
-// (order n <= 128), one workgroup per system with the system held in LDS.
+// (order n <= 128), one workgroup per system with the system held in
+// registers.
 //
-// Each system is the same factorization as the large path -- partial
-// pivoting with LAPACK's conventions, blocked right-looking with a W-column
-// panel and a rank-W trailing update (the blocked loop of Section 4.3 and
-// the column-block step of Section 4.1, at the scale of one workgroup) --
-// applied to the augmented matrix [A | b], so that the row interchanges and
-// the elimination also carry b to L^{-1} P b; a backward substitution with U
-// then gives x (skipped, as in LAPACK's gesv, when a pivot is exactly zero).
+// Each system is factored with LAPACK's conventions for partial pivoting
+// (the column step of Section 4.1, one column at a time, at the scale of one
+// workgroup) applied to the augmented matrix [A | b], so that the row
+// interchanges and the elimination also carry b to L^{-1} P b; a backward
+// substitution with U then gives x (skipped, as in LAPACK's gesv, when a
+// pivot is exactly zero).
 //
 // Scheduling: a binning kernel sorts the systems into four size classes
 // (n <= 32, 64, 96, 128), each served by one persistent launch whose
-// workgroups (64, 256, 512, 512 threads) take systems from an atomic queue;
-// the LDS footprint of a class is its largest augmented matrix, so smaller
-// classes run more workgroups per CU.  The classes are launched on four
-// streams so that the short classes fill the CUs the long ones leave idle.
-// No host synchronization or allocation happens per call (graph-capturable
-// once the workspace exists for the batch size).
+// workgroups (1, 2, 4, 4 wavefronts) take the class's systems in round
+// robin (no shared counter: thousands of workgroups contending for one
+// global atomic cost more than the small systems themselves).  A
+// CU's register file (512 KB) holds several systems of every class, where its
+// LDS (160 KB) would hold one of the largest.  The classes are launched on
+// four streams so that the short classes fill the CUs the long ones leave
+// idle.  No host synchronization or allocation happens per call
+// (graph-capturable once the workspace exists for the batch size).
 #include "handle.h"
 #include "wave.h"
 
@@ -29,7 +31,7 @@ constexpr int kBatchMaxN = 128;
 struct BatchWs {
   int64_t capacity = 0;
   int32_t* list = nullptr;  // capacity entries: system ids grouped by class
-  int32_t* meta = nullptr;  // [0,4) counts, [4,8) offsets, [8,12) queue heads
+  int32_t* meta = nullptr;  // [0,4) counts, [4,8) offsets
   hipStream_t streams[kBatchClasses] = {};
   hipEvent_t fork = nullptr, join[kBatchClasses] = {};
   int grid[2][kBatchClasses] = {};  // persistent grid per (precision, class)
@@ -37,22 +39,32 @@ struct BatchWs {
 
 namespace {
 
-constexpr int kPanelW = 8;  // panel width of the per-system blocked factorization
-
 __device__ __forceinline__ int size_class(int n) { return n <= 32 ? 0 : (n <= 64 ? 1 : (n <= 96 ? 2 : 3)); }
 
-// Sort systems into size classes; reset the queue heads.  One workgroup.
+// Sort systems into size classes.  One workgroup; the
+// counters are updated once per wavefront and class (ballot + popcount), not
+// once per system.
 __global__ __launch_bounds__(1024) void k_batch_bin(int32_t batch, const int32_t* __restrict__ dn,
                                                     int32_t* __restrict__ list, int32_t* __restrict__ meta,
                                                     int32_t* __restrict__ info) {
   __shared__ int cnt[kBatchClasses], cur[kBatchClasses], off[kBatchClasses];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   if (tid < kBatchClasses) cnt[tid] = 0;
   __syncthreads();
-  for (int i = tid; i < batch; i += 1024) {
-    const int n = dn[i];
-    if (n >= 1 && n <= kBatchMaxN) atomicAdd(&cnt[size_class(n)], 1);
-    else info[i] = (n == 0) ? 0 : -1;  // empty system: nothing to do; bad order: rejected
+  for (int base = 0; base < batch; base += 1024) {
+    const int i = base + tid;
+    int c = -1;
+    if (i < batch) {
+      const int n = dn[i];
+      if (n >= 1 && n <= kBatchMaxN) c = size_class(n);
+      else info[i] = (n == 0) ? 0 : -1;  // empty system: nothing to do; bad order: rejected
+    }
+#pragma unroll
+    for (int q = 0; q < kBatchClasses; ++q) {
+      const uint64_t b = __ballot(c == q);
+      if (lane == 0 && b) atomicAdd(&cnt[q], __popcll(b));
+    }
   }
   __syncthreads();
   if (tid == 0) {
@@ -62,286 +74,385 @@ __global__ __launch_bounds__(1024) void k_batch_bin(int32_t batch, const int32_t
       cur[c] = 0;
       meta[c] = cnt[c];
       meta[4 + c] = o;
-      meta[8 + c] = 0;
       o += cnt[c];
     }
   }
   __syncthreads();
-  for (int i = tid; i < batch; i += 1024) {
-    const int n = dn[i];
-    if (n >= 1 && n <= kBatchMaxN) {
-      const int c = size_class(n);
-      list[off[c] + atomicAdd(&cur[c], 1)] = i;
+  for (int base = 0; base < batch; base += 1024) {
+    const int i = base + tid;
+    int c = -1;
+    if (i < batch) {
+      const int n = dn[i];
+      if (n >= 1 && n <= kBatchMaxN) c = size_class(n);
+    }
+#pragma unroll
+    for (int q = 0; q < kBatchClasses; ++q) {
+      const uint64_t b = __ballot(c == q);
+      if (!b) continue;
+      int at = 0;
+      if (lane == 0) at = atomicAdd(&cur[q], __popcll(b));
+      at = __builtin_amdgcn_readlane(at, 0);
+      if (c == q) list[off[q] + at + __popcll(b & below)] = i;
     }
   }
 }
 
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_batch_lu(int cls, const int32_t* __restrict__ dn,
-                                                 const int64_t* __restrict__ aoff, T* __restrict__ gA,
-                                                 const int64_t* __restrict__ poff, int32_t* __restrict__ gpiv,
-                                                 const int64_t* __restrict__ boff, T* __restrict__ gB,
-                                                 int32_t* __restrict__ ginfo, const int32_t* __restrict__ list,
-                                                 int32_t* __restrict__ meta) {
-  constexpr int NW = NT / 64;
-  constexpr int W = kPanelW;
-  extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
-  T* As = (T*)dyn;  // n x (n + 1), leading dimension n
-  __shared__ int s_piv[kBatchMaxN];
-  __shared__ int s_pdst[2 * W], s_psrc[2 * W];
-  __shared__ int s_sys, s_info, s_npairs;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+// Pivot search on one column held as R row slots per lane (slot h*64 + lane):
+// the largest |a| over the rows whose logical position is >= kp, the lowest
+// logical row on ties (LAPACK's first maximum).  Returns the winner's slot
+// and logical row; unless the pivot is zero, the column's candidate rows are
+// replaced by their multipliers (true division, so |l| <= 1 exactly), which
+// are also returned in lo (0 in every other slot).
+template <int R, typename T>
+__device__ __forceinline__ void pivot_column(T (&col)[R], T (&lo)[R], const int (&pos)[R], const bool (&valid)[R],
+                                             int kp, int n, int lane, int& ps_out, int& p_out, bool& nz_out) {
+  double a[R];
+  double am = -1.0;
+#pragma unroll
+  for (int h = 0; h < R; ++h) {
+    const bool cand = valid[h] && pos[h] >= kp;
+    a[h] = cand ? (double)fabs(col[h]) : -1.0;
+    am = fmax(am, a[h]);
+  }
+  const double m = wave_max_f64(am);
+  uint32_t key = 0x7fffffffu;
+#pragma unroll
+  for (int h = 0; h < R; ++h)
+    if (a[h] >= 0.0 && a[h] == m) key = min(key, (uint32_t)pos[h]);
+  const uint32_t pm = wave_min_u32(key);
+  const int p = (pm >= (uint32_t)kp && pm < (uint32_t)n) ? (int)pm : kp;  // kp only with NaN entries
+  int ps = 0;
+#pragma unroll
+  for (int h = 0; h < R; ++h) {
+    const uint64_t b = __ballot(valid[h] && pos[h] == p);
+    if (b) ps = h * 64 + (int)__builtin_ctzll(b);
+  }
+  const T pv = (R == 1 || ps < 64) ? readlane_d(col[0], ps & 63) : readlane_d(col[R - 1], ps & 63);
+  const bool nz = pv != T(0);
+#pragma unroll
+  for (int h = 0; h < R; ++h) {
+    const bool cand = nz && valid[h] && pos[h] >= kp && h * 64 + lane != ps;
+    const T q = col[h] / pv;
+    lo[h] = cand ? q : T(0);
+    if (cand) col[h] = q;
+  }
+  ps_out = ps;
+  p_out = p;
+  nz_out = nz;
+}
+
+// One system per workgroup of NW wavefronts, the whole augmented matrix
+// [A | b] in registers: lane l holds rows l and (R = 2) l + 64, wavefront w
+// holds columns w, w + NW, w + 2 NW, ... (C of them at most; b is column n).
+//
+// The factorization is LAPACK's unblocked right-looking elimination with
+// partial pivoting (the column step of Section 4.1 applied one column at a
+// time): for each column k, pivot search, interchange, scaling by the pivot
+// and the rank-1 update of the columns to the right.  Rows never move: pos
+// holds the logical row of each slot, an interchange exchanges two logical
+// positions, and each row is written to its final position at the end.
+//
+// Step k:
+//  - the multipliers and the pivot slot come from the wavefront owning
+//    column k through LDS (one LDS-only barrier per step);
+//  - each wavefront reads the pivot row's entries of its columns from the
+//    pivot lane into scalar registers (v_readlane: 8 bytes per column, where
+//    a broadcast through LDS would move 512 and saturate the LDS pipe) and
+//    applies the rank-1 update as a chain of FMAs, register subscripts
+//    static and no per-column branch (in a finished column it changes only
+//    L entries, whose values were stored when the column was factored);
+//  - lookahead: the owner of column k+1 applies step k to a copy of that
+//    column first and publishes its pivot and multipliers before its chain,
+//    so the pivot search overlaps the other wavefronts' updates.  The
+//    multipliers are stored to the global matrix at the rows' slots (the
+//    registers keep the column's updated values, the same as the copy's);
+//    the final store takes L from there and U from the registers.
+//
+// The solve x = inv(U) c, c = L^{-1} P b being column n after the
+// elimination, is a backward substitution by the wavefront holding b, with
+// U read back from the stored factors (ten columns in flight) and the
+// reciprocals of U's diagonal (skipped on a zero pivot, as in LAPACK's gesv).
+//
+// The multipliers on rows that are not below the pivot are zero: with finite
+// values the FMA leaves such rows exactly unchanged (up to the sign of a
+// zero); with +-Inf or NaN in the pivot row they become NaN where LAPACK
+// would leave them.
+template <typename T, int NW, int R, int C>
+__global__ __launch_bounds__(64 * NW, NW == 4 ? 3 : 4) void k_batch_lu(int cls, const int32_t* __restrict__ dn,
+                                                      const int64_t* __restrict__ aoff, T* __restrict__ gA,
+                                                      const int64_t* __restrict__ poff, int32_t* __restrict__ gpiv,
+                                                      const int64_t* __restrict__ boff, T* __restrict__ gB,
+                                                      int32_t* __restrict__ ginfo, const int32_t* __restrict__ list,
+                                                      const int32_t* __restrict__ meta) {
+  constexpr int NT = 64 * NW;
+  __shared__ T s_l[2][64 * R];                       // multipliers of the current and the next step
+  __shared__ int s_pp[2][4];                         // pivot slot, pivot's logical row, pivot nonzero
+  __shared__ int s_slot[kBatchMaxN], s_piv[kBatchMaxN];
+  __shared__ int s_info;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 6);
   const int count = meta[cls], first = meta[4 + cls];
 
-  for (;;) {
-    if (tid == 0) {
-      const int q = atomicAdd(&meta[8 + cls], 1);
-      s_sys = q < count ? list[first + q] : -1;
-      s_info = 0;
-    }
-    __syncthreads();
-    const int sys = s_sys;
-    if (sys < 0) return;
+  // systems of the class in round robin over the persistent workgroups
+  for (int q = blockIdx.x; q < count; q += gridDim.x) {
+    const int sys = list[first + q];
     const int n = dn[sys];
     T* A = gA + aoff[sys];
     T* Bv = gB ? gB + boff[sys] : nullptr;
-    const int ncol = n + (Bv ? 1 : 0);
-    const int nn = n * n;
-    // ---- system into LDS, eight loads in flight per thread
-    for (int base = 0; base < nn; base += 8 * NT) {
-      T tmp[8];
+    if (tid == 0) s_info = 0;
+
+    int pos[R];
+    bool valid[R];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = base + u * NT + tid;
-        tmp[u] = (e < nn) ? A[e] : T(0);
-      }
+    for (int h = 0; h < R; ++h) {
+      pos[h] = h * 64 + lane;
+      valid[h] = pos[h] < n;
+    }
+    // ---- the system into registers (all loads issued before any use)
+    T v[R][C];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = base + u * NT + tid;
-        if (e < nn) As[e] = tmp[u];
+    for (int c = 0; c < C; ++c) {
+      const int j = c * NW + w;
+      const T* colp = j < n ? A + j * n : Bv;  // uniform column base
+      const bool live = j < n || (j == n && Bv);
+#pragma unroll
+      for (int h = 0; h < R; ++h) {
+        v[h][c] = T(0);
+        if (live && valid[h]) v[h][c] = colp[(uint32_t)pos[h]];
       }
     }
-    if (Bv)
-      for (int i = tid; i < n; i += NT) As[nn + i] = Bv[i];
-    __syncthreads();
 
-    for (int j0 = 0; j0 < n; j0 += W) {
-      const int w = (n - j0 < W) ? (n - j0) : W;
-      // ---- panel: columns j0 .. j0+w-1, rows j0 .. n-1, factored by wave 0
-      // with the rows in registers (lane holds rows lane and lane + 64).  Rows
-      // are not moved during the panel: pos0/pos1 give the logical row whose
-      // data each slot holds, an interchange swaps two logical positions, and
-      // the data is written to its final rows once at the end.
-      if (wave == 0) {
-        const int r0 = lane, r1 = lane + 64;
-        const bool ok0 = r0 >= j0 && r0 < n, ok1 = r1 >= j0 && r1 < n;
-        int pos0 = r0, pos1 = r1;
-        T v0[W], v1[W];
-#pragma unroll
-        for (int t = 0; t < W; ++t) {
-          v0[t] = (t < w && ok0) ? As[r0 + (j0 + t) * n] : T(0);
-          v1[t] = (t < w && ok1) ? As[r1 + (j0 + t) * n] : T(0);
-        }
-#pragma unroll
-        for (int t = 0; t < W; ++t) {
-          if (t < w) {
-            const int c = j0 + t;
-            // pivot: the largest |a| over logical rows >= c, lowest row on ties
-            const bool q0 = ok0 && pos0 >= c, q1 = ok1 && pos1 >= c;
-            const double a0 = q0 ? (double)fabs(v0[t]) : -1.0, a1 = q1 ? (double)fabs(v1[t]) : -1.0;
-            const double m = wave_max_f64(fmax(a0, a1));
-            const uint32_t k0 = (q0 && a0 == m) ? (uint32_t)pos0 : 0x7fffffffu;
-            const uint32_t k1 = (q1 && a1 == m) ? (uint32_t)pos1 : 0x7fffffffu;
-            const uint32_t pm = wave_min_u32(min(k0, k1));
-            const int p = (pm >= (uint32_t)c && pm < (uint32_t)n) ? (int)pm : c;  // c only with NaN entries
-            // where logical row p lives
-            const uint64_t b0 = __ballot(ok0 && pos0 == p), b1 = __ballot(ok1 && pos1 == p);
-            const bool in1 = b0 == 0;
-            const uint64_t bm = in1 ? b1 : b0;
-            const int pl = bm ? (int)__builtin_ctzll(bm) : 0;
-            T rp[W];
-#pragma unroll
-            for (int t2 = 0; t2 < W; ++t2) {
-              rp[t2] = T(0);
-              if (t2 >= t && t2 < w) rp[t2] = readlane_d(in1 ? v1[t2] : v0[t2], pl);
-            }
-            const T pv = rp[t];
-            if (lane == 0) {
-              s_piv[c] = p;
-              if (pv == T(0) && s_info == 0) s_info = c + 1;
-            }
-            if (p != c) {
-              pos0 = (pos0 == c) ? p : ((pos0 == p) ? c : pos0);
-              pos1 = (pos1 == c) ? p : ((pos1 == p) ? c : pos1);
-            }
-            // multipliers (true division: |l| <= 1 exactly) and the panel's rank-1 update
-            if (pv != T(0)) {
-              if (ok0 && pos0 > c) {
-                const T l = v0[t] / pv;
-                v0[t] = l;
-#pragma unroll
-                for (int t2 = t + 1; t2 < W; ++t2) v0[t2] -= l * rp[t2];
-              }
-              if (ok1 && pos1 > c) {
-                const T l = v1[t] / pv;
-                v1[t] = l;
-#pragma unroll
-                for (int t2 = t + 1; t2 < W; ++t2) v1[t2] -= l * rp[t2];
-              }
-            }
-          }
-        }
-#pragma unroll
-        for (int t = 0; t < W; ++t) {
-          if (t < w && ok0) As[pos0 + (j0 + t) * n] = v0[t];
-          if (t < w && ok1) As[pos1 + (j0 + t) * n] = v1[t];
-        }
-        // the block's interchanges composed: row pos <- row r for every moved row
-        const bool mv0 = ok0 && pos0 != r0, mv1 = ok1 && pos1 != r1;
-        const uint64_t m0 = __ballot(mv0), m1 = __ballot(mv1);
-        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        const int cnt0 = __popcll(m0);
-        if (mv0) {
-          const int q = __popcll(m0 & below);
-          s_pdst[q] = pos0;
-          s_psrc[q] = r0;
-        }
-        if (mv1) {
-          const int q = cnt0 + __popcll(m1 & below);
-          s_pdst[q] = pos1;
-          s_psrc[q] = r1;
-        }
-        if (lane == 0) s_npairs = cnt0 + __popcll(m1);
+    // ---- elimination
+    T lm[R];
+    int ps = 0, pp = 0;
+    bool nz = true;
+    // owner of column kp: record the pivot, store the multipliers at the
+    // rows' slots, publish them to the other wavefronts
+    auto publish = [&](int kp, const T(&col)[R], const T(&lo)[R], int ps1, int p1, bool nz1)
+                       __attribute__((always_inline)) {
+      if (lane == 0) {
+        s_piv[kp] = p1;
+        s_slot[kp] = ps1;
+        if (!nz1 && s_info == 0) s_info = kp + 1;
       }
-      __syncthreads();
-      // ---- per column outside the panel (b included), one column per thread:
-      // the block's composed interchanges (all moved rows read, then
-      // written), then U12 := inv(L11) A12 for the columns right of the panel
-      const int j1 = j0 + w;
-      {
-        const int np = s_npairs;
-        for (int j = tid; j < ncol; j += NT) {
-          if (j >= j0 && j < j1) continue;
-          if (np > 0) {
-            T val[2 * W];
+      T* colp = A + kp * n;
 #pragma unroll
-            for (int q = 0; q < 2 * W; ++q)
-              if (q < np) val[q] = As[s_psrc[q] + j * n];
+      for (int h = 0; h < R; ++h)
+        if (valid[h] && pos[h] >= kp && h * 64 + lane != ps1) colp[h * 64 + lane] = col[h];
+      if constexpr (NW > 1) {
+        const int b = kp & 1;
 #pragma unroll
-            for (int q = 0; q < 2 * W; ++q)
-              if (q < np) As[s_pdst[q] + j * n] = val[q];
-          }
-          if (j >= j1) {
-            T x[W];
-#pragma unroll
-            for (int q = 0; q < W; ++q) x[q] = (q < w) ? As[j0 + q + j * n] : T(0);
-#pragma unroll
-            for (int q = 0; q < W; ++q)
-#pragma unroll
-              for (int r = q + 1; r < W; ++r)
-                if (r < w) x[r] -= As[j0 + r + (j0 + q) * n] * x[q];
-#pragma unroll
-            for (int q = 1; q < W; ++q)
-              if (q < w) As[j0 + q + j * n] = x[q];
-          }
+        for (int h = 0; h < R; ++h) s_l[b][h * 64 + lane] = lo[h];
+        if (lane == 0) {
+          s_pp[b][0] = ps1;
+          s_pp[b][1] = p1;
+          s_pp[b][2] = nz1 ? 1 : 0;
         }
       }
-      if (j1 >= ncol) break;
-      __syncthreads();
-      // ---- A22 -= L21 U12: lanes over rows (two 64-row halves), waves over
-      // columns, two columns per step
-      if (j1 < n) {
-        T l[2][W];
-        const int i0 = j1 + lane, i1 = j1 + 64 + lane;
+    };
+    {
+      T lo[R];
+      int ps0 = 0, p0 = 0;
+      bool nz0 = true;
+      if (w == 0) {  // column 0: wavefront 0, local column 0
+        T col[R];
 #pragma unroll
-        for (int q = 0; q < W; ++q) {
-          l[0][q] = (q < w && i0 < n) ? As[i0 + (j0 + q) * n] : T(0);
-          l[1][q] = (q < w && i1 < n) ? As[i1 + (j0 + q) * n] : T(0);
+        for (int h = 0; h < R; ++h) col[h] = v[h][0];
+        pivot_column<R>(col, lo, pos, valid, 0, n, lane, ps0, p0, nz0);
+        publish(0, col, lo, ps0, p0, nz0);
+      }
+      if constexpr (NW > 1) {
+        lds_barrier();
+      } else {
+#pragma unroll
+        for (int h = 0; h < R; ++h) lm[h] = lo[h];
+        ps = ps0;
+        pp = p0;
+        nz = nz0;
+      }
+    }
+    for (int k = 0; k < n; ++k) {
+      if constexpr (NW > 1) {
+        const int b = k & 1;
+        ps = __builtin_amdgcn_readfirstlane(s_pp[b][0]);
+        pp = __builtin_amdgcn_readfirstlane(s_pp[b][1]);
+        nz = __builtin_amdgcn_readfirstlane(s_pp[b][2]) != 0;
+#pragma unroll
+        for (int h = 0; h < R; ++h) lm[h] = s_l[b][h * 64 + lane];
+      }
+      // the interchange of step k: the pivot slot takes logical row k, the
+      // slot that held row k takes the pivot's former position
+      T ln[R];
+#pragma unroll
+      for (int h = 0; h < R; ++h) {
+        const int sl = h * 64 + lane;
+        pos[h] = (sl == ps) ? k : ((pos[h] == k) ? pp : pos[h]);
+        ln[h] = (nz && valid[h] && pos[h] > k) ? -lm[h] : T(0);
+      }
+      const int hp = ps >> 6, lp = ps & 63;
+      // lookahead on column k+1
+      const int k1 = k + 1;
+      const bool own1 = k1 < n && (NW == 1 || k1 % NW == w);
+      T lo1[R];
+      int ps1 = 0, p1 = 0;
+      bool nz1 = true;
+      if (own1) {
+        const int c1 = k1 / NW;
+        T col[R];
+        dispatch<0, C>(c1, [&](auto ci) __attribute__((always_inline)) {
+          constexpr int c = decltype(ci)::value;
+#pragma unroll
+          for (int h = 0; h < R; ++h) col[h] = v[h][c];
+        });
+        T u1 = readlane_d(col[0], lp);
+        if constexpr (R > 1) {
+          const T u1h = readlane_d(col[R - 1], lp);
+          if (hp != 0) u1 = u1h;
         }
-        for (int j = j1 + wave; j < ncol; j += 2 * NW) {
-          const int jb = j + NW;
-          const bool two = jb < ncol;
-          T u[W], ub[W];
 #pragma unroll
-          for (int q = 0; q < W; ++q) {
-            u[q] = (q < w) ? As[j0 + q + j * n] : T(0);
-            ub[q] = (q < w && two) ? As[j0 + q + jb * n] : T(0);
-          }
-          T s0 = (i0 < n) ? As[i0 + j * n] : T(0);
-          T s1 = (i1 < n) ? As[i1 + j * n] : T(0);
-          T s2 = (i0 < n && two) ? As[i0 + jb * n] : T(0);
-          T s3 = (i1 < n && two) ? As[i1 + jb * n] : T(0);
+        for (int h = 0; h < R; ++h) col[h] = fma(ln[h], u1, col[h]);
+        pivot_column<R>(col, lo1, pos, valid, k1, n, lane, ps1, p1, nz1);
+        publish(k1, col, lo1, ps1, p1, nz1);
+      }
+      // rank-1 update of the local columns from cmin on (the first column
+      // right of k), in chunks of eight: the chunk's pivot-row entries are
+      // read from the pivot lane into scalar registers (a branch on the
+      // pivot's half that writes scalars only), then every lane applies its
+      // FMAs.  A column left of cmin inside a live chunk is updated too: on
+      // rows below the pivot it holds L entries, whose values were stored
+      // when the column was factored, and the other rows have a zero
+      // multiplier.
+      const int cmin = k < w ? 0 : (k - w) / NW + 1;
+      constexpr int CH = 8;
 #pragma unroll
-          for (int q = 0; q < W; ++q) {
-            s0 -= l[0][q] * u[q];
-            s1 -= l[1][q] * u[q];
-            s2 -= l[0][q] * ub[q];
-            s3 -= l[1][q] * ub[q];
+      for (int c0 = 0; c0 < C; c0 += CH) {
+        if (c0 + CH - 1 >= cmin) {
+          T u[CH];
+          if (R == 1 || hp == 0) {
+#pragma unroll
+            for (int c = c0; c < c0 + CH && c < C; ++c) u[c - c0] = readlane_d(v[0][c], lp);
+          } else {
+#pragma unroll
+            for (int c = c0; c < c0 + CH && c < C; ++c) u[c - c0] = readlane_d(v[R - 1][c], lp);
           }
-          if (i0 < n) As[i0 + j * n] = s0;
-          if (i1 < n) As[i1 + j * n] = s1;
-          if (two && i0 < n) As[i0 + jb * n] = s2;
-          if (two && i1 < n) As[i1 + jb * n] = s3;
+#pragma unroll
+          for (int c = c0; c < c0 + CH && c < C; ++c)
+#pragma unroll
+            for (int h = 0; h < R; ++h) v[h][c] = fma(ln[h], u[c - c0], v[h][c]);
         }
       }
-      __syncthreads();
+      if constexpr (NW > 1) {
+        lds_barrier();
+      } else {
+#pragma unroll
+        for (int h = 0; h < R; ++h) lm[h] = lo1[h];
+        ps = ps1;
+        pp = p1;
+        nz = nz1;
+      }
     }
     __syncthreads();
-
-    // ---- x = inv(U) c with c = L^{-1} P b in column n (one wave; skipped on a
-    // zero pivot, as in LAPACK's gesv): reciprocals of the diagonal first, the
-    // next column of U prefetched while the current one is applied
     const int info = s_info;
-    if (Bv && info == 0 && wave == 0) {
-      T c0 = (lane < n) ? As[nn + lane] : T(0);
-      T c1 = (lane + 64 < n) ? As[nn + lane + 64] : T(0);
-      const T d0 = (lane < n) ? T(1) / As[lane + lane * n] : T(0);
-      const T d1 = (lane + 64 < n) ? T(1) / As[lane + 64 + (lane + 64) * n] : T(0);
-      int k = n - 1;
-      T u0 = (lane < k) ? As[lane + k * n] : T(0);
-      T u1 = (lane + 64 < k) ? As[lane + 64 + k * n] : T(0);
-      for (; k >= 0; --k) {
-        T u0n = T(0), u1n = T(0);
-        if (k > 0) {
-          if (lane < k - 1) u0n = As[lane + (k - 1) * n];
-          if (lane + 64 < k - 1) u1n = As[lane + 64 + (k - 1) * n];
-        }
-        const bool hi = k >= 64;
-        const int kl = hi ? k - 64 : k;
-        const T xk = readlane_d(hi ? c1 : c0, kl) * readlane_d(hi ? d1 : d0, kl);
-        if (!hi && lane == kl) c0 = xk;
-        if (hi && lane == kl) c1 = xk;
-        c0 -= u0 * xk;
-        c1 -= u1 * xk;
-        u0 = u0n;
-        u1 = u1n;
+
+    // ---- L\U to its final rows: L (rows below the diagonal) from the
+    // slot-ordered copy, U from the registers; every load of the workgroup
+    // completes before any store moves a row
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int j = c * NW + w;
+      if (j < n) {
+        const T* colp = A + j * n;
+#pragma unroll
+        for (int h = 0; h < R; ++h)
+          if (valid[h] && pos[h] > j) v[h][c] = colp[h * 64 + lane];
       }
-      if (lane < n) Bv[lane] = c0;
-      if (lane + 64 < n) Bv[lane + 64] = c1;
     }
-    for (int e = tid; e < nn; e += NT) A[e] = As[e];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int j = c * NW + w;
+      if (j < n) {
+        T* colp = A + j * n;
+#pragma unroll
+        for (int h = 0; h < R; ++h)
+          if (valid[h]) colp[(uint32_t)pos[h]] = v[h][c];
+      }
+    }
+
+    // ---- x = inv(U) c by the wavefront holding b
+    if (Bv && info == 0) {
+      __syncthreads();  // the stored factors are visible to the workgroup
+      if (w == n % NW) {
+        T cv[R], rd[R];
+        int sl[R];
+        dispatch<0, C>(n / NW, [&](auto ci) __attribute__((always_inline)) {
+          constexpr int c = decltype(ci)::value;
+#pragma unroll
+          for (int h = 0; h < R; ++h) cv[h] = v[h][c];
+        });
+#pragma unroll
+        for (int h = 0; h < R; ++h) {
+          rd[h] = valid[h] ? T(1) / A[pos[h] + pos[h] * n] : T(0);
+          sl[h] = valid[h] ? s_slot[h * 64 + lane] : 0;
+        }
+        // U's column k at this lane's rows, D columns ahead; the loads are
+        // unconditional (row and column clamped into the matrix) so that
+        // none waits for the others, and the entries not above the diagonal
+        // are masked where they are used
+        constexpr int D = 10;
+        int prow[R];
+#pragma unroll
+        for (int h = 0; h < R; ++h) prow[h] = valid[h] ? pos[h] : 0;
+        T ub[D][R];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const int kk = max(n - 1 - d, 0);
+#pragma unroll
+          for (int h = 0; h < R; ++h) ub[d][h] = A[prow[h] + kk * n];
+        }
+        for (int kb = n - 1; kb >= 0; kb -= D) {
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            const int k = kb - d;
+            if (k < 0) break;
+            const int sk = (R == 1 || k < 64) ? __builtin_amdgcn_readlane(sl[0], k & 63)
+                                              : __builtin_amdgcn_readlane(sl[R - 1], k & 63);
+            const int lk = sk & 63;
+            const T xk = (R == 1 || sk < 64) ? readlane_d(cv[0], lk) * readlane_d(rd[0], lk)
+                                             : readlane_d(cv[R - 1], lk) * readlane_d(rd[R - 1], lk);
+#pragma unroll
+            for (int h = 0; h < R; ++h) {
+              const T t = fma(-ub[d][h], xk, cv[h]);
+              cv[h] = (h * 64 + lane == sk) ? xk : ((valid[h] && pos[h] < k) ? t : cv[h]);
+            }
+            const int kn = max(k - D, 0);
+#pragma unroll
+            for (int h = 0; h < R; ++h) ub[d][h] = A[prow[h] + kn * n];
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < R; ++h)
+          if (valid[h]) Bv[pos[h]] = cv[h];
+      }
+    }
     int32_t* P = gpiv + poff[sys];
     for (int k = tid; k < n; k += NT) P[k] = s_piv[k] + 1;
     if (tid == 0) ginfo[sys] = info;
-    __syncthreads();
+    __syncthreads();  // LDS reused by the next system
   }
 }
 
+// size classes: (wavefronts, row slots per lane, columns per wavefront)
 template <typename T>
 const void* batch_kernel(int cls) {
   switch (cls) {
-    case 0: return (const void*)k_batch_lu<T, 64>;
-    case 1: return (const void*)k_batch_lu<T, 256>;
-    default: return (const void*)k_batch_lu<T, 512>;
+    case 0: return (const void*)k_batch_lu<T, 1, 1, 33>;
+    case 1: return (const void*)k_batch_lu<T, 2, 1, 33>;
+    case 2: return (const void*)k_batch_lu<T, 4, 2, 25>;
+    default: return (const void*)k_batch_lu<T, 4, 2, 33>;
   }
 }
-inline int class_threads(int cls) { return cls == 0 ? 64 : (cls == 1 ? 256 : 512); }
-inline int class_nmax(int cls) { return 32 * (cls + 1); }
-template <typename T>
-size_t class_lds(int cls) {
-  const size_t nm = (size_t)class_nmax(cls);
-  return nm * (nm + 1) * sizeof(T);
-}
+inline int class_threads(int cls) { return cls == 0 ? 64 : (cls == 1 ? 128 : 256); }
 
 template <typename T>
 hipError_t setup_class_kernels(lupp_handle_t h, BatchWs* w, int prec) {
@@ -349,10 +460,8 @@ hipError_t setup_class_kernels(lupp_handle_t h, BatchWs* w, int prec) {
   LUPP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
   for (int c = 0; c < kBatchClasses; ++c) {
     const void* f = batch_kernel<T>(c);
-    const size_t lds = class_lds<T>(c);
-    LUPP_TRY(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int occ = 0;
-    LUPP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, class_threads(c), lds));
+    LUPP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, class_threads(c), 0));
     if (occ < 1) return hipErrorInvalidConfiguration;
     w->grid[prec][c] = occ * ncu;
   }
@@ -425,9 +534,10 @@ int gesv_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_
     e = hipStreamWaitEvent(sc, w->fork, 0);
     if (e != hipSuccess) return hip_status(e);
     const void* f = batch_kernel<T>(c);
+    const int32_t* meta = w->meta;
     void* args[] = {(void*)&c, (void*)&dn, (void*)&aoff, (void*)&A, (void*)&poff, (void*)&piv, (void*)&boff,
-                    (void*)&B, (void*)&info, (void*)&w->list, (void*)&w->meta};
-    e = hipLaunchKernel(f, dim3(w->grid[prec][c]), dim3(class_threads(c)), args, class_lds<T>(c), sc);
+                    (void*)&B, (void*)&info, (void*)&w->list, (void*)&meta};
+    e = hipLaunchKernel(f, dim3(w->grid[prec][c]), dim3(class_threads(c)), args, 0, sc);
     if (e != hipSuccess) return hip_status(e);
     e = hipEventRecord(w->join[c], sc);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, w->join[c], 0);

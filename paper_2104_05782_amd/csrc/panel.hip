@@ -79,16 +79,6 @@ __device__ __forceinline__ void release_stores() {
 }
 
 
-// Workgroup barrier that waits only for LDS traffic.  (__syncthreads also
-// waits for every outstanding global load and store of the wave, which would
-// put a memory round trip on each pivot step.)  The signal fences keep the
-// compiler from moving LDS accesses across it.
-__device__ __forceinline__ void lds_barrier() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), vmcnt and expcnt untouched
-  __builtin_amdgcn_s_barrier();
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
 
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_panel_block(int64_t r, int wt, T* __restrict__ P, int64_t ld,

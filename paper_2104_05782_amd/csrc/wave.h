@@ -127,11 +127,42 @@ __device__ __forceinline__ float row_bcast(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + K, 0xF, 0xF, false));
 }
 
+// Workgroup barrier that waits only for LDS traffic.  (__syncthreads also
+// waits for every outstanding global load and store of the wave, which would
+// put a memory round trip on each step.)  The signal fences keep the compiler
+// from moving LDS accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), vmcnt and expcnt untouched
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 template <int K, int N, typename F>
 __device__ __forceinline__ void static_for(F&& f) {
   if constexpr (K < N) {
     f(std::integral_constant<int, K>());
     static_for<K + 1, N>(f);
+  }
+}
+
+// f(integral_constant<c>) for a wave-uniform runtime c in [LO, HI): a
+// balanced tree of scalar branches, so that register arrays are indexed with
+// compile-time subscripts only.
+template <int LO, int HI, typename F>
+__device__ __forceinline__ void dispatch(int c, F&& f) {
+  if constexpr (HI - LO == 1) {
+    f(std::integral_constant<int, LO>());
+    // an empty asm statement with the leaf's constant keeps the optimizer
+    // from merging the leaves into one access at a computed offset (which
+    // would move the register array to scratch memory)
+    __asm__ volatile("; leaf %0" ::"n"(LO));
+  } else {
+    constexpr int MID = (LO + HI) / 2;
+    if (c < MID)
+      dispatch<LO, MID>(c, f);
+    else
+      dispatch<MID, HI>(c, f);
   }
 }
 
