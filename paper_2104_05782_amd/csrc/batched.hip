@@ -26,6 +26,11 @@ namespace lupp {
 
 constexpr int kBatchClasses = 4;
 constexpr int kBatchMaxN = 128;
+// Bound on a wavefront's wait for a published step (iterations of a ~64-cycle
+// sleep, about 0.1 s): a wait that long means a fault in the schedule, and the
+// system is then abandoned with info = kStalled instead of hanging the GPU.
+constexpr int kSpinLimit = 1 << 22;
+constexpr int kStalled = -1000;
 
 // Workspace of the batched path: per-class system lists and counters.
 struct BatchWs {
@@ -154,7 +159,8 @@ __device__ __forceinline__ void pivot_column(T (&col)[R], T (&lo)[R], const int 
 //
 // Step k:
 //  - the multipliers and the pivot slot come from the wavefront owning
-//    column k through LDS (one LDS-only barrier per step);
+//    column k through LDS, published with a step counter: a wavefront waits
+//    only for the step it needs, not for the other wavefronts' updates;
 //  - each wavefront reads the pivot row's entries of its columns from the
 //    pivot lane into scalar registers (v_readlane: 8 bytes per column, where
 //    a broadcast through LDS would move 512 and saturate the LDS pipe) and
@@ -185,8 +191,15 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 3 : 4) void k_batch_lu(int cls, 
                                                       int32_t* __restrict__ ginfo, const int32_t* __restrict__ list,
                                                       const int32_t* __restrict__ meta) {
   constexpr int NT = 64 * NW;
-  __shared__ T s_l[2][64 * R];                       // multipliers of the current and the next step
-  __shared__ int s_pp[2][4];                         // pivot slot, pivot's logical row, pivot nonzero
+  // Published steps, a ring of kRing slots: slot k % kRing is rewritten for
+  // step k + kRing, published by its owner only after every wavefront has
+  // published a later step than k (each owns one of any NW consecutive
+  // steps), hence has read slot k; kRing >= NW + 1 suffices.
+  constexpr int kRing = 8;
+  static_assert(kRing >= NW + 1, "ring of published steps too short");
+  __shared__ T s_l[kRing][64 * R];  // multipliers
+  __shared__ int s_pp[kRing][4];    // pivot slot, pivot's logical row, pivot nonzero
+  __shared__ int s_done;            // steps published so far
   __shared__ int s_slot[kBatchMaxN], s_piv[kBatchMaxN];
   __shared__ int s_info;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -199,7 +212,11 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 3 : 4) void k_batch_lu(int cls, 
     const int n = dn[sys];
     T* A = gA + aoff[sys];
     T* Bv = gB ? gB + boff[sys] : nullptr;
-    if (tid == 0) s_info = 0;
+    if (tid == 0) {
+      s_info = 0;
+      s_done = 0;
+    }
+    __syncthreads();  // no wavefront sees the previous system's counter
 
     int pos[R];
     bool valid[R];
@@ -240,13 +257,14 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 3 : 4) void k_batch_lu(int cls, 
       for (int h = 0; h < R; ++h)
         if (valid[h] && pos[h] >= kp && h * 64 + lane != ps1) colp[h * 64 + lane] = col[h];
       if constexpr (NW > 1) {
-        const int b = kp & 1;
+        const int b = kp % kRing;
 #pragma unroll
         for (int h = 0; h < R; ++h) s_l[b][h * 64 + lane] = lo[h];
         if (lane == 0) {
           s_pp[b][0] = ps1;
           s_pp[b][1] = p1;
           s_pp[b][2] = nz1 ? 1 : 0;
+          __hip_atomic_store(&s_done, kp + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       }
     };
@@ -261,9 +279,7 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 3 : 4) void k_batch_lu(int cls, 
         pivot_column<R>(col, lo, pos, valid, 0, n, lane, ps0, p0, nz0);
         publish(0, col, lo, ps0, p0, nz0);
       }
-      if constexpr (NW > 1) {
-        lds_barrier();
-      } else {
+      if constexpr (NW == 1) {
 #pragma unroll
         for (int h = 0; h < R; ++h) lm[h] = lo[h];
         ps = ps0;
@@ -271,9 +287,22 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 3 : 4) void k_batch_lu(int cls, 
         nz = nz0;
       }
     }
+    bool stalled = false;
     for (int k = 0; k < n; ++k) {
       if constexpr (NW > 1) {
-        const int b = k & 1;
+        // wait for step k (bounded: on a stall the system is abandoned, so
+        // that no wavefront can spin forever)
+        int spins = 0;
+        while (__builtin_amdgcn_readfirstlane(
+                   __hip_atomic_load(&s_done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) <= k) {
+          if (++spins > kSpinLimit) {
+            stalled = true;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        if (stalled) break;
+        const int b = k % kRing;
         ps = __builtin_amdgcn_readfirstlane(s_pp[b][0]);
         pp = __builtin_amdgcn_readfirstlane(s_pp[b][1]);
         nz = __builtin_amdgcn_readfirstlane(s_pp[b][2]) != 0;
@@ -341,9 +370,7 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 3 : 4) void k_batch_lu(int cls, 
             for (int h = 0; h < R; ++h) v[h][c] = fma(ln[h], u[c - c0], v[h][c]);
         }
       }
-      if constexpr (NW > 1) {
-        lds_barrier();
-      } else {
+      if constexpr (NW == 1) {
 #pragma unroll
         for (int h = 0; h < R; ++h) lm[h] = lo1[h];
         ps = ps1;
@@ -351,8 +378,14 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 3 : 4) void k_batch_lu(int cls, 
         nz = nz1;
       }
     }
+    if (stalled && lane == 0) s_info = kStalled;
     __syncthreads();
     const int info = s_info;
+    if (info == kStalled) {  // nothing stored; info reports it
+      if (tid == 0) ginfo[sys] = info;
+      __syncthreads();
+      continue;
+    }
 
     // ---- L\U to its final rows: L (rows below the diagonal) from the
     // slot-ordered copy, U from the registers; every load of the workgroup
