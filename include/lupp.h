@@ -250,9 +250,9 @@ int lupp_dgesv_mixed(lupp_handle_t h, int64_t n, int64_t nrhs, const double* dA,
  *
  * The paper's factorizations are of one large matrix; this entry point
  * applies the same factorization (partial pivoting, LAPACK conventions, the
- * blocked right-looking loop of Section 4.3 with its column-block step of
- * Section 4.1) to a batch of small systems at once, one workgroup per system
- * with the system held in on-chip memory.
+ * elimination step of Section 4.1 taken one column at a time) to a batch of
+ * small systems at once, one workgroup per system with the system held in
+ * registers.
  *
  *   batch       number of systems (>= 0)
  *   dn          device int32[batch]: order n_i of system i, 0 <= n_i <= 128
@@ -265,7 +265,10 @@ int lupp_dgesv_mixed(lupp_handle_t h, int64_t n, int64_t nrhs, const double* dA,
  *   dinfo       device int32[batch]: 0; k > 0 when U(k,k) of system i is
  *               exactly zero (the factorization completes, x_i is not
  *               computed and b_i is left unchanged, as in LAPACK's gesv);
- *               -1 when n_i is outside [0, 128] (system untouched)
+ *               -1 when n_i is outside [0, 128] (system untouched);
+ *               -1000 if the workgroup's internal step schedule stalled
+ *               (bounded waits; a fault in the library, never expected):
+ *               system i's outputs are then not written
  * Systems must not overlap.  The call is asynchronous on the handle's
  * stream; it allocates its workspace on the first call for a batch size and
  * afterwards neither allocates nor synchronizes with the host, so it can be
