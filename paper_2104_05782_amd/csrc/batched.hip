@@ -247,16 +247,7 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 3 : 4) void k_batch_lu(int cls, 
     // rows' slots, publish them to the other wavefronts
     auto publish = [&](int kp, const T(&col)[R], const T(&lo)[R], int ps1, int p1, bool nz1)
                        __attribute__((always_inline)) {
-      if (lane == 0) {
-        s_piv[kp] = p1;
-        s_slot[kp] = ps1;
-        if (!nz1 && s_info == 0) s_info = kp + 1;
-      }
-      T* colp = A + kp * n;
-#pragma unroll
-      for (int h = 0; h < R; ++h)
-        if (valid[h] && pos[h] >= kp && h * 64 + lane != ps1) colp[h * 64 + lane] = col[h];
-      if constexpr (NW > 1) {
+      if constexpr (NW > 1) {  // the step record first: the other wavefronts wait for it
         const int b = kp % kRing;
 #pragma unroll
         for (int h = 0; h < R; ++h) s_l[b][h * 64 + lane] = lo[h];
@@ -267,6 +258,15 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 3 : 4) void k_batch_lu(int cls, 
           __hip_atomic_store(&s_done, kp + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       }
+      if (lane == 0) {
+        s_piv[kp] = p1;
+        s_slot[kp] = ps1;
+        if (!nz1 && s_info == 0) s_info = kp + 1;
+      }
+      T* colp = A + kp * n;
+#pragma unroll
+      for (int h = 0; h < R; ++h)
+        if (valid[h] && pos[h] >= kp && h * 64 + lane != ps1) colp[h * 64 + lane] = col[h];
     };
     {
       T lo[R];
@@ -326,6 +326,8 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 3 : 4) void k_batch_lu(int cls, 
       int ps1 = 0, p1 = 0;
       bool nz1 = true;
       if (own1) {
+        // the lookahead is the critical path: its wavefront first in issue
+        if constexpr (NW > 1) __builtin_amdgcn_s_setprio(3);
         const int c1 = k1 / NW;
         T col[R];
         dispatch<0, C>(c1, [&](auto ci) __attribute__((always_inline)) {
@@ -342,6 +344,7 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 3 : 4) void k_batch_lu(int cls, 
         for (int h = 0; h < R; ++h) col[h] = fma(ln[h], u1, col[h]);
         pivot_column<R>(col, lo1, pos, valid, k1, n, lane, ps1, p1, nz1);
         publish(k1, col, lo1, ps1, p1, nz1);
+        if constexpr (NW > 1) __builtin_amdgcn_s_setprio(0);
       }
       // rank-1 update of the local columns from cmin on (the first column
       // right of k), in chunks of eight: the chunk's pivot-row entries are
