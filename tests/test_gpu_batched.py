@@ -178,6 +178,43 @@ def test_batch_singular_and_rejected():
     assert torch.equal(dA, before)
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_batch_nonfinite_inputs_isolated(dtype):
+    """NaN and +-Inf entries are outside the contract (results unspecified),
+    but the call completes, no system is abandoned (info -1000), every pivot
+    index stays in range, and the finite systems of the same batch come out
+    bit for bit as in a batch without the bad ones."""
+    announce("batched non-finite inputs %s" % np.dtype(dtype).name)
+    ns = [5, 40, 70, 100, 128, 17, 64, 96]
+    good = [synth.uniform(48, 10 + i, n, n) for i, n in enumerate(ns)]
+    grhs = [synth.uniform(48, 100 + i, n, 1)[:, 0] for i, n in enumerate(ns)]
+    bad = []
+    for i, n in enumerate(ns):
+        m = synth.uniform(48, 200 + i, n, n)
+        m[(3 * i) % n, (5 * i + 1) % n] = np.nan
+        m[(7 * i + 2) % n, (2 * i) % n] = np.inf if i % 2 else -np.inf
+        bad.append(m)
+    brhs = [synth.uniform(48, 300 + i, n, 1)[:, 0] for i, n in enumerate(ns)]
+    # interleaved: good, bad, good, bad, ...
+    mats = [m for pair in zip(good, bad) for m in pair]
+    rhs = [b for pair in zip(grhs, brhs) for b in pair]
+    sizes, A, a_off, B, b_off = _pack(mats, rhs, dtype)
+    LU, ipiv, p_off, info, X = _run(sizes, A, a_off, B, b_off)
+    assert not np.any(info == -1000), info
+    for i, n in enumerate(sizes):
+        pi = ipiv[p_off[i]:p_off[i] + n]
+        assert np.all(pi >= np.arange(1, n + 1)) and np.all(pi <= n), (i, pi)
+    sg, Ag, ag, Bg, bg = _pack(good, grhs, dtype)
+    LUg, ipg, pg, infg, Xg = _run(sg, Ag, ag, Bg, bg)
+    for j, n in enumerate(ns):
+        i = 2 * j
+        assert info[i] == infg[j] == 0
+        assert np.array_equal(LU[a_off[i]:a_off[i] + n * n].view(np.uint8),
+                              LUg[ag[j]:ag[j] + n * n].view(np.uint8)), j
+        assert np.array_equal(ipiv[p_off[i]:p_off[i] + n], ipg[pg[j]:pg[j] + n])
+        assert np.array_equal(X[b_off[i]:b_off[i] + n].view(np.uint8), Xg[bg[j]:bg[j] + n].view(np.uint8))
+
+
 def test_batch_host_errors():
     announce("batched host errors")
     dn = torch.ones(2, dtype=torch.int32, device="cuda")
