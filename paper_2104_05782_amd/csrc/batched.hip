@@ -11,7 +11,7 @@
 //
 // Scheduling: a binning kernel sorts the systems into four size classes
 // (n <= 32, 64, 96, 128), each served by one persistent launch whose
-// workgroups (1, 2, 4, 4 wavefronts) take the class's systems in round
+// workgroups (1, 2 (FP64) or 1 (FP32), 4, 4 wavefronts) take the class's systems in round
 // robin (no shared counter: thousands of workgroups contending for one
 // global atomic cost more than the small systems themselves).  A
 // CU's register file (512 KB) holds several systems of every class, where its
@@ -183,8 +183,13 @@ __device__ __forceinline__ void pivot_column(T (&col)[R], T (&lo)[R], const int 
 // values the FMA leaves such rows exactly unchanged (up to the sign of a
 // zero); with +-Inf or NaN in the pivot row they become NaN where LAPACK
 // would leave them.
+// wavefronts per SIMD to ask of the register allocator: the matrix takes
+// 2*R*C VGPRs in FP64, and what is left must hold the step's working set
+template <int R, int C>
+constexpr int kMinWaves = R * C > 80 ? 2 : (R * C > 40 ? 3 : 4);
+
 template <typename T, int NW, int R, int C>
-__global__ __launch_bounds__(64 * NW, NW == 4 ? 3 : 4) void k_batch_lu(int cls, const int32_t* __restrict__ dn,
+__global__ __launch_bounds__(64 * NW, (kMinWaves<R, C>)) void k_batch_lu(int cls, const int32_t* __restrict__ dn,
                                                       const int64_t* __restrict__ aoff, T* __restrict__ gA,
                                                       const int64_t* __restrict__ poff, int32_t* __restrict__ gpiv,
                                                       const int64_t* __restrict__ boff, T* __restrict__ gB,
@@ -483,12 +488,17 @@ template <typename T>
 const void* batch_kernel(int cls) {
   switch (cls) {
     case 0: return (const void*)k_batch_lu<T, 1, 1, 33>;
-    case 1: return (const void*)k_batch_lu<T, 2, 1, 33>;
+    case 1:  // one wavefront in FP32; in FP64 its 163 VGPRs pack worse beside the other classes
+      if constexpr (sizeof(T) == 4) return (const void*)k_batch_lu<T, 1, 1, 65>;
+      return (const void*)k_batch_lu<T, 2, 1, 33>;
     case 2: return (const void*)k_batch_lu<T, 4, 2, 25>;
     default: return (const void*)k_batch_lu<T, 4, 2, 33>;
   }
 }
-inline int class_threads(int cls) { return cls == 0 ? 64 : (cls == 1 ? 128 : 256); }
+template <typename T>
+int class_threads(int cls) {
+  return cls == 0 ? 64 : (cls == 1 ? (sizeof(T) == 4 ? 64 : 128) : 256);
+}
 
 template <typename T>
 hipError_t setup_class_kernels(lupp_handle_t h, BatchWs* w, int prec) {
@@ -497,7 +507,7 @@ hipError_t setup_class_kernels(lupp_handle_t h, BatchWs* w, int prec) {
   for (int c = 0; c < kBatchClasses; ++c) {
     const void* f = batch_kernel<T>(c);
     int occ = 0;
-    LUPP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, class_threads(c), 0));
+    LUPP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, class_threads<T>(c), 0));
     if (occ < 1) return hipErrorInvalidConfiguration;
     w->grid[prec][c] = occ * ncu;
   }
@@ -573,7 +583,7 @@ int gesv_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_
     const int32_t* meta = w->meta;
     void* args[] = {(void*)&c, (void*)&dn, (void*)&aoff, (void*)&A, (void*)&poff, (void*)&piv, (void*)&boff,
                     (void*)&B, (void*)&info, (void*)&w->list, (void*)&meta};
-    e = hipLaunchKernel(f, dim3(w->grid[prec][c]), dim3(class_threads(c)), args, 0, sc);
+    e = hipLaunchKernel(f, dim3(w->grid[prec][c]), dim3(class_threads<T>(c)), args, 0, sc);
     if (e != hipSuccess) return hip_status(e);
     e = hipEventRecord(w->join[c], sc);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, w->join[c], 0);
