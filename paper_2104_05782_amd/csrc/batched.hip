@@ -11,9 +11,10 @@
 //
 // Scheduling: a binning kernel sorts the systems into four size classes
 // (n <= 32, 64, 96, 128), each served by one persistent launch whose
-// workgroups (1, 2 (FP64) or 1 (FP32), 4, 4 wavefronts) take the class's systems in round
-// robin (no shared counter: thousands of workgroups contending for one
-// global atomic cost more than the small systems themselves).  A
+// workgroups (1, 2 in FP64 or 1 in FP32, 4, 4 wavefronts) take the class's
+// systems in round robin (no shared counter: thousands of workgroups
+// contending for one global atomic cost more than the small systems
+// themselves).  A
 // CU's register file (512 KB) holds several systems of every class, where its
 // LDS (160 KB) would hold one of the largest.  The classes are launched on
 // four streams so that the short classes fill the CUs the long ones leave
@@ -146,6 +147,11 @@ __device__ __forceinline__ void pivot_column(T (&col)[R], T (&lo)[R], const int 
   nz_out = nz;
 }
 
+// wavefronts per SIMD to ask of the register allocator: the matrix takes
+// 2*R*C VGPRs in FP64, and what is left must hold the step's working set
+template <int R, int C>
+constexpr int kMinWaves = R * C > 80 ? 2 : (R * C > 40 ? 3 : 4);
+
 // One system per workgroup of NW wavefronts, the whole augmented matrix
 // [A | b] in registers: lane l holds rows l and (R = 2) l + 64, wavefront w
 // holds columns w, w + NW, w + 2 NW, ... (C of them at most; b is column n).
@@ -183,11 +189,6 @@ __device__ __forceinline__ void pivot_column(T (&col)[R], T (&lo)[R], const int 
 // values the FMA leaves such rows exactly unchanged (up to the sign of a
 // zero); with +-Inf or NaN in the pivot row they become NaN where LAPACK
 // would leave them.
-// wavefronts per SIMD to ask of the register allocator: the matrix takes
-// 2*R*C VGPRs in FP64, and what is left must hold the step's working set
-template <int R, int C>
-constexpr int kMinWaves = R * C > 80 ? 2 : (R * C > 40 ? 3 : 4);
-
 template <typename T, int NW, int R, int C>
 __global__ __launch_bounds__(64 * NW, (kMinWaves<R, C>)) void k_batch_lu(int cls, const int32_t* __restrict__ dn,
                                                       const int64_t* __restrict__ aoff, T* __restrict__ gA,
