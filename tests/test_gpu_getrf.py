@@ -189,6 +189,33 @@ def test_getrs_multi_rhs(dtype):
                                      B[:, j].astype(np.float64)) <= 8 * n * u
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [1000, 3000])
+def test_nonfinite_inputs_complete(n, dtype):
+    """NaN and +-Inf entries are outside the contract (results unspecified),
+    but getrf and getrs complete without a library error (no expired wait),
+    every pivot index stays in range and info is not negative."""
+    announce("non-finite n=%d %s" % (n, dtype))
+    npdt = np.float64 if dtype == "f64" else np.float32
+    A = synth.uniform(49, 0, n, n).astype(npdt)
+    A[n // 3, 5] = np.nan
+    A[7, n // 2] = np.inf
+    A[n - 2, n - 9] = -np.inf
+    h = lupp.Handle()
+    dA = to_dev(A)
+    ipiv, info = lupp.getrf(dA, handle=h)
+    h.sync()
+    torch.cuda.synchronize()
+    ip = ipiv.cpu().numpy()
+    assert np.all(ip >= np.arange(1, n + 1)) and np.all(ip <= n)
+    assert int(info.item()) >= 0
+    dB = to_dev(synth.uniform(49, 1, n, 1).astype(npdt))
+    lupp.getrs(dA, ipiv, dB, handle=h)
+    h.sync()
+    torch.cuda.synchronize()
+    h.close()
+
+
 def _factor_opts(A, **opts):
     h = lupp.Handle()
     for k, v in opts.items():
