@@ -177,6 +177,21 @@ def test_mixed_singular():
     assert not np.any(x)
 
 
+@pytest.mark.parametrize("solver", ["classical", "gmres"])
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_mixed_nonfinite_input(solver, prec):
+    """A NaN and an Inf in A are outside the contract, but the call returns
+    normally with a status that does not claim convergence."""
+    n = 600
+    announce("mixed non-finite n=%d %s %s" % (n, prec, solver))
+    A = synth.uniform(17, 0, n, n)
+    A[10, 20] = np.nan
+    A[300, 5] = np.inf
+    b = synth.uniform(17, 1, n, 1)[:, 0]
+    _, rep = _mixed(A, b, solver, prec)
+    assert rep["status_name"] in ("diverged", "stagnated", "maxiter", "singular"), rep
+
+
 def test_mixed_fallback_fp64():
     """One FP8 classical iteration cannot reach 1e-14: MAXITER, then the FP64
     fallback solves the system."""
