@@ -55,6 +55,7 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, const T* __restrict__ A
                                               uint32_t* __restrict__ flags, uint64_t* __restrict__ ticket,
                                               uint64_t tbase, uint32_t epoch, int32_t* __restrict__ err) {
   __shared__ T s_part[4][TB];
+  __shared__ T s_diag[TB * TB];
   __shared__ int64_t s_blk;
   __shared__ int s_ready;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -77,6 +78,13 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, const T* __restrict__ A
   // matrix tile does not depend on the flag, so this wave's 16 columns of it
   // are loaded now; after the flag only x is read.
   T apf[16];
+  // the diagonal block depends on nothing either: staged in LDS before the
+  // waits (column-major, so wave 0 reads its rows without bank conflicts), it
+  // is off the critical path
+  for (int e = tid; e < TB * TB; e += 256) {
+    const int c = e / TB, rr = e % TB;
+    s_diag[e] = (r0 + rr < n && r0 + c < n) ? A[(r0 + rr) + (r0 + c) * lda] : T(0);
+  }
   const int64_t lastd = ndep - 1;
   if (ndep > 0) {
     const int64_t c0 = (LOWER ? lastd : (nblk - 1 - lastd)) * TB + wave * 16;
@@ -136,10 +144,10 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, const T* __restrict__ A
   if (wave == 0) {
     T v = rok ? x[row] : T(0);
     v = v + s_part[0][lane] + s_part[1][lane] + s_part[2][lane] + s_part[3][lane];
-    // diagonal block: lane holds row `lane` of it
+    // diagonal block (staged at the start): lane holds row `lane` of it
     T dr[TB];
 #pragma unroll
-    for (int c = 0; c < TB; ++c) dr[c] = (rok && r0 + c < n) ? A[row + (r0 + c) * lda] : T(0);
+    for (int c = 0; c < TB; ++c) dr[c] = s_diag[c * TB + lane];
     if (LOWER) {
 #pragma unroll
       for (int k = 0; k < TB; ++k) {
