@@ -155,9 +155,13 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, const T* __restrict__ A
         if (lane > k) v = v - dr[k] * xk;
       }
     } else {
+      // each lane's reciprocal of its diagonal entry, computed once: the
+      // chain below then multiplies instead of dividing (64 dependent
+      // divisions were half of the upper solve's step)
+      const T dinv = T(1) / s_diag[lane * TB + lane];
 #pragma unroll
       for (int k = TB - 1; k >= 0; --k) {
-        if (lane == k && rok) v = v / dr[k];
+        if (lane == k && rok) v = v * dinv;
         const T xk = readlane_t(v, k);
         if (lane < k) v = v - dr[k] * xk;
       }
