@@ -121,12 +121,19 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, const T* __restrict__ A
     for (int64_t d = done; d < done + nready && d < lastd; ++d) {
       const int64_t blk = LOWER ? d : (nblk - 1 - d);
       const int64_t c0 = blk * TB;
-      // this wave's 16 columns of the 64x64 tile
-#pragma unroll 4
+      // this wave's 16 columns of the 64x64 tile.  Every load is issued
+      // before the first use, so a finished block costs one memory round
+      // trip: with four loads in flight at a time the catch-up on each new
+      // block took longer than a chain step and set the solve's pace.
+      T av[16], xw[16];
+#pragma unroll
       for (int cc = 0; cc < 16; ++cc) {
         const int64_t c = c0 + wave * 16 + cc;
-        if (c < n && rok) acc = acc - A[row + c * lda] * ld_coh(&x[c]);
+        av[cc] = (c < n && rok) ? A[row + c * lda] : T(0);
+        xw[cc] = (c < n) ? ld_coh(&x[c]) : T(0);
       }
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc) acc = acc - av[cc] * xw[cc];
     }
     done += nready;
     __syncthreads();
