@@ -8,6 +8,9 @@
 //   diagonal block inside one wavefront (lane i holds row i of the block in
 //   registers; x_k is read with readlane), and publishes its x with
 //   device-coherent stores before raising its flag.  The matrix is read once.
+// * k_trsv128: the same chain over 128-row blocks (eight wavefronts, two
+//   64-row diagonal solves with the off-diagonal 64x64 update between them),
+//   used from kTrsvWideMinN rows on: half as many handoffs between workgroups.
 // * k_gemv_part / k_gemv_fin: r = b - A x in FP64, two passes over column
 //   chunks, deterministic (no floating-point atomics).
 // * norms, dot products, axpy and format conversions for the refinement.
@@ -16,7 +19,9 @@
 namespace lupp {
 namespace {
 
-constexpr int TB = 64;  // rows per triangular-solve block
+constexpr int TB = 64;                // rows per triangular-solve block
+constexpr int TB2 = 128;              // rows per block of the wide variant
+constexpr int64_t kTrsvWideMinN = 8192;  // the wide variant from this order on
 
 __device__ __forceinline__ double readlane_t(double v, int k) {
   const uint64_t u = (uint64_t)__double_as_longlong(v);
@@ -173,6 +178,172 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, const T* __restrict__ A
         if (lane < k) v = v - dr[k] * xk;
       }
     }
+    if (rok) st_coh(&x[row], v);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    if (lane == 0) __hip_atomic_store(&flags[b], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// x := inverse of one 64x64 diagonal block (unit lower, or upper with its
+// diagonal) times v; lane i holds row i; sd is the block, column-major in LDS
+template <typename T, bool LOWER>
+__device__ __forceinline__ T solve64(T v, const T* __restrict__ sd, int lane, bool rok) {
+  T dr[64];
+#pragma unroll
+  for (int c = 0; c < 64; ++c) dr[c] = sd[c * 64 + lane];
+  if (LOWER) {
+#pragma unroll
+    for (int k = 0; k < 64; ++k) {
+      const T xk = readlane_t(v, k);
+      if (lane > k) v = v - dr[k] * xk;
+    }
+  } else {
+    const T dinv = T(1) / sd[lane * 64 + lane];
+#pragma unroll
+    for (int k = 63; k >= 0; --k) {
+      if (lane == k && rok) v = v * dinv;
+      const T xk = readlane_t(v, k);
+      if (lane < k) v = v - dr[k] * xk;
+    }
+  }
+  return v;
+}
+
+// 128-row blocks: wavefront w covers rows 64*(w/4) .. +63 of the block and
+// columns 32*(w%4) .. +31 of each finished block.  The half solved first
+// (the top one for L, the bottom one for U) is solved by its first wavefront;
+// the other half's wavefronts subtract its contribution through the
+// off-diagonal 64x64 tile (in registers since the start), and that half's
+// first wavefront solves it and raises the block's flag.
+template <typename T, bool LOWER>
+__global__ __launch_bounds__(512) void k_trsv128(int64_t n, const T* __restrict__ A, int64_t lda, T* __restrict__ x,
+                                                 uint32_t* __restrict__ flags, uint64_t* __restrict__ ticket,
+                                                 uint64_t tbase, uint32_t epoch, int32_t* __restrict__ err) {
+  __shared__ T s_part[8][64];
+  __shared__ T s_diag[2][64 * 64];
+  __shared__ T s_x[64];
+  __shared__ int64_t s_blk;
+  __shared__ int s_ready;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rh = wave >> 2, cw = wave & 3;
+  const int fh = LOWER ? 0 : 1, sh = 1 - fh;
+  const int64_t nblk = (n + TB2 - 1) / TB2;
+  if (tid == 0) s_blk = (int64_t)(atomicAdd((unsigned long long*)ticket, 1ull) - tbase);
+  __syncthreads();
+  const int64_t q = s_blk;
+  if (q < 0 || q >= nblk) {  // ticket bookkeeping out of step: report, touch nothing
+    if (tid == 0) *err = 2;
+    return;
+  }
+  const int64_t b = LOWER ? q : (nblk - 1 - q);
+  const int64_t r0 = b * TB2;
+  const int64_t row = r0 + rh * 64 + lane;
+  const bool rok = row < n;
+  T acc = T(0);
+  const int64_t ndep = LOWER ? b : (nblk - 1 - b);
+  // both diagonal blocks staged in LDS before the waits, column-major
+  for (int e = tid; e < 2 * 64 * 64; e += 512) {
+    const int h = e >> 12, c = (e >> 6) & 63, rr = e & 63;
+    const int64_t gr = r0 + h * 64 + rr, gc = r0 + h * 64 + c;
+    s_diag[h][c * 64 + rr] = (gr < n && gc < n) ? A[gr + gc * lda] : T(0);
+  }
+  T ofd[16];  // off-diagonal tile: second half's rows, first half's columns
+  {
+    const int64_t c0 = r0 + fh * 64 + cw * 16;
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) {
+      const int64_t c = c0 + cc;
+      ofd[cc] = (rh == sh && c < n && rok) ? A[row + c * lda] : T(0);
+    }
+  }
+  T apf[32];  // adjacent finished block, loaded before its flag
+  const int64_t lastd = ndep - 1;
+  if (ndep > 0) {
+    const int64_t c0 = (LOWER ? lastd : (nblk - 1 - lastd)) * TB2 + cw * 32;
+#pragma unroll
+    for (int cc = 0; cc < 32; ++cc) {
+      const int64_t c = c0 + cc;
+      apf[cc] = (c < n && rok) ? A[row + c * lda] : T(0);
+    }
+  }
+  int64_t done = 0;
+  long spins = 0;
+  while (done < ndep) {
+    if (wave == 0) {
+      const int64_t d0 = done + lane;
+      const int64_t blk = LOWER ? d0 : (nblk - 1 - d0);
+      bool ok = true;
+      if (d0 < ndep) ok = __hip_atomic_load(&flags[blk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+      const unsigned long long notready = __ballot(!ok);
+      const int nready = notready ? (__ffsll((long long)notready) - 1) : 64;
+      if (lane == 0) s_ready = nready;
+    }
+    __syncthreads();
+    int nready = s_ready;
+    if (nready == 0) {
+      if (++spins > (1L << 22)) {
+        if (tid == 0) *err = 1;
+        nready = (int)(ndep - done);  // give up waiting (results invalid, flagged)
+      } else {
+        __syncthreads();
+        continue;
+      }
+    }
+    for (int64_t d = done; d < done + nready && d < lastd; ++d) {
+      const int64_t blk = LOWER ? d : (nblk - 1 - d);
+      const int64_t c0 = blk * TB2 + cw * 32;
+      // two rounds of 16 columns, all loads of a round in flight together
+#pragma unroll 1
+      for (int hh = 0; hh < 32; hh += 16) {
+        T av[16], xw[16];
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) {
+          const int64_t c = c0 + hh + cc;
+          av[cc] = (c < n && rok) ? A[row + c * lda] : T(0);
+          xw[cc] = (c < n) ? ld_coh(&x[c]) : T(0);
+        }
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) acc = acc - av[cc] * xw[cc];
+      }
+    }
+    done += nready;
+    __syncthreads();
+  }
+  if (ndep > 0) {
+    const int64_t c0 = (LOWER ? lastd : (nblk - 1 - lastd)) * TB2 + cw * 32;
+    T xv[32];
+#pragma unroll
+    for (int cc = 0; cc < 32; ++cc) xv[cc] = (c0 + cc < n) ? ld_coh(&x[c0 + cc]) : T(0);
+#pragma unroll
+    for (int cc = 0; cc < 32; ++cc) acc = acc - apf[cc] * xv[cc];
+  }
+  s_part[wave][lane] = acc;
+  __syncthreads();
+  if (wave == fh * 4) {
+    T v = rok ? x[row] : T(0);
+    v = v + s_part[fh * 4 + 0][lane] + s_part[fh * 4 + 1][lane] + s_part[fh * 4 + 2][lane] + s_part[fh * 4 + 3][lane];
+    v = solve64<T, LOWER>(v, s_diag[fh], lane, rok);
+    s_x[lane] = v;
+    if (rok) st_coh(&x[row], v);
+    // stores complete before the barrier, so before the flag raised after it
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  }
+  __syncthreads();
+  if (rh == sh) {
+    T t = acc;
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) t = t - ofd[cc] * s_x[cw * 16 + cc];
+    s_part[wave][lane] = t;
+  }
+  __syncthreads();
+  if (wave == sh * 4) {
+    T v = rok ? x[row] : T(0);
+    v = v + s_part[sh * 4 + 0][lane] + s_part[sh * 4 + 1][lane] + s_part[sh * 4 + 2][lane] + s_part[sh * 4 + 3][lane];
+    v = solve64<T, LOWER>(v, s_diag[sh], lane, rok);
     if (rok) st_coh(&x[row], v);
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_s_waitcnt(0);
@@ -370,6 +541,17 @@ hipError_t trsv_wave(hipStream_t s, bool lower, int64_t n, const T* A, int64_t l
   if (st->epoch > 0xF0000000u) return hipErrorInvalidValue;  // caller resets
   st->epoch += 1;
   const uint64_t tbase = st->tickets;
+  if (n >= kTrsvWideMinN) {
+    const int64_t nblk2 = (n + TB2 - 1) / TB2;
+    st->tickets += (uint64_t)nblk2;
+    if (lower)
+      hipLaunchKernelGGL((k_trsv128<T, true>), dim3((unsigned)nblk2), dim3(512), 0, s, n, A, lda, x, st->flags,
+                         st->ticket, tbase, st->epoch, st->err);
+    else
+      hipLaunchKernelGGL((k_trsv128<T, false>), dim3((unsigned)nblk2), dim3(512), 0, s, n, A, lda, x, st->flags,
+                         st->ticket, tbase, st->epoch, st->err);
+    return hipGetLastError();
+  }
   st->tickets += (uint64_t)nblk;
   if (lower)
     hipLaunchKernelGGL((k_trsv<T, true>), dim3((unsigned)nblk), dim3(256), 0, s, n, A, lda, x, st->flags, st->ticket,

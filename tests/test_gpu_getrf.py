@@ -190,6 +190,28 @@ def test_getrs_multi_rhs(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_getrs_wide_blocks_ragged(dtype):
+    """From order 8192 on the triangular solves use 128-row blocks: a ragged
+    order (a partial last block, 77 rows past a 64-row boundary) above that
+    threshold, solved to the backward-error bound."""
+    n = 8192 + 77
+    announce("getrs n=%d %s (128-row solve blocks)" % (n, dtype))
+    npdt = np.float64 if dtype == "f64" else np.float32
+    A = synth.uniform(6, 0, n, n).astype(npdt)
+    b = synth.uniform(6, 1, n, 1).astype(npdt)
+    dA = to_dev(A)
+    ipiv, info = lupp.getrf(dA)
+    assert info == 0
+    db = to_dev(b)
+    lupp.getrs(dA, ipiv, db)
+    torch.cuda.synchronize()
+    x = to_host(db)[:, 0].astype(np.float64)
+    u = checks.U64 if dtype == "f64" else checks.U32
+    assert np.all(np.isfinite(x))
+    assert checks.backward_error(A.astype(np.float64), x, b[:, 0].astype(np.float64)) <= 8 * n * u
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("n", [1000, 3000])
 def test_nonfinite_inputs_complete(n, dtype):
     """NaN and +-Inf entries are outside the contract (results unspecified),
