@@ -169,7 +169,7 @@ struct TrsvState {
   uint32_t* flags;     // device, max_blocks entries
   uint64_t* ticket;    // device counter, only ever incremented
   int32_t* err;        // device, set when a bounded wait expires
-  int64_t max_blocks;  // capacity of flags (rows / 64)
+  int64_t max_blocks;  // capacity of flags: ceil(rows / 64) (128-row blocks use half)
   uint32_t epoch;      // host copy of the last epoch used
   uint64_t tickets;    // host copy of the tickets handed out so far
 };
