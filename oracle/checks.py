@@ -15,6 +15,11 @@ Definitions (FP64 unless stated):
   step whose pivot column is not separated (gap < tau).
 * ``closed_form_ipiv``: pivots of A = Pi * D when D's pivot order is the
   identity (column dominance), from the row placement alone.
+
+Pins (tests/test_oracle_pins.py): both measures are checked against values
+worked by hand on small cases chosen so that another norm, another dimension
+factor or another eps gives a different number, and against planted errors in
+factors and solutions that they must reject.
 """
 from __future__ import annotations
 

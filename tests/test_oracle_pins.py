@@ -433,3 +433,182 @@ def test_synth_fast_generator_matches_numpy_philox():
         a = synth.uniform(123, 9, m, n, lo, hi)
         b = synth.uniform_numpy(123, 9, m, n, lo, hi)
         assert a.flags["F_CONTIGUOUS"] and np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------- acceptance measures
+# The two numbers every parity test checks against its bound are pinned here by
+# hand-worked values.  Each case is built so that the plausible slips give a
+# different number: the infinity norm in place of the 1-norm, n^2 or min(m,n) in
+# place of max(m,n), eps = 1 or DBL_EPSILON in place of the unit roundoff, an
+# unpermuted A, or the 1-norm of r, x or b in the backward error.
+
+def test_scaled_residual_hand_worked():
+    # A is upper triangular: P = I, L = I, U = A.  ||A||_1 = 2 (column sums
+    # 1, 2, 2), ||A||_inf = 3.  Planting delta at L(1,0) adds delta * U(0,:) =
+    # delta * (1, 1, 1) to row 1 of L*U (exact in binary64 for delta = 30u), so
+    # ||PA - LU||_1 = delta and ||PA - LU||_inf = 3 delta.
+    u = checks.U64
+    A = np.array([[1.0, 1, 1], [0, 1, 0], [0, 0, 1]], order="F")
+    LU = A.copy(order="F")
+    delta = 30 * u
+    LU[1, 0] = delta
+    ipiv = np.array([1, 2, 3], dtype=np.int32)
+    # delta / (max(m,n) * u * ||A||_1) = 30u / (3 * u * 2) = 5 exactly
+    assert checks.scaled_residual(A, LU, ipiv) == 5.0
+    # the same planted error measured against FP32's unit roundoff
+    assert checks.scaled_residual(A, LU, ipiv, checks.U32) == 30 * u / (3 * checks.U32 * 2)
+    # an exact factorization scores 0
+    assert checks.scaled_residual(A, A, ipiv) == 0.0
+
+
+def test_scaled_residual_uses_max_dimension_and_permutation():
+    # 4 x 2, A = P^T * [I; 0] with rows swapped: ipiv (2, 2) swaps rows 0 and 1.
+    u = checks.U64
+    A = np.array([[0.0, 1], [1, 0], [0, 0], [0, 0]], order="F")
+    LU = np.array([[1.0, 0], [0, 1], [0, 0], [0, 0]], order="F")
+    ipiv = np.array([2, 2], dtype=np.int32)
+    assert checks.scaled_residual(A, LU, ipiv) == 0.0
+    # the unpermuted comparison would see ||A - LU||_1 = 2
+    assert checks.scaled_residual(A, LU, np.array([1, 2], dtype=np.int32)) == 2.0 / (4 * u * 1.0)
+    # planted error 8u at L(3,1): ||R||_1 = 8u, max(m,n) = 4, ||A||_1 = 1 -> 2
+    LU[3, 1] = 8 * u
+    assert checks.scaled_residual(A, LU, ipiv) == 2.0
+
+
+def test_scaled_residual_rejects_perturbed_factors():
+    o = _oracle()
+    A = synth.uniform(77, 5, 60, 60)
+    LU, ipiv, info = o.getrf(A)
+    assert checks.scaled_residual(A, LU, ipiv) < 10
+    bad = LU.copy(order="F")
+    bad[40, 7] += 1e-9  # one wrong multiplier
+    assert checks.scaled_residual(A, bad, ipiv) > 1e3
+    bad = LU.copy(order="F")
+    bad[7, 40] *= 1 + 1e-10  # one wrong U entry
+    assert checks.scaled_residual(A, bad, ipiv) > 10
+    wrong = ipiv.copy()
+    wrong[3], wrong[4] = wrong[4], wrong[3]
+    if not np.array_equal(wrong, ipiv):
+        assert checks.scaled_residual(A, LU, wrong) > 1e3
+
+
+def test_backward_error_hand_worked():
+    # A = [[1, 2], [1, 0]]: ||A||_inf = 3 (row sums 3, 1), ||A||_1 = 2.
+    # x = (1, -2): A x = (-3, 1).  b = (-2.5, 2): r = b - A x = (0.5, 1),
+    # ||r||_inf = 1, ||x||_inf = 2, ||b||_inf = 2.5.
+    # eta = 1 / (3 * 2 + 2.5) = 2/17 (any other norm gives another value).
+    A = np.array([[1.0, 2], [1, 0]], order="F")
+    x = np.array([1.0, -2])
+    b = np.array([-2.5, 2.0])
+    assert checks.backward_error(A, x, b) == 1.0 / 8.5
+    # the exact solution has eta = 0
+    xs = np.linalg.solve(A, b)
+    assert checks.backward_error(A, xs, b) <= 2 * checks.U64
+    # zero data: defined as 0
+    assert checks.backward_error(np.zeros((2, 2)), np.zeros(2), np.zeros(2)) == 0.0
+
+
+def test_backward_error_rejects_perturbed_solution():
+    o = _oracle()
+    n = 80
+    A = synth.uniform(78, 0, n, n)
+    b = synth.uniform(78, 1, n, 1)[:, 0]
+    LU, ipiv, _ = o.getrf(A)
+    x, st = o.getrs(LU, ipiv, b)
+    assert checks.backward_error(A, x, b) <= 8 * n * checks.U64
+    y = x.copy()
+    y[17] += 1e-8 * np.abs(x).max()
+    assert checks.backward_error(A, y, b) > 1e3 * n * checks.U64
+
+
+def test_gap_hand_worked():
+    """gap_k on the worked 4 x 4 example: column maxima 4 vs 4 (tie), then
+    4 vs 1, then 11/4 vs 5/4, then a single row."""
+    A = np.array([[1.0, 2, 0, 1], [4, 4, 2, 0], [2, 1, 3, 1], [-4, 0, 1, 2]], order="F")
+    _, _, _, gap = _oracle().getrf(A, with_gap=True)
+    assert gap[0] == 0.0
+    assert gap[1] == 0.75
+    assert gap[2] == (2.75 - 1.25) / 2.75
+    assert gap[3] == 1.0
+    assert checks.separated_prefix(gap, 1e-9) == 0
+    assert checks.separated_prefix(np.array([0.5, 0.2, 1e-12, 1.0]), 1e-9) == 2
+
+
+# ---------------------------------------------------------------- FP32 solve and batched driver
+def _dyadic_system(seed, n, dtype):
+    """A = Pi^T L U with exactly factorable dyadic factors and an integer x:
+    b = A x, every partial sum of the solve is a multiple of 1/4 bounded by
+    a few hundred, so a correct solve returns x exactly in binary32."""
+    A, L, U, perm = synth.exact_lu_product(seed, 31, n)
+    x = synth.stream(seed, 32).integers(-3, 4, size=n).astype(np.float64)
+    b = A @ x
+    return A.astype(dtype), b.astype(dtype), x
+
+
+@pytest.mark.parametrize("n", [1, 5, 16, 40])
+def test_sgetrs_exact_dyadic(n):
+    o = _oracle()
+    A, b, x = _dyadic_system(900 + n, n, np.float32)
+    LU, ipiv, info = o.getrf(A)
+    assert info == 0 and LU.dtype == np.float32
+    xs, st = o.getrs(LU, ipiv, b)
+    assert st == 0 and xs.dtype == np.float32
+    assert np.array_equal(xs.astype(np.float64), x)
+    # two right-hand sides at once, the second the negated first
+    X, st = o.getrs(LU, ipiv, np.stack([b, -b], axis=1))
+    assert st == 0 and np.array_equal(X[:, 0].astype(np.float64), x) and np.array_equal(X[:, 1].astype(np.float64), -x)
+
+
+def test_sgetrs_refuses_singular_and_bounds_error():
+    o = _oracle()
+    A = synth.uniform(5, 1, 7, 7).astype(np.float32)
+    A[:, 4] = 0
+    LU, ipiv, info = o.getrf(A)
+    _, st = o.getrs(LU, ipiv, np.ones(7, dtype=np.float32))
+    assert info == 5 and st == 5
+    n = 120
+    A = synth.uniform(6, 1, n, n).astype(np.float32)
+    b = synth.uniform(6, 2, n, 1)[:, 0].astype(np.float32)
+    LU, ipiv, _ = o.getrf(A)
+    x, _ = o.getrs(LU, ipiv, b)
+    assert checks.backward_error(A, x, b) <= 8 * n * checks.U32
+
+
+def test_batched_oracle_exact_dyadic_systems():
+    """Every system of a packed batch of exactly factorable systems comes back
+    with its exact pivots, factors and solution, in both precisions."""
+    o = _oracle()
+    sizes = np.array([1, 3, 8, 17, 2, 33], dtype=np.int32)
+    for dtype in (np.float64, np.float32):
+        blocks, rhs, sols, facs = [], [], [], []
+        for i, n in enumerate(sizes):
+            A, L, U, perm = synth.exact_lu_product(500 + i, 31, int(n))
+            x = synth.stream(500 + i, 32).integers(-3, 4, size=int(n)).astype(np.float64)
+            blocks.append(A.ravel(order="F"))
+            rhs.append(A @ x)
+            sols.append(x)
+            facs.append((L, U, checks.closed_form_ipiv(perm)))
+        a_off = np.concatenate([[0], np.cumsum(sizes.astype(np.int64) ** 2)[:-1]])
+        b_off = np.concatenate([[0], np.cumsum(sizes.astype(np.int64))[:-1]])
+        Ap = np.concatenate(blocks).astype(dtype)
+        Bp = np.concatenate(rhs).astype(dtype)
+        LU, ipiv, p_off, X, info = o.gesv_batched(sizes, Ap, a_off, Bp, b_off, nthreads=3)
+        assert np.all(info == 0) and LU.dtype == dtype and X.dtype == dtype
+        for i, n in enumerate(sizes):
+            n = int(n)
+            L, U, ip = facs[i]
+            Ls, Us = checks.unpack(LU[a_off[i]:a_off[i] + n * n].reshape(n, n, order="F"))
+            assert np.array_equal(ipiv[p_off[i]:p_off[i] + n], ip)
+            assert np.array_equal(Ls, L) and np.array_equal(Us, U)
+            assert np.array_equal(X[b_off[i]:b_off[i] + n].astype(np.float64), sols[i])
+
+
+def test_batched_oracle_zero_pivot_leaves_rhs():
+    o = _oracle()
+    sizes = np.array([4, 5], dtype=np.int32)
+    A, aoff, B, boff = synth.batch_uniform(8, sizes)
+    A[aoff[1] + 2 * 5:aoff[1] + 3 * 5] = 0.0  # column 2 of system 1 is zero
+    LU, ipiv, poff, X, info = o.gesv_batched(sizes, A, aoff, B, boff, nthreads=2)
+    assert info[0] == 0 and info[1] == 3
+    assert np.array_equal(X[boff[1]:boff[1] + 5], B[boff[1]:boff[1] + 5])
+    assert checks.backward_error(A[:16].reshape(4, 4, order="F"), X[:4], B[:4]) <= 32 * checks.U64
