@@ -14,17 +14,30 @@ The JSON line carries:
   roofline    the trailing-update GEMM (128x128-tile kernel): its algorithmic
               flops 2*M*N*K summed over its launches in the timed steps,
               divided by the summed launch durations from HIP events recorded
-              on the library's stream, against MI355X's FP64 MFMA peak
-  cpu_baseline  the CPU oracle (unblocked FP64 LUPP, all host cores) on a
-              bounded sample: its first S elimination steps on the same matrix
-  check       info, pivot-closed-form and residual checks of the last step
-  mixed       the mixed-precision solve at the same n (lupp_dgesv_mixed): FP32
-              factorization with BF16 / FP16 / FP8 trailing updates, then FP64
-              classical or GMRES refinement to backward error <= 1e-14, on the
-              diagonally dominant matrix of the same draw (entries halved to
-              U(-0.5,0.5), then a_ii := sum_j |a_ij|) and b iid U(-1,1); its
-              effective rate is 2/3 n^3 over the wall time of factorization
-              plus refinement
+              on the library's stream, against MI355X's FP64 MFMA peak; traffic
+              from the committed counter summary (labelled with its n)
+  cpu_baseline  the CPU oracle (unblocked FP64 LUPP) on the host cores: n = 512
+              (median of 3) and n = 4096, each with 1 thread and with all cores,
+              the input copy outside the timer; value = all cores at n = 4096.
+              The same leg solves the kappa systems of the kappa leg (n = 4096)
+              with the oracle: their FP64 reference solutions
+  check       info and a random-probe residual of the last step, and the
+              closed-form pivots of A = Pi*D (D column diagonally dominant) at
+              the same n, compared bit for bit
+  c2          FP64 and FP32 factorizations at n = 4096, 8192, 16384 (and FP32 at
+              32768): median of 3, TFLOP/s against the FP64 / FP32 peaks, probe
+              residual, Pi*D closed-form pivots at every n
+  mixed       the mixed-precision solve (lupp_dgesv_mixed) at n = 32768 and
+              16384: FP32 factorization with BF16 / FP16 / FP8 trailing
+              updates, then FP64 classical or GMRES refinement to backward
+              error <= 1e-14, on the diagonally dominant matrix (U(-0.5,0.5),
+              then a_ii := sum_j |a_ij|), b iid U(-1,1); effective rate 2/3 n^3
+              over the wall time; forward errors against the GPU FP64 solve and
+              (second, untimed call with b = A x_true) against x_true
+  kappa       n = 4096, A = U diag(sigma) V^T with geometric sigma from 1 to
+              1/kappa, kappa in {1e2, 1e4, 1e6}, b = A x_true: iterations, eta and
+              forward errors (vs the CPU oracle's FP64 solve, the GPU FP64 solve
+              and x_true) per (precision, kappa, refinement)
   batched     20000 independent systems, n_i iid uniform on [8, 128], A_i and
               b_i iid U(-1,1), packed column-major (lupp_xgesv_batched: LU with
               partial pivoting and solve): factorizations per second from the
@@ -34,7 +47,8 @@ The JSON line carries:
               written, pivots written, sizes and offsets read)
   large       n = 65536 (diagonally dominant recipe drawn on the device): plain FP64
               factorization + solve against the FP8-update GMRES-IR solve (wall
-              times, effective TFLOP/s, backward errors)
+              times, effective TFLOP/s, backward errors, forward error against
+              the FP64 solve, a long-double host check of 64 sampled rows)
 """
 from __future__ import annotations
 
@@ -85,35 +99,184 @@ def probe_residual(torch, A0, LU, ipiv, nprobe=8, seed=5):
     return r / (n * 2.0 ** -53 * na * nx)
 
 
-def cpu_baseline(A_host, budget_s=15.0):
-    """Oracle (unblocked, threaded over trailing columns) on the first S steps
-    of the same factorization; rate in TFLOP/s of the steps done."""
+def closed_form_ipiv(perm) -> np.ndarray:
+    """Pivots of A = Pi*D with D's pivot order the identity: row perm[d] of A
+    holds row d of D; partial pivoting picks D's row k at step k, wherever the
+    earlier interchanges have moved it."""
+    perm = np.asarray(perm)
+    m = len(perm)
+    where = np.array(perm, copy=True)      # current row of D-row d
+    content = np.empty(m, dtype=np.int64)  # D-row at current row r
+    content[perm] = np.arange(m)
+    ipiv = np.empty(m, dtype=np.int32)
+    for k in range(m):
+        r = int(where[k])
+        ipiv[k] = r + 1
+        if r != k:
+            dk = int(content[k])
+            content[k], content[r] = k, dk
+            where[k], where[dk] = k, r
+    return ipiv
+
+
+def host_backward_error(A, x, b) -> float:
+    r = b - A @ x
+    den = np.abs(A).sum(axis=1).max() * np.abs(x).max() + np.abs(b).max()
+    return float(np.abs(r).max() / den) if den > 0 else 0.0
+
+
+def rel_err(x, ref) -> float:
+    """||x - ref||_inf / ||ref||_inf (device or host vectors)."""
+    d = (x - ref).abs().max() if hasattr(x, "abs") else np.abs(x - ref).max()
+    r = ref.abs().max() if hasattr(ref, "abs") else np.abs(ref).max()
+    return float(d / r)
+
+
+def pi_d_matrix(torch, n, seed, tdt):
+    """A = Pi*D on the device, D strictly column diagonally dominant by an
+    absolute margin of 1 (off-diagonal iid U(-1,1) from torch's seeded
+    generator, d_jj = 1 + sum_{i != j} |d_ij|), row i of D placed at row perm[i]
+    of A.  Returns (A column-major, perm)."""
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    D = torch.empty((n, n), dtype=tdt, device="cuda").t()
+    D.uniform_(-1.0, 1.0, generator=g)
+    D.diagonal().zero_()
+    colsum = D.abs().sum(dim=0, dtype=torch.float64)
+    D.diagonal().copy_((1.0 + colsum).to(tdt))
+    del colsum
+    perm = torch.randperm(n, generator=torch.Generator().manual_seed(seed + 1))
+    A = torch.empty_like(D.t()).t()
+    A[perm.cuda()] = D
+    del D
+    return A, perm.numpy()
+
+
+def factor_dev(lupp, h, A, tdt):
+    import torch
+    n = A.shape[1]
+    ipiv = torch.empty(max(1, min(A.shape)), dtype=torch.int32, device="cuda")
+    info = torch.empty(1, dtype=torch.int32, device="cuda")
+    (lupp.lupp_dgetrf if tdt == torch.float64 else lupp.lupp_sgetrf)(A, ipiv, info, handle=h)
+    return ipiv[:min(A.shape[0], n)], info
+
+
+def pid_pivot_check(torch, lupp, n, seed, tdt):
+    """Closed-form pivots of a Pi*D factorization, bit for bit."""
+    A, perm = pi_d_matrix(torch, n, seed, tdt)
+    h = lupp.Handle()
+    ipiv, info = factor_dev(lupp, h, A, tdt)
+    h.sync()
+    got = ipiv.cpu().numpy()
+    want = closed_form_ipiv(perm)
+    bad = np.nonzero(got != want)[0]
+    h.close()
+    del A
+    torch.cuda.empty_cache()
+    return {"n": n, "pivots_equal_closed_form": bool(len(bad) == 0), "mismatches": int(len(bad)),
+            "first_mismatch": int(bad[0]) if len(bad) else -1, "info": int(info.item())}
+
+
+def c2_leg(torch, lupp, seed, sizes=(4096, 8192, 16384), extra_f32=(32768,), reps=3):
+    """Plain blocked LUPP FP64 and FP32 over a range of n (A iid U(-1,1) drawn
+    on the device with torch's seeded generator): median of reps timed calls
+    after one warmup (the input restored outside the timed interval, HIP events
+    around the factorization on the handle's stream)."""
+    out = []
+    for dname, tdt, peak in (("f64", torch.float64, FP64_PEAK_TFLOPS), ("f32", torch.float32, FP32_PEAK_TFLOPS)):
+        ns = list(sizes) + (list(extra_f32) if dname == "f32" else [])
+        for n in ns:
+            g = torch.Generator(device="cuda").manual_seed(seed + n)
+            A0 = torch.empty((n, n), dtype=tdt, device="cuda").t()
+            A0.uniform_(-1.0, 1.0, generator=g)
+            A = torch.empty_like(A0.t()).t()
+            h = lupp.Handle()
+            times = []
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            for r in range(reps + 1):
+                A.copy_(A0)
+                torch.cuda.synchronize()
+                e0.record()
+                ipiv, info = factor_dev(lupp, h, A, tdt)
+                e1.record()
+                h.sync()
+                torch.cuda.synchronize()
+                if r > 0:
+                    times.append(e0.elapsed_time(e1))
+            ms = float(np.median(times))
+            flops = 2.0 / 3.0 * float(n) ** 3
+            tf = flops / (ms * 1e-3) / 1e12
+            u = 2.0 ** -53 if dname == "f64" else 2.0 ** -24
+            res = probe_residual(torch, A0.double(), A.double(), ipiv) * (2.0 ** -53 / u)
+            h.close()
+            del A, A0
+            torch.cuda.empty_cache()
+            pid = pid_pivot_check(torch, lupp, n, seed + 7 * n, tdt)
+            rec = {"dtype": dname, "n": n, "ms": round(ms, 3), "tflops": round(tf, 3), "peak": peak,
+                   "frac": round(tf / peak, 4), "info": int(info.item()), "probe_scaled_residual": res,
+                   "pi_d": pid}
+            log("c2: %s" % rec)
+            out.append(rec)
+    return {"workload": "plain blocked LUPP, A iid U(-1,1) (device-drawn, seed + n), 1 warmup + median of %d" % reps,
+            "runs": out}
+
+
+def cpu_baseline(seed, kappa_systems=None):
+    """The oracle (unblocked right-looking FP64 LUPP) on the host cores: n = 512
+    (median of 3) and n = 4096 (one run), each with 1 thread and with all the
+    cores of the affinity mask; the input copy is made before the timer.  Then
+    the FP64 reference solutions of the kappa systems (all cores)."""
     import oracle
-    n = A_host.shape[0]
-    cores = oracle.host_cores()
-    # one step to size the sample (oracle.getrf factors a private copy)
-    t = time.perf_counter()
-    oracle.getrf(A_host, ksteps=1, nthreads=cores)
-    t1 = time.perf_counter() - t
-    steps = int(max(2, min(512, budget_s / max(t1, 1e-3))))
-    t = time.perf_counter()
-    oracle.getrf(A_host, ksteps=steps, nthreads=cores)
-    dt = time.perf_counter() - t
-    flops = sum(2.0 * (n - k - 1) ** 2 + (n - k - 1) for k in range(steps))
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
-            "sample": "first %d elimination steps of the same n=%d FP64 factorization (%.1f s, %.3g flop)"
-            % (steps, n, dt, flops)}
-
-
-def mixed_leg(torch, lupp, A0, n, seed, fp64_ms, runs):
-    """Mixed-precision solves on the diagonally dominant matrix built in place
-    from A0 (A0 is overwritten)."""
     import synth
-    A0.mul_(0.5)  # U(-1,1) -> U(-0.5,0.5), exact
-    d = A0.abs().sum(dim=1)
-    A0.diagonal().copy_(d)
-    del d
-    b = torch.from_numpy(synth.uniform(seed, 1, n, 1)).cuda()  # (n, 1), column-major
+    cores = oracle.host_cores()
+    runs = []
+    for n, reps in ((512, 3), (4096, 1)):
+        A = synth.uniform(seed, 0, n, n)
+        for th in (1, cores):
+            ts = []
+            for _ in range(reps):
+                W = np.array(A, order="F", copy=True)
+                t = time.perf_counter()
+                oracle.getrf(W, nthreads=th, overwrite=True)
+                ts.append(time.perf_counter() - t)
+            dt = float(np.median(ts))
+            runs.append({"n": n, "threads": th, "seconds": round(dt, 4),
+                         "tflops": 2.0 / 3.0 * n ** 3 / dt / 1e12})
+            log("cpu oracle n=%d threads=%d: %.3f s" % (n, th, dt))
+    refs = {}
+    for key, (A, b) in (kappa_systems or {}).items():
+        W = np.array(A, order="F", copy=True)
+        t = time.perf_counter()
+        LU, ipiv, info = oracle.getrf(W, nthreads=cores, overwrite=True)
+        x, st = oracle.getrs(LU, ipiv, b)
+        refs[key] = x
+        log("cpu oracle reference solve %s: %.2f s" % (key, time.perf_counter() - t))
+    best = [r for r in runs if r["n"] == 4096 and r["threads"] == cores][0]
+    return {"value": best["tflops"], "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": "whole FP64 factorization at n=4096 (A iid U(-1,1), seed %d), all %d cores; also n=512 "
+                      "(median of 3) and 1 thread, in runs" % (seed, cores),
+            "runs": runs}, refs
+
+
+def fp64_solve(torch, lupp, A0, B):
+    """GPU FP64 LUPP + solve of A0 X = B (A0 not modified)."""
+    A = torch.empty_like(A0.t()).t()
+    A.copy_(A0)
+    X = torch.empty_like(B.t()).t()
+    X.copy_(B)
+    h = lupp.Handle()
+    ipiv, info = factor_dev(lupp, h, A, torch.float64)
+    lupp.lupp_dgetrs(A, ipiv, X, handle=h)
+    h.sync()
+    h.close()
+    del A
+    return X
+
+
+def mixed_runs(torch, lupp, A0, b, runs, fp64_ms=None, x_fp64=None, x_true=None, x_ref=None, b_true=None):
+    """Timed mixed solves of A0 x = b (one right-hand side each); forward
+    errors against the references given.  b_true = A0 x_true (an untimed
+    second call per run) when b itself is not A0 x_true."""
+    n = A0.shape[0]
     X = torch.empty((1, n), dtype=torch.float64, device="cuda").t()
     h = lupp.Handle()
     flops = 2.0 / 3.0 * float(n) ** 3
@@ -129,15 +292,112 @@ def mixed_leg(torch, lupp, A0, n, seed, fp64_ms, runs):
         r = {"factor_prec": prec, "solver": solver, "status": rep["status_name"], "iters": rep["iters"],
              "inner_iters": rep["inner_iters"], "backward_error": rep["backward_error"],
              "factor_ms": round(rep["factor_ms"], 2), "refine_ms": round(rep["refine_ms"], 2),
-             "wall_ms": round(ms, 2), "effective_tflops": round(flops / (ms * 1e-3) / 1e12, 3),
-             "speedup_vs_fp64_factor": round(fp64_ms / ms, 3)}
-        log("mixed: %s" % r)
+             "wall_ms": round(ms, 2), "effective_tflops": round(flops / (ms * 1e-3) / 1e12, 3)}
+        if fp64_ms:
+            r["speedup_vs_fp64_factor"] = round(fp64_ms / ms, 3)
+        if x_fp64 is not None:
+            r["forward_error_vs_gpu_fp64"] = rel_err(X[:, 0], x_fp64)
+        if x_ref is not None:
+            r["forward_error_vs_cpu_oracle"] = rel_err(X[:, 0].cpu().numpy(), x_ref)
+        if x_true is not None:
+            if b_true is None:
+                r["forward_error_vs_x_true"] = rel_err(X[:, 0], x_true)
+            else:
+                Xt = torch.empty_like(X.t()).t()
+                lupp.lupp_dgesv_mixed(A0, b_true, Xt, lupp.ir_opts(solver, factor_prec=prec), handle=h)
+                r["forward_error_vs_x_true"] = rel_err(Xt[:, 0], x_true)
+        log("mixed n=%d: %s" % (n, r))
         out.append(r)
     h.close()
+    return out
+
+
+def diag_dominant_dev(torch, A0):
+    """In place: U(-1,1) -> U(-0.5,0.5) (exact), then a_ii := sum_j |a_ij|."""
+    A0.mul_(0.5)
+    d = A0.abs().sum(dim=1)
+    A0.diagonal().copy_(d)
+    del d
+
+
+def mixed_leg(torch, lupp, A0, n, seed, fp64_ms, runs):
+    """Mixed-precision solves on the diagonally dominant matrix built in place
+    from A0 (A0 is overwritten)."""
+    import synth
+    diag_dominant_dev(torch, A0)
+    b = torch.from_numpy(synth.uniform(seed, 1, n, 1)).cuda()  # (n, 1), column-major
+    g = torch.Generator(device="cuda").manual_seed(seed + 3)
+    x_true = torch.empty(n, dtype=torch.float64, device="cuda").uniform_(-1.0, 1.0, generator=g)
+    b_true = (A0 @ x_true).view(n, 1)
+    x64 = fp64_solve(torch, lupp, A0, b)[:, 0]
+    out = mixed_runs(torch, lupp, A0, b, runs, fp64_ms, x_fp64=x64, x_true=x_true, b_true=b_true)
     conv = [r for r in out if r["status"] == "converged"]
     best = max(conv, key=lambda r: r["effective_tflops"]) if conv else None
-    return {"workload": "diag-dominant n=%d (a_ii = row abs-sum of U(-0.5,0.5)), b iid U(-1,1), tol 1e-14" % n,
+    return {"workload": "diag-dominant n=%d (a_ii = row abs-sum of U(-0.5,0.5)), b iid U(-1,1), tol 1e-14; forward "
+                        "errors vs the GPU FP64 LUPP solve and, from a second untimed call with b = A x_true "
+                        "(x_true iid U(-1,1)), vs x_true" % n,
             "runs": out, "best_converged": best}
+
+
+def mixed16_leg(torch, lupp, seed, n=16384):
+    """Config C3a at n = 16384: the diagonally dominant recipe drawn on the
+    device (torch's seeded generator)."""
+    g = torch.Generator(device="cuda").manual_seed(seed + n)
+    A0 = torch.empty((n, n), dtype=torch.float64, device="cuda").t()
+    A0.uniform_(-1.0, 1.0, generator=g)
+    diag_dominant_dev(torch, A0)
+    b = torch.empty((n, 1), dtype=torch.float64, device="cuda").uniform_(-1.0, 1.0, generator=g)
+    x_true = torch.empty(n, dtype=torch.float64, device="cuda").uniform_(-1.0, 1.0, generator=g)
+    b_true = (A0 @ x_true).view(n, 1)
+    x64 = fp64_solve(torch, lupp, A0, b)[:, 0]
+    runs = [("fp16", "gmres"), ("bf16", "gmres"), ("fp16", "classical"), ("bf16", "classical")]
+    out = mixed_runs(torch, lupp, A0, b, runs, x_fp64=x64, x_true=x_true, b_true=b_true)
+    del A0
+    torch.cuda.empty_cache()
+    return {"workload": "diag-dominant n=%d drawn on the device (seed %d), b iid U(-1,1); forward errors vs the "
+                        "GPU FP64 solve and vs x_true (b = A x_true, untimed second call)" % (n, seed + n),
+            "runs": out}
+
+
+def kappa_systems(seed, n=4096, kappas=(1e2, 1e4, 1e6)):
+    """A = U diag(sigma) V^T, sigma_i = kappa^(-(i-1)/(n-1)), U and V the Q
+    factors of QR of iid Gaussian matrices (Philox streams 2 and 3, signs fixed
+    so diag(R) > 0); b = A x_true with x_true iid U(-1,1) (stream 4)."""
+    import synth
+    t = time.time()
+
+    def haar(sid):  # the same construction as synth.kappa_matrix, its factors shared over kappa
+        q, r = np.linalg.qr(synth.gaussian(seed, sid, n, n))
+        return q * np.sign(np.diag(r))[None, :]
+    U = haar(2)
+    V = haar(3)
+    x_true = synth.uniform(seed, 4, n, 1)[:, 0]
+    out = {}
+    for k in kappas:
+        sig = k ** (-(np.arange(n) / max(n - 1, 1)))
+        A = np.asfortranarray((U * sig[None, :]) @ V.T)
+        out["%g" % k] = (A, A @ x_true)
+    log("kappa systems built in %.1f s" % (time.time() - t))
+    return out, x_true
+
+
+def kappa_leg(torch, lupp, systems, x_true, refs):
+    res = []
+    xt = torch.from_numpy(x_true).cuda()
+    for key, (A, b) in systems.items():
+        A0 = torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t()
+        bd = torch.from_numpy(b.copy()).cuda().view(-1, 1)
+        x64 = fp64_solve(torch, lupp, A0, bd)[:, 0]
+        runs = [(p, s) for p in ("bf16", "fp16") for s in ("classical", "gmres")]
+        out = mixed_runs(torch, lupp, A0, bd, runs, x_fp64=x64, x_true=xt, x_ref=refs.get(key))
+        for r in out:
+            r["kappa"] = float(key)
+        res.extend(out)
+        del A0
+    return {"workload": "n=4096, A = U diag(sigma) V^T (Haar U, V from QR of Philox Gaussians, geometric sigma "
+                        "1..1/kappa), b = A x_true; forward errors vs the CPU oracle's FP64 solve (when the CPU leg "
+                        "ran), the GPU FP64 solve and x_true",
+            "runs": res}
 
 
 def large_leg(torch, lupp, n, seed):
@@ -184,7 +444,8 @@ def large_leg(torch, lupp, n, seed):
             "info": int(info.item()), "backward_error": eta(x[:, 0])}
     log("large FP64: %s" % fp64)
     h.close()
-    del A, x, ipiv, info
+    x64 = x
+    del A, ipiv, info
     torch.cuda.empty_cache()
 
     X = torch.empty((1, n), dtype=torch.float64, device="cuda").t()
@@ -203,8 +464,17 @@ def large_leg(torch, lupp, n, seed):
              "refine_ms": round(rep["refine_ms"], 2), "wall_ms": round(ms, 2),
              "effective_tflops": round(flops / (ms * 1e-3) / 1e12, 3),
              "speedup_vs_fp64_solve": round(fp64["wall_ms"] / ms, 3)}
+    mixed["forward_error_vs_gpu_fp64"] = rel_err(X[:, 0], x64[:, 0])
+    # 64 sampled rows of the residual in long double on the host
+    rows = torch.randperm(n, generator=torch.Generator().manual_seed(seed + 64))[:64]
+    Ar = A0[rows.cuda()].cpu().numpy().astype(np.longdouble)
+    xr = X[:, 0].cpu().numpy().astype(np.longdouble)
+    br = b[rows.cuda(), 0].cpu().numpy().astype(np.longdouble)
+    rr = np.abs(br - Ar @ xr).max()
+    den = float(A0.abs().sum(dim=1).max()) * float(np.abs(xr).max()) + float(b.abs().max())
+    mixed["sampled_rows_backward_error_longdouble"] = float(rr / np.longdouble(den))
     log("large mixed: %s" % mixed)
-    del A0, b, X
+    del A0, b, X, x64
     torch.cuda.empty_cache()
     return {"workload": "diag-dominant n=%d (U(-0.5,0.5), a_ii = row abs-sum, drawn on the device from seed %d), "
                         "b iid U(-1,1); FP8 (e4m3, per-block power-of-two scales) updates + FP64 GMRES-IR to 1e-14 "
@@ -264,14 +534,14 @@ def batched_leg(torch, lupp, seed, count=20000, replays=20, dtype="f64", graph=T
     flops = float((2.0 / 3.0 * s64 ** 3 + 2 * s64 ** 2).sum())
     # a sampled backward-error check of the last replay
     X = dB.cpu().numpy()
-    from oracle import checks
+    u = 2.0 ** -53 if dtype == "f64" else 2.0 ** -24
     worst = 0.0
     for i in range(0, count, max(1, count // 200)):
         n = int(sizes[i])
         Ai = A[a_off[i]:a_off[i] + n * n].reshape(n, n, order="F").astype(np.float64)
-        eta = checks.backward_error(Ai, X[b_off[i]:b_off[i] + n].astype(np.float64),
-                                    B[b_off[i]:b_off[i] + n].astype(np.float64))
-        worst = max(worst, eta / (n * (checks.U64 if dtype == "f64" else checks.U32)))
+        eta = host_backward_error(Ai, X[b_off[i]:b_off[i] + n].astype(np.float64),
+                                  B[b_off[i]:b_off[i] + n].astype(np.float64))
+        worst = max(worst, eta / (n * u))
     h.close()
     gbs = nbytes / (ms * 1e-3) / 1e9
     out = {"workload": "%d systems, n_i ~ U{8..128}, A_i and b_i iid U(-1,1), %s, LU + solve" % (count, dtype),
@@ -303,6 +573,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solve leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched small-systems leg")
     ap.add_argument("--no-large", action="store_true", help="skip the large mixed-precision leg")
+    ap.add_argument("--no-c2", action="store_true", help="skip the FP64/FP32 size sweep")
+    ap.add_argument("--no-kappa", action="store_true", help="skip the kappa (n=4096) mixed-precision leg")
     ap.add_argument("--large-n", type=int, default=65536)
     ap.add_argument("--profile-once", action="store_true",
                     help="counter runs: factor once without a pristine device copy, after a 1 GiB "
@@ -340,6 +612,7 @@ def main():
         step = max(1, (256 << 20) // (n * At.itemsize))
         for c0 in range(0, n, step):
             A0.t()[c0:c0 + step].copy_(torch.from_numpy(At[c0:c0 + step]))
+        A_host = At = None  # the host copy is not needed again
     if args.profile_once:
         if args.steps != 1 or args.warmup != 0:
             sys.exit("--profile-once needs --steps 1 --warmup 0")
@@ -406,21 +679,46 @@ def main():
         inf = int(info.item())
         res = probe_residual(torch, A0.double(), A.double(), ipiv) if n <= 32768 else None
         check = {"info": inf, "probe_scaled_residual": res}
+        if not args.profile_once:
+            del A
+            A = None
+            torch.cuda.empty_cache()
+            check["pi_d"] = pid_pivot_check(torch, lupp, n, args.seed + 11, tdt)
         log("check: %s" % check)
 
+    c2 = None
+    if not args.no_c2 and not args.profile_once:
+        log("c2 sweep")
+        c2 = c2_leg(torch, lupp, args.seed)
+
+    ksys = xk_true = None
+    if not args.no_kappa and not args.profile_once:
+        ksys, xk_true = kappa_systems(args.seed)
+
     cpu = None
+    krefs = {}
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle sample)")
-        cpu = cpu_baseline(A_host)
+        log("cpu baseline (oracle)")
+        cpu, krefs = cpu_baseline(args.seed, ksys)
         log("cpu baseline: %s" % cpu)
+
+    kappa = None
+    if ksys is not None:
+        log("kappa leg")
+        kappa = kappa_leg(torch, lupp, ksys, xk_true, krefs)
+        ksys = None
 
     mixed = None
     if not args.no_mixed and args.dtype == "f64":
-        del A
+        A = None
         torch.cuda.empty_cache()
         log("mixed-precision leg")
         runs = [("fp16", "gmres"), ("bf16", "gmres"), ("fp8", "gmres"), ("fp16", "classical"), ("bf16", "classical")]
-        mixed = mixed_leg(torch, lupp, A0, n, args.seed, ms_per_step, runs[:1] if args.profile_once else runs)
+        mixed = {"n%d" % n: mixed_leg(torch, lupp, A0, n, args.seed, ms_per_step, runs[:1] if args.profile_once else runs)}
+        if not args.profile_once:
+            A0 = None
+            torch.cuda.empty_cache()
+            mixed["n16384"] = mixed16_leg(torch, lupp, args.seed)
 
     batched = None
     if not args.no_batched:
@@ -459,6 +757,8 @@ def main():
         "cpu_baseline": cpu,
         "phases": phases,
         "check": check,
+        "c2": c2,
+        "kappa": kappa,
         "mixed": mixed,
         "batched": batched,
         "large": large,

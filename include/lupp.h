@@ -45,9 +45,13 @@ enum {
   LUPP_OK = 0,
   LUPP_ERR_HIP = 1000,         /* 1000 + hipError_t of the failing runtime call   */
   LUPP_ERR_ALLOC = 2000,       /* workspace allocation failed                      */
-  LUPP_ERR_INTERNAL = 2001,    /* a device-side bounded wait expired (reported by
-                                  lupp_sync); results of the affected call invalid */
-  LUPP_ERR_UNSUPPORTED = 2002  /* size or option outside what this build supports */
+  LUPP_ERR_INTERNAL = 2001,    /* a device-side bounded wait expired, or the
+                                  triangular solve's block tickets were out of step
+                                  (reported by lupp_sync); results of the affected
+                                  call invalid */
+  LUPP_ERR_UNSUPPORTED = 2002, /* size or option outside what this build supports */
+  LUPP_ERR_SINGULAR = 2003     /* xGETRS was given a U with an exactly zero diagonal
+                                  entry (reported by lupp_sync)                    */
 };
 
 /* Options for lupp_set_option. */
@@ -115,9 +119,45 @@ int lupp_set_stream(lupp_handle_t h, void* hip_stream);
 /* Set an option (see LUPP_OPT_*).  Errors: -2 unknown option, -3 bad value. */
 int lupp_set_option(lupp_handle_t h, int option, int64_t value);
 
-/* Wait for all work on the handle's stream.  Returns LUPP_ERR_INTERNAL once if
- * a device-side wait of an earlier call expired, else 0 or LUPP_ERR_HIP+e. */
+/* Wait for all work on the handle's streams and collect the device-side status
+ * of the calls made since the previous lupp_sync.  Returns, in this order of
+ * precedence: LUPP_ERR_HIP+e if the wait itself failed; LUPP_ERR_INTERNAL if a
+ * bounded wait of the column-block kernel or of the triangular solve expired,
+ * or the solve found its block tickets out of step (the affected results are
+ * invalid; the flags are cleared and the solve's ticket count re-read from the
+ * device, so later calls run normally); LUPP_ERR_SINGULAR if an xGETRS met an
+ * exactly zero U(k,k) (its X holds Inf/NaN); else 0.  Each status is reported
+ * once. */
 int lupp_sync(lupp_handle_t h);
+
+/* Device workspace, in bytes, that the handle holds after a call of kind op
+ * with the handle's current options (allocated on the call's first use, kept
+ * and reused until lupp_destroy; an upper bound for the mixed solve).
+ *   LUPP_WS_DGETRF / LUPP_WS_SGETRF: an m x n factorization;
+ *   LUPP_WS_DGETRS / LUPP_WS_SGETRS: a solve of order n (m ignored);
+ *   LUPP_WS_DGESV_MIXED: a mixed solve of order n with GMRES restart length k
+ *     (k = 1 for classical refinement; m ignored);
+ *   LUPP_WS_BATCHED: a batched call of m systems (n ignored).
+ * Host only; nothing is allocated.  Errors: -2 op, -3 m, -4 n, -5 k,
+ * -6 bytes NULL. */
+enum {
+  LUPP_WS_DGETRF = 1,
+  LUPP_WS_SGETRF = 2,
+  LUPP_WS_DGETRS = 3,
+  LUPP_WS_SGETRS = 4,
+  LUPP_WS_DGESV_MIXED = 5,
+  LUPP_WS_BATCHED = 6
+};
+int lupp_workspace_bytes(lupp_handle_t h, int op, int64_t m, int64_t n, int64_t k, size_t* bytes);
+
+/* Test hook for the error paths of lupp_sync; not for production use.  Makes
+ * no kernel wait or fault: what = 1 sets the triangular solve's device error
+ * flag as an expired wait would; what = 2 moves the host's ticket count of the
+ * triangular solve far ahead of the device counter, so that every workgroup of
+ * the next solve finds its ticket out of range, writes nothing and exits at
+ * once (x is left as the interchanges made it).  Either is reported by the
+ * next lupp_sync as LUPP_ERR_INTERNAL.  Errors: -2 what. */
+int lupp_test_inject_fault(lupp_handle_t h, int what);
 
 /* Instrumentation (test and benchmark use).  With LUPP_OPT_TIMING set, every
  * xGETRF phase launched on the handle's stream is bracketed by HIP events on
@@ -142,8 +182,19 @@ const char* lupp_status_string(int status);
  * interchanges are applied to the other columns, U12 := inv(L11)*A12 and
  * A22 := A22 - A21*U12 (the paper's finding that the matrix-matrix products
  * dominate: Sections 4.1 and 5.4).
- * Requires m < 2^31 (ipiv is int32).  Errors: -2 m, -3 n, -4 dA, -5 lda,
- * -6 dipiv, -7 dinfo.
+ * Size limit: m <= 131072 (the column-block kernel runs one workgroup of
+ * 1024 threads per 1024 rows, at most 128 workgroups); larger m returns
+ * LUPP_ERR_UNSUPPORTED before anything is launched.
+ * Co-residency: the column-block kernel's workgroups exchange pivot records
+ * through device memory and wait for each other, so they must all be resident
+ * at once.  It is launched with at most one workgroup per CU of the stream it
+ * runs on: with lookahead, on a stream masked to 32 CUs (m - k <= 32768 rows
+ * left) or 64 CUs (<= 65536), otherwise on the caller's stream (up to 128
+ * workgroups on the device's 256 CUs).  Work the caller runs concurrently on
+ * the same GPU may delay but not prevent residency; every wait is bounded, and
+ * an expired wait is reported as LUPP_ERR_INTERNAL by lupp_sync instead of
+ * hanging.
+ * Errors: -2 m (negative or >= 2^31), -3 n, -4 dA, -5 lda, -6 dipiv, -7 dinfo.
  */
 int lupp_dgetrf(lupp_handle_t h, int64_t m, int64_t n, double* dA, int64_t lda,
                 int32_t* dipiv, int32_t* dinfo);
@@ -156,8 +207,10 @@ int lupp_sgetrf(lupp_handle_t h, int64_t m, int64_t n, float* dA, int64_t lda,
  *   dLU    device, lda >= max(1,n);  dipiv device int32[n]
  *   dB     device n x nrhs, ldb >= max(1,n); overwritten by X
  * X = inv(U) * inv(L) * P * B: the interchanges are applied in order, then the
- * unit-lower and upper triangular solves.  No singularity check (a zero U(k,k)
- * yields Inf/NaN, as in LAPACK's getrs); check *info from xGETRF first.
+ * unit-lower and upper triangular solves.  The diagonal of U is checked on the
+ * device: an exactly zero U(k,k) still completes the call (X then holds
+ * Inf/NaN, as in LAPACK's getrs) and is reported as LUPP_ERR_SINGULAR by the
+ * next lupp_sync.  Asynchronous on the handle's stream.
  * Errors: -2 trans, -3 n, -4 nrhs, -5 dLU, -6 lda, -7 dipiv, -8 dB, -9 ldb.
  */
 int lupp_dgetrs(lupp_handle_t h, char trans, int64_t n, int64_t nrhs, const double* dLU,

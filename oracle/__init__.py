@@ -72,13 +72,17 @@ def host_cores() -> int:
         return os.cpu_count() or 1
 
 
-def getrf(A: np.ndarray, ksteps: int = -1, nthreads: int = 1, with_gap: bool = False):
+def getrf(A: np.ndarray, ksteps: int = -1, nthreads: int = 1, with_gap: bool = False, overwrite: bool = False):
     """Factor a copy of A (FP64 or FP32).  Returns (LU, ipiv, info[, gap]).
 
     ``ksteps >= 0`` stops after that many elimination steps (the array then
-    holds the factored leading part and the Schur complement).
+    holds the factored leading part and the Schur complement).  With
+    ``overwrite`` a writable Fortran-ordered FP64/FP32 A is factored in place
+    (no copy; used when the copy must stay outside a timed interval).
     """
-    A = np.array(A, order="F", copy=True)
+    if not (overwrite and isinstance(A, np.ndarray) and A.flags["F_CONTIGUOUS"] and A.flags["WRITEABLE"]
+            and A.dtype in (np.float64, np.float32)):
+        A = np.array(A, order="F", copy=True)
     if A.dtype not in (np.float64, np.float32):
         A = A.astype(np.float64, order="F")
     m, n = A.shape

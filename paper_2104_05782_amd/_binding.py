@@ -20,6 +20,8 @@ _lib.lupp_set_option.argtypes = [_vp, _i32, _i64]
 _lib.lupp_sync.argtypes = [_vp]
 _lib.lupp_timing_summary.argtypes = [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double), _i32]
+_lib.lupp_workspace_bytes.argtypes = [_vp, _i32, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)]
+_lib.lupp_test_inject_fault.argtypes = [_vp, _i32]
 _lib.lupp_status_string.argtypes = [_i32]
 _lib.lupp_status_string.restype = ctypes.c_char_p
 for _name in ("lupp_dgetrf", "lupp_sgetrf"):
@@ -37,6 +39,10 @@ OPT_SPLIT_UPDATE = 7
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "fp8": 3}
 IR_SOLVER = {"classical": 0, "gmres": 1}
 IR_STATUS = {0: "converged", 1: "stagnated", 2: "diverged", 3: "singular", 4: "maxiter"}
+ERR_INTERNAL = 2001
+ERR_UNSUPPORTED = 2002
+ERR_SINGULAR = 2003
+WS = {"dgetrf": 1, "sgetrf": 2, "dgetrs": 3, "sgetrs": 4, "dgesv_mixed": 5, "batched": 6}
 
 
 class IrOpts(ctypes.Structure):
@@ -103,6 +109,16 @@ class Handle:
 
     def sync(self):
         _check(_lib.lupp_sync(self._p), "lupp_sync")
+
+    def workspace_bytes(self, op: str, m: int = 0, n: int = 0, k: int = 0) -> int:
+        """lupp_workspace_bytes for a call kind of WS."""
+        out = ctypes.c_size_t()
+        _check(_lib.lupp_workspace_bytes(self._p, WS[op], m, n, k, ctypes.byref(out)), "lupp_workspace_bytes")
+        return out.value
+
+    def inject_fault(self, what: int):
+        """lupp_test_inject_fault (test hook of lupp_sync's error paths)."""
+        _check(_lib.lupp_test_inject_fault(self._p, what), "lupp_test_inject_fault")
 
     def timing_summary(self, phase: str, reset: bool = False):
         """(count, ms, flops) recorded for a phase (see lupp_timing_summary)."""

@@ -531,6 +531,8 @@ void free_batched(lupp_handle_t h) {
   h->batch = nullptr;
 }
 
+size_t batch_workspace_bytes(int64_t batch) { return (size_t)(batch < 1024 ? 1024 : batch) * 4 + 256; }
+
 namespace {
 
 hipError_t ensure_batch(lupp_handle_t h, int64_t batch) {

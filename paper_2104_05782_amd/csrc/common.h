@@ -168,7 +168,8 @@ hipError_t gemm_lp_sub(hipStream_t s, int mode, int64_t M, int64_t N, int64_t K,
 struct TrsvState {
   uint32_t* flags;     // device, max_blocks entries
   uint64_t* ticket;    // device counter, only ever incremented
-  int32_t* err;        // device, set when a bounded wait expires
+  int32_t* err;        // device, set when a bounded wait expires (1) or tickets are out of step (2)
+  int32_t* sing;       // device, set by getrs when a diagonal entry of U is exactly zero
   int64_t max_blocks;  // capacity of flags: ceil(rows / 64) (128-row blocks use half)
   uint32_t epoch;      // host copy of the last epoch used
   uint64_t tickets;    // host copy of the tickets handed out so far
@@ -178,6 +179,10 @@ struct TrsvState {
 // one right-hand side, with L/U in the n x n matrix A.
 template <typename T>
 hipError_t trsv_wave(hipStream_t s, bool lower, int64_t n, const T* A, int64_t lda, T* x, TrsvState* st);
+
+// *flag = 1 when some A(k,k), k < n, is exactly zero (flag untouched otherwise).
+template <typename T>
+hipError_t diag_zero_check(hipStream_t s, int64_t n, const T* A, int64_t lda, int32_t* flag);
 
 // r = b - A x in FP64 (deterministic: nchunk column chunks, part holds nchunk*n)
 hipError_t residual(hipStream_t s, int64_t n, const double* A, int64_t lda, const double* x, const double* b,

@@ -93,3 +93,16 @@ void free_mixed(lupp_handle_t h);
 void free_batched(lupp_handle_t h);
 
 }  // namespace lupp
+
+namespace lupp {
+// After the stream has drained: read and clear the triangular solve's error
+// flag; when it was set, the host's ticket count is re-read from the device
+// counter, so that later solves start in step.  Returns the flag (0 none,
+// 1 an expired wait, 2 a ticket mismatch) or -1 if the copies failed.
+int take_trsv_error(lupp_handle_t h);
+// Device bytes the handle holds for these calls with its current options.
+size_t getrf_workspace_bytes(lupp_handle_t h, int64_t m, int64_t n, size_t elem);
+size_t trsv_workspace_bytes(int64_t n);
+size_t mixed_workspace_bytes(int64_t n, int64_t restart);
+size_t batch_workspace_bytes(int64_t batch);
+}  // namespace lupp

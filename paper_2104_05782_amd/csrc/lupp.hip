@@ -336,6 +336,7 @@ template <typename T>
 hipError_t getrs(lupp_handle_t h, int64_t n, int64_t nrhs, const T* LU, int64_t lda, const int32_t* ipiv, T* B,
                  int64_t ldb) {
   hipStream_t s = h->stream;
+  LUPP_TRY(diag_zero_check<T>(s, n, LU, lda, h->trsv.sing));
   for (int64_t k1 = 0; k1 < n; k1 += kMaxSwaps) {
     const int64_t k2 = (n - k1 < kMaxSwaps) ? n : k1 + kMaxSwaps;
     LUPP_TRY(laswp<T>(s, B, ldb, n, 0, nrhs, 0, 0, ipiv, k1, k2, h->pairs));
@@ -394,6 +395,7 @@ hipError_t ensure_trsv(lupp_handle_t h, int64_t n) {
     t.flags = (uint32_t*)p;
     t.ticket = (uint64_t*)((char*)p + ((size_t)cap * sizeof(uint32_t) + 7) / 8 * 8);
     t.err = (int32_t*)(t.ticket + 1);
+    t.sing = t.err + 1;
     t.max_blocks = cap;
     LUPP_TRY(hipMemsetAsync(p, 0, (size_t)cap * sizeof(uint32_t) + 64, h->stream));
     t.tickets = 0;
@@ -479,6 +481,39 @@ hipError_t ensure_workspace(lupp_handle_t h) {
   return hipSuccess;
 }
 
+int take_trsv_error(lupp_handle_t h) {
+  TrsvState& t = h->trsv;
+  if (!t.err) return 0;
+  int32_t err = 0;
+  if (hipMemcpy(&err, t.err, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) return -1;
+  if (!err) return 0;
+  const int32_t zero = 0;
+  uint64_t dev = 0;
+  if (hipMemcpy(t.err, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(&dev, t.ticket, sizeof(dev), hipMemcpyDeviceToHost) != hipSuccess)
+    return -1;
+  t.tickets = dev;
+  return err;
+}
+
+size_t getrf_workspace_bytes(lupp_handle_t h, int64_t m, int64_t n, size_t elem) {
+  size_t bytes = sizeof(LeafSlots) + sizeof(SwapPairs);
+  const int64_t p = m < n ? m : n;
+  const int64_t nb = h->nb;
+  const int64_t J = (p + nb - 1) / nb;
+  if (h->defer && J >= 2 && nb <= kMaxSwaps && m - nb <= left_gather_max_rows(elem) && (J - 1) * nb <= 0x7fffffff) {
+    const size_t d = (size_t)J * sizeof(SwapPairs) + sizeof(int32_t) * (size_t)(2 * m + left_map_entries(J, m, nb));
+    if (d <= ((size_t)1 << 30)) bytes += d;
+  }
+  if (elem == 4 && h->update_prec != LUPP_PREC_FP32) bytes += (size_t)gemm_lp_scale_slots(m, n) * 3 * sizeof(int);
+  return bytes;
+}
+
+size_t trsv_workspace_bytes(int64_t n) {
+  const int64_t need = (n + 63) / 64;
+  return (size_t)(need < 1024 ? 1024 : need) * sizeof(uint32_t) + 64;
+}
+
 namespace {
 
 template <typename T>
@@ -514,7 +549,7 @@ int getrs_entry(lupp_handle_t h, char trans, int64_t n, int64_t nrhs, const T* L
   if (ldb < (n > 1 ? n : 1)) return -9;
   if (n == 0 || nrhs == 0) return LUPP_OK;
   hipError_t e = ensure_workspace(h);
-  if (e == hipSuccess && nrhs <= 2) e = ensure_trsv(h, n);
+  if (e == hipSuccess) e = ensure_trsv(h, nrhs <= 2 ? n : 1);
   if (e != hipSuccess) return LUPP_ERR_ALLOC;
   return hip_status(getrs<T>(h, n, nrhs, LU, lda, ipiv, B, ldb));
 }
@@ -628,9 +663,64 @@ int lupp_sync(lupp_handle_t h) {
     if (err) {
       const int32_t zero = 0;
       (void)hipMemcpy(&h->slots->err, &zero, sizeof(zero), hipMemcpyHostToDevice);
+      (void)lupp::take_trsv_error(h);
       return LUPP_ERR_INTERNAL;
     }
   }
+  const int terr = lupp::take_trsv_error(h);
+  if (terr < 0) return lupp::hip_status(hipGetLastError());
+  int32_t sing = 0;
+  if (h->trsv.sing) {
+    e = hipMemcpy(&sing, h->trsv.sing, sizeof(sing), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return lupp::hip_status(e);
+    if (sing) {
+      const int32_t zero = 0;
+      (void)hipMemcpy(h->trsv.sing, &zero, sizeof(zero), hipMemcpyHostToDevice);
+    }
+  }
+  if (terr) return LUPP_ERR_INTERNAL;
+  if (sing) return LUPP_ERR_SINGULAR;
+  return LUPP_OK;
+}
+
+int lupp_workspace_bytes(lupp_handle_t h, int op, int64_t m, int64_t n, int64_t k, size_t* bytes) {
+  if (!h) return -1;
+  if (op < LUPP_WS_DGETRF || op > LUPP_WS_BATCHED) return -2;
+  if (m < 0) return -3;
+  if (n < 0) return -4;
+  if (k < 0 || (op == LUPP_WS_DGESV_MIXED && k > 60)) return -5;
+  if (!bytes) return -6;
+  const size_t base = sizeof(lupp::LeafSlots) + sizeof(lupp::SwapPairs);
+  switch (op) {
+    case LUPP_WS_DGETRF: *bytes = lupp::getrf_workspace_bytes(h, m, n, 8); break;
+    case LUPP_WS_SGETRF: *bytes = lupp::getrf_workspace_bytes(h, m, n, 4); break;
+    case LUPP_WS_DGETRS:
+    case LUPP_WS_SGETRS: *bytes = base + lupp::trsv_workspace_bytes(n); break;
+    case LUPP_WS_DGESV_MIXED: {
+      const int saved = h->update_prec;
+      h->update_prec = LUPP_PREC_FP16;  // the scale workspace of any low-precision format
+      *bytes = lupp::getrf_workspace_bytes(h, n, n, 4) + lupp::trsv_workspace_bytes(n) +
+               lupp::mixed_workspace_bytes(n, k < 1 ? 1 : k);
+      h->update_prec = saved;
+      break;
+    }
+    default: *bytes = lupp::batch_workspace_bytes(m); break;
+  }
+  return LUPP_OK;
+}
+
+int lupp_test_inject_fault(lupp_handle_t h, int what) {
+  if (!h) return -1;
+  if (what != 1 && what != 2) return -2;
+  const hipError_t e = lupp::ensure_workspace(h);
+  if (e != hipSuccess || lupp::ensure_trsv(h, 1) != hipSuccess) return LUPP_ERR_ALLOC;
+  if (what == 1) {
+    const hipError_t e1 = hipStreamSynchronize(h->stream);
+    if (e1 != hipSuccess) return lupp::hip_status(e1);
+    const int32_t one = 1;
+    return lupp::hip_status(hipMemcpy(h->trsv.err, &one, sizeof(one), hipMemcpyHostToDevice));
+  }
+  h->trsv.tickets += (uint64_t)1 << 40;  // every ticket of the next solve falls below its base
   return LUPP_OK;
 }
 
@@ -670,6 +760,7 @@ const char* lupp_status_string(int status) {
   if (status == LUPP_ERR_ALLOC) return "workspace allocation failed";
   if (status == LUPP_ERR_INTERNAL) return "device-side wait expired";
   if (status == LUPP_ERR_UNSUPPORTED) return "unsupported size or option";
+  if (status == LUPP_ERR_SINGULAR) return "exactly singular triangular factor";
   if (status > LUPP_ERR_HIP && status < LUPP_ERR_ALLOC) return hipGetErrorString((hipError_t)(status - LUPP_ERR_HIP));
   return "unknown status";
 }

@@ -49,6 +49,35 @@ void free_mixed(lupp_handle_t h) {
 
 namespace {
 
+// Layout of the mixed solve's single allocation for order n and restart m.
+struct MixedLayout {
+  size_t oA, oi, ov, oz, op, oV, oh, total;
+};
+MixedLayout mixed_layout(int64_t n, int64_t m) {
+  const int64_t nblk = (n + 255) / 256;
+  int64_t part = kResidualChunks * n;
+  if (nblk * 64 > part) part = nblk * 64;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  MixedLayout L;
+  size_t off = 0;
+  L.oA = off;
+  off += al((size_t)n * n * 4);
+  L.oi = off;
+  off += al((size_t)n * 4 * 2 + 64);  // ipiv, perm, info
+  L.ov = off;
+  off += al((size_t)n * 8) * 6;  // x, xbest, r, t, d, zero
+  L.oz = off;
+  off += al((size_t)n * 4);
+  L.op = off;
+  off += al((size_t)part * 8);
+  L.oV = off;
+  off += al((size_t)n * (m + 1) * 8);
+  L.oh = off;
+  off += al(3 * 64 * 8 + 16 * 8);
+  L.total = off;
+  return L;
+}
+
 hipError_t ensure_mixed(lupp_handle_t h, int64_t n, int64_t m) {
   MixedWs* w = h->mixed;
   if (w && w->n >= n && w->m >= m) return hipSuccess;
@@ -58,27 +87,10 @@ hipError_t ensure_mixed(lupp_handle_t h, int64_t n, int64_t m) {
   free_mixed(h);
   w = new (std::nothrow) MixedWs();
   if (!w) return hipErrorOutOfMemory;
-  const int64_t nblk = (n + 255) / 256;
-  int64_t part = kResidualChunks * n;
-  if (nblk * 64 > part) part = nblk * 64;
+  const MixedLayout Lo = mixed_layout(n, m);
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  size_t off = 0;
-  const size_t oA = off;
-  off += al((size_t)n * n * 4);
-  const size_t oi = off;
-  off += al((size_t)n * 4 * 2 + 64);  // ipiv, perm, info
-  const size_t ov = off;
-  off += al((size_t)n * 8) * 6;  // x, xbest, r, t, d, zero
-  const size_t oz = off;
-  off += al((size_t)n * 4);
-  const size_t op = off;
-  off += al((size_t)part * 8);
-  const size_t oV = off;
-  off += al((size_t)n * (m + 1) * 8);
-  const size_t oh = off;
-  off += al(3 * 64 * 8 + 16 * 8);
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, off);
+  hipError_t e = hipMalloc(&p, Lo.total);
   if (e != hipSuccess) {
     delete w;
     return e;
@@ -87,11 +99,11 @@ hipError_t ensure_mixed(lupp_handle_t h, int64_t n, int64_t m) {
   w->base = p;
   w->n = n;
   w->m = m;
-  w->A32 = (float*)(b + oA);
-  w->ipiv = (int32_t*)(b + oi);
+  w->A32 = (float*)(b + Lo.oA);
+  w->ipiv = (int32_t*)(b + Lo.oi);
   w->perm = w->ipiv + n;
   w->info = w->perm + n;
-  double* vs = (double*)(b + ov);
+  double* vs = (double*)(b + Lo.ov);
   const size_t vstride = al((size_t)n * 8) / 8;
   w->x = vs;
   w->xbest = vs + vstride;
@@ -99,10 +111,10 @@ hipError_t ensure_mixed(lupp_handle_t h, int64_t n, int64_t m) {
   w->t = vs + 3 * vstride;
   w->d = vs + 4 * vstride;
   w->zero = vs + 5 * vstride;
-  w->z32 = (float*)(b + oz);
-  w->part = (double*)(b + op);
-  w->V = (double*)(b + oV);
-  w->hdev = (double*)(b + oh);
+  w->z32 = (float*)(b + Lo.oz);
+  w->part = (double*)(b + Lo.op);
+  w->V = (double*)(b + Lo.oV);
+  w->hdev = (double*)(b + Lo.oh);
   w->mx = (unsigned long long*)(w->hdev + 3 * 64);
   h->mixed = w;
   LUPP_TRY(hipMemsetAsync(w->zero, 0, (size_t)n * 8, h->stream));
@@ -397,17 +409,15 @@ int gesv_mixed(lupp_handle_t h, int64_t n, int64_t nrhs, const double* A, int64_
   }
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_status(e);
-  int32_t terr = 0;
-  if (h->trsv.err && hipMemcpy(&terr, h->trsv.err, 4, hipMemcpyDeviceToHost) == hipSuccess && terr) {
-    const int32_t zero = 0;
-    (void)hipMemcpy(h->trsv.err, &zero, 4, hipMemcpyHostToDevice);
-    return LUPP_ERR_INTERNAL;
-  }
+  if (take_trsv_error(h) != 0) return LUPP_ERR_INTERNAL;
   rep.refine_ms = std::chrono::duration<double, std::milli>(clk::now() - t1).count();
   return LUPP_OK;
 }
 
 }  // namespace
+
+size_t mixed_workspace_bytes(int64_t n, int64_t restart) { return mixed_layout(n, restart).total; }
+
 }  // namespace lupp
 
 extern "C" {

@@ -530,6 +530,12 @@ __global__ void k_axpy_dev(int64_t n, double sign, const unsigned long long* __r
 
 inline unsigned grid1(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+template <typename T>
+__global__ void k_diag_zero(int64_t n, const T* __restrict__ A, int64_t lda, int32_t* __restrict__ flag) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k < n && A[k + k * lda] == T(0)) *flag = 1;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -541,6 +547,7 @@ hipError_t trsv_wave(hipStream_t s, bool lower, int64_t n, const T* A, int64_t l
   if (st->epoch > 0xF0000000u) return hipErrorInvalidValue;  // caller resets
   st->epoch += 1;
   const uint64_t tbase = st->tickets;
+  hipError_t e;
   if (n >= kTrsvWideMinN) {
     const int64_t nblk2 = (n + TB2 - 1) / TB2;
     st->tickets += (uint64_t)nblk2;
@@ -550,17 +557,32 @@ hipError_t trsv_wave(hipStream_t s, bool lower, int64_t n, const T* A, int64_t l
     else
       hipLaunchKernelGGL((k_trsv128<T, false>), dim3((unsigned)nblk2), dim3(512), 0, s, n, A, lda, x, st->flags,
                          st->ticket, tbase, st->epoch, st->err);
-    return hipGetLastError();
+    e = hipGetLastError();
+  } else {
+    st->tickets += (uint64_t)nblk;
+    if (lower)
+      hipLaunchKernelGGL((k_trsv<T, true>), dim3((unsigned)nblk), dim3(256), 0, s, n, A, lda, x, st->flags,
+                         st->ticket, tbase, st->epoch, st->err);
+    else
+      hipLaunchKernelGGL((k_trsv<T, false>), dim3((unsigned)nblk), dim3(256), 0, s, n, A, lda, x, st->flags,
+                         st->ticket, tbase, st->epoch, st->err);
+    e = hipGetLastError();
   }
-  st->tickets += (uint64_t)nblk;
-  if (lower)
-    hipLaunchKernelGGL((k_trsv<T, true>), dim3((unsigned)nblk), dim3(256), 0, s, n, A, lda, x, st->flags, st->ticket,
-                       tbase, st->epoch, st->err);
-  else
-    hipLaunchKernelGGL((k_trsv<T, false>), dim3((unsigned)nblk), dim3(256), 0, s, n, A, lda, x, st->flags, st->ticket,
-                       tbase, st->epoch, st->err);
+  if (e != hipSuccess) {  // nothing ran: the host's counts go back to the device's
+    st->tickets = tbase;
+    st->epoch -= 1;
+  }
+  return e;
+}
+template <typename T>
+hipError_t diag_zero_check(hipStream_t s, int64_t n, const T* A, int64_t lda, int32_t* flag) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_diag_zero<T>, dim3(grid1(n)), dim3(256), 0, s, n, A, lda, flag);
   return hipGetLastError();
 }
+template hipError_t diag_zero_check<double>(hipStream_t, int64_t, const double*, int64_t, int32_t*);
+template hipError_t diag_zero_check<float>(hipStream_t, int64_t, const float*, int64_t, int32_t*);
+
 template hipError_t trsv_wave<double>(hipStream_t, bool, int64_t, const double*, int64_t, double*, TrsvState*);
 template hipError_t trsv_wave<float>(hipStream_t, bool, int64_t, const float*, int64_t, float*, TrsvState*);
 

@@ -190,11 +190,12 @@ def test_getrs_multi_rhs(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_getrs_wide_blocks_ragged(dtype):
-    """From order 8192 on the triangular solves use 128-row blocks: a ragged
-    order (a partial last block, 77 rows past a 64-row boundary) above that
-    threshold, solved to the backward-error bound."""
-    n = 8192 + 77
+@pytest.mark.parametrize("n", [8192 + 77, 8192 + 40])
+def test_getrs_wide_blocks_ragged(dtype, n):
+    """From order 8192 on the triangular solves use 128-row blocks: ragged
+    orders above that threshold -- a last block whose second 64-row half is
+    partly filled (77 rows past the boundary) or empty (40 rows) -- solved to
+    the backward-error bound."""
     announce("getrs n=%d %s (128-row solve blocks)" % (n, dtype))
     npdt = np.float64 if dtype == "f64" else np.float32
     A = synth.uniform(6, 0, n, n).astype(npdt)
@@ -438,3 +439,96 @@ def test_lookahead_wide_panel_pair_bit_identical(dtype):
     r = (A0.double() @ x)[P] - L @ (U @ x)
     u = checks.U64 if dtype == "f64" else checks.U32
     assert float(r.abs().max() / (m * A0.double().abs().sum(dim=1).max() * x.abs().max())) < 10 * u
+
+
+# ---------------------------------------------------------------- device-side status through lupp_sync
+def _solve_setup(n, seed, zero_col=None):
+    A = synth.uniform(seed, 0, n, n)
+    if zero_col is not None:
+        A[:, zero_col] = 0.0
+    b = synth.uniform(seed, 1, n, 1)[:, 0]
+    h = lupp.Handle()
+    dA = to_dev(A)
+    ipiv, info = lupp.getrf(dA, handle=h)
+    h.sync()
+    return A, b, h, dA, ipiv, int(info.item())
+
+
+@pytest.mark.gpu
+def test_getrs_reports_zero_diagonal():
+    """A zero column gives info > 0; a solve with those factors is reported
+    as LUPP_ERR_SINGULAR by the next sync, once."""
+    n = 300
+    announce("getrs singular n=%d" % n)
+    A, b, h, dA, ipiv, info = _solve_setup(n, 61, zero_col=200)
+    assert info == 201
+    db = to_dev(b)
+    lupp.getrs(dA, ipiv, db, handle=h)
+    with pytest.raises(lupp.LuppError) as ex:
+        h.sync()
+    assert ex.value.rc == lupp._binding.ERR_SINGULAR
+    h.sync()  # reported once
+    h.close()
+
+
+@pytest.mark.gpu
+def test_sync_reports_solve_error_flag():
+    """The triangular solve's device error flag (set from the host by the
+    test hook, as an expired wait sets it) is reported by lupp_sync once."""
+    n = 257
+    announce("sync trsv error flag n=%d" % n)
+    A, b, h, dA, ipiv, info = _solve_setup(n, 62)
+    h.inject_fault(1)
+    with pytest.raises(lupp.LuppError) as ex:
+        h.sync()
+    assert ex.value.rc == lupp._binding.ERR_INTERNAL
+    db = to_dev(b)
+    lupp.getrs(dA, ipiv, db, handle=h)
+    h.sync()
+    assert checks.backward_error(A, to_host(db), b) <= 8 * n * checks.U64
+    h.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n", [700, 8192 + 40])
+def test_ticket_mismatch_reported_and_recovered(n):
+    """Host and device ticket counts out of step (forced by the test hook, so
+    that every workgroup finds its ticket out of range and exits): the solve
+    is reported as LUPP_ERR_INTERNAL, and the next solve is correct again."""
+    announce("ticket mismatch n=%d" % n)
+    A, b, h, dA, ipiv, info = _solve_setup(n, 63)
+    assert info == 0
+    h.inject_fault(2)
+    db = to_dev(b)
+    lupp.getrs(dA, ipiv, db, handle=h)
+    with pytest.raises(lupp.LuppError) as ex:
+        h.sync()
+    assert ex.value.rc == lupp._binding.ERR_INTERNAL
+    db = to_dev(b)
+    lupp.getrs(dA, ipiv, db, handle=h)
+    h.sync()
+    assert checks.backward_error(A, to_host(db), b) <= 8 * n * checks.U64
+    h.close()
+
+
+@pytest.mark.gpu
+def test_workspace_bytes():
+    """lupp_workspace_bytes: the documented components, growing with the shape."""
+    h = lupp.Handle()
+    base = h.workspace_bytes("dgetrs", 0, 1)
+    assert h.workspace_bytes("dgetrs", 0, 100) == base
+    assert h.workspace_bytes("dgetrs", 0, 64 * 4096) == base + (4096 - 1024) * 4
+    assert h.workspace_bytes("batched", 20000) == 20000 * 4 + 256
+    assert h.workspace_bytes("batched", 10) == 1024 * 4 + 256
+    small = h.workspace_bytes("dgetrf", 400, 400)   # one block: no deferred interchanges
+    big = h.workspace_bytes("dgetrf", 4096, 4096)
+    assert big > small > 0
+    h.set_option(6, 0)  # no deferral: the factorization's base workspace only
+    assert h.workspace_bytes("dgetrf", 4096, 4096) == small
+    mixed = h.workspace_bytes("dgesv_mixed", 0, 2000, 30)
+    assert mixed > 2000 * 2000 * 4 + 31 * 2000 * 8
+    assert h.workspace_bytes("dgesv_mixed", 0, 2000, 1) < mixed
+    for bad in ((99, 1, 1, 0), (1, -1, 1, 0), (1, 1, -1, 0), (5, 0, 10, 61)):
+        rc = lupp._binding._lib.lupp_workspace_bytes(h.ptr, bad[0], bad[1], bad[2], bad[3], None)
+        assert rc < 0
+    h.close()
