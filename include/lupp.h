@@ -107,7 +107,10 @@ enum {
 
 /* Create a handle on the current HIP device.  The handle owns its workspace
  * (allocated on first use, freed by lupp_destroy) and borrows a stream
- * (default: the null stream).  Errors: -1 if h is NULL. */
+ * (default: the null stream).  Creation itself allocates no device memory: it
+ * creates the batched path's streams and events and looks up the device
+ * address of lupp_dgesv_batched_noalloc's scratch array on this device.
+ * Errors: -1 if h is NULL. */
 int lupp_create(lupp_handle_t* h);
 
 /* Release the handle and its workspace.  Waits for the handle's stream. */
@@ -334,6 +337,28 @@ int lupp_dgesv_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const 
 int lupp_sgesv_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_t* dA_off,
                        float* dA, const int64_t* dipiv_off, int32_t* dipiv,
                        const int64_t* dB_off, float* dB, int32_t* dinfo);
+/*
+ * Allocation-free variant of lupp_dgesv_batched, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, kernels and results as
+ * lupp_dgesv_batched, but the class list and counters live in a fixed array
+ * of the library (about 4 MiB per device, held until the process ends)
+ * instead of handle workspace, so no call allocates or frees device memory
+ * (the handle's streams were created by lupp_create).
+ *   batch <= 1048576 (LUPP_NOALLOC_MAX_BATCH); a larger batch returns
+ *   LUPP_ERR_UNSUPPORTED before anything is launched.
+ * Every call on one device shares that device's array: calls that may
+ * overlap in time on the same device (different handles or streams without
+ * ordering between them) race and corrupt each other's results.  Calls
+ * ordered on one stream do not.  Nothing in the array needs clearing: each
+ * call rewrites the parts it reads.
+ * Errors: as lupp_dgesv_batched.
+ */
+#define LUPP_NOALLOC_MAX_BATCH 1048576
+int lupp_dgesv_batched_noalloc(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_t* dA_off,
+                               double* dA, const int64_t* dipiv_off, int32_t* dipiv,
+                               const int64_t* dB_off, double* dB, int32_t* dinfo);
+
 /* Factorization only (no right-hand sides). */
 int lupp_dgetrf_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_t* dA_off,
                         double* dA, const int64_t* dipiv_off, int32_t* dipiv, int32_t* dinfo);

@@ -27,6 +27,8 @@ from ._binding import (  # noqa: F401
     gesv_batched,
     gesv_mixed,
     lupp_xgesv_batched,
+    lupp_dgesv_batched_noalloc,
+    NOALLOC_MAX_BATCH,
     ir_opts,
     lupp_dgesv_mixed,
     status_string,

@@ -63,7 +63,7 @@ _lib.lupp_ir_opts_default.argtypes = [ctypes.POINTER(IrOpts), ctypes.c_int32]
 _lib.lupp_ir_opts_default.restype = None
 _lib.lupp_dgesv_mixed.argtypes = [_vp, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(IrOpts),
                                   ctypes.POINTER(IrReport)]
-for _name in ("lupp_dgesv_batched", "lupp_sgesv_batched"):
+for _name in ("lupp_dgesv_batched", "lupp_sgesv_batched", "lupp_dgesv_batched_noalloc"):
     getattr(_lib, _name).argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 for _name in ("lupp_dgetrf_batched", "lupp_sgetrf_batched"):
     getattr(_lib, _name).argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -291,6 +291,25 @@ def lupp_xgesv_batched(n, A, a_off, ipiv, p_off, B, b_off, info, handle: Handle 
     if b_off.numel() < batch:
         raise ValueError("b_off needs one entry per system")
     fn = _lib.lupp_dgesv_batched if d else _lib.lupp_sgesv_batched
+    _check(fn(h.ptr, batch, n.data_ptr(), a_off.data_ptr(), A.data_ptr(), p_off.data_ptr(), ipiv.data_ptr(),
+              b_off.data_ptr(), B.data_ptr(), info.data_ptr()), fn.__name__)
+
+
+NOALLOC_MAX_BATCH = 1048576
+
+
+def lupp_dgesv_batched_noalloc(n, A, a_off, ipiv, p_off, B, b_off, info, handle: Handle | None = None):
+    """lupp_dgesv_batched_noalloc: lupp_dgesv_batched with the library's fixed
+    scratch array instead of handle workspace (FP64, with right-hand sides)."""
+    batch = int(n.numel())
+    for t, dt, what in ((n, torch.int32, "n"), (a_off, torch.int64, "a_off"), (p_off, torch.int64, "p_off"),
+                        (ipiv, torch.int32, "ipiv"), (info, torch.int32, "info"), (A, torch.float64, "A"),
+                        (B, torch.float64, "B"), (b_off, torch.int64, "b_off")):
+        _dev(t, dt, what)
+    if min(info.numel(), a_off.numel(), p_off.numel(), b_off.numel()) < batch:
+        raise ValueError("n, a_off, p_off, b_off and info need one entry per system")
+    h = _prep(handle)
+    fn = _lib.lupp_dgesv_batched_noalloc
     _check(fn(h.ptr, batch, n.data_ptr(), a_off.data_ptr(), A.data_ptr(), p_off.data_ptr(), ipiv.data_ptr(),
               b_off.data_ptr(), B.data_ptr(), info.data_ptr()), fn.__name__)
 

@@ -20,6 +20,8 @@
 // four streams so that the short classes fill the CUs the long ones leave
 // idle.  No host synchronization or allocation happens per call
 // (graph-capturable once the workspace exists for the batch size).
+#include <mutex>
+
 #include "handle.h"
 #include "wave.h"
 
@@ -535,20 +537,38 @@ size_t batch_workspace_bytes(int64_t batch) { return (size_t)(batch < 1024 ? 102
 
 namespace {
 
-hipError_t ensure_batch(lupp_handle_t h, int64_t batch) {
+// Scratch of the allocation-free entry point: the class list (one int per
+// system) followed by the eight class counters and offsets, for at most
+// kNoAllocMaxBatch systems.  Each device holds one copy until the process
+// ends; every call on that device shares it.  Host code never passes the
+// array's name to a kernel: it uses the device address looked up once per
+// device at handle creation (g_scratch).
+constexpr int64_t kNoAllocMaxBatch = 1 << 20;
+constexpr int kScratchMeta = 64;  // ints after the list: meta[0, 8), padded to 256 bytes
+__device__ __align__(256) int32_t scratch[kNoAllocMaxBatch + kScratchMeta];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch[kMaxDevices] = {};
+
+// The device address of this device's scratch array (the current device
+// must be h->device).
+hipError_t lookup_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return hipSuccess;
+  void* ptr = nullptr;
+  LUPP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch[device] = (int32_t*)ptr;
+  return hipSuccess;
+}
+
+// The class list of an allocating call: grown on demand (this synchronizes
+// the handle's streams and reallocates).
+hipError_t ensure_batch_list(lupp_handle_t h, int64_t batch) {
   BatchWs* w = h->batch;
-  if (!w) {
-    w = new (std::nothrow) BatchWs();
-    if (!w) return hipErrorOutOfMemory;
-    h->batch = w;
-    for (int c = 0; c < kBatchClasses; ++c) {
-      LUPP_TRY(hipStreamCreateWithFlags(&w->streams[c], hipStreamNonBlocking));
-      LUPP_TRY(hipEventCreateWithFlags(&w->join[c], hipEventDisableTiming));
-    }
-    LUPP_TRY(hipEventCreateWithFlags(&w->fork, hipEventDisableTiming));
-    LUPP_TRY(setup_class_kernels<double>(h, w, 0));
-    LUPP_TRY(setup_class_kernels<float>(h, w, 1));
-  }
+  if (!w) return hipErrorNotInitialized;
   if (batch <= w->capacity && w->list) return hipSuccess;
   LUPP_TRY(hipStreamSynchronize(h->stream));
   for (int c = 0; c < kBatchClasses; ++c) LUPP_TRY(hipStreamSynchronize(w->streams[c]));
@@ -564,16 +584,17 @@ hipError_t ensure_batch(lupp_handle_t h, int64_t batch) {
   return hipSuccess;
 }
 
+// Binning and the per-class launches on the handle's class streams (forked
+// from and joined to the handle's stream), with the class list and counters
+// at list / meta.  Launches only: no allocation, no host synchronization.
 template <typename T>
-int gesv_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_t* aoff, T* A, const int64_t* poff,
-                 int32_t* piv, const int64_t* boff, T* B, int32_t* info) {
-  hipError_t e = ensure_batch(h, batch);
-  if (e != hipSuccess) return e == hipErrorOutOfMemory ? LUPP_ERR_ALLOC : hip_status(e);
+int launch_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_t* aoff, T* A, const int64_t* poff,
+                   int32_t* piv, const int64_t* boff, T* B, int32_t* info, int32_t* list, int32_t* meta) {
   BatchWs* w = h->batch;
   hipStream_t s = h->stream;
   const int prec = sizeof(T) == 8 ? 0 : 1;
-  hipLaunchKernelGGL(k_batch_bin, dim3(1), dim3(1024), 0, s, batch, dn, w->list, w->meta, info);
-  e = hipGetLastError();
+  hipLaunchKernelGGL(k_batch_bin, dim3(1), dim3(1024), 0, s, batch, dn, list, meta, info);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_status(e);
   e = hipEventRecord(w->fork, s);
   if (e != hipSuccess) return hip_status(e);
@@ -583,9 +604,10 @@ int gesv_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_
     e = hipStreamWaitEvent(sc, w->fork, 0);
     if (e != hipSuccess) return hip_status(e);
     const void* f = batch_kernel<T>(c);
-    const int32_t* meta = w->meta;
+    const int32_t* cmeta = meta;
+    const int32_t* clist = list;
     void* args[] = {(void*)&c, (void*)&dn, (void*)&aoff, (void*)&A, (void*)&poff, (void*)&piv, (void*)&boff,
-                    (void*)&B, (void*)&info, (void*)&w->list, (void*)&meta};
+                    (void*)&B, (void*)&info, (void*)&clist, (void*)&cmeta};
     e = hipLaunchKernel(f, dim3(w->grid[prec][c]), dim3(class_threads<T>(c)), args, 0, sc);
     if (e != hipSuccess) return hip_status(e);
     e = hipEventRecord(w->join[c], sc);
@@ -594,6 +616,36 @@ int gesv_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_
   }
   return LUPP_OK;
 }
+
+template <typename T>
+int gesv_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_t* aoff, T* A, const int64_t* poff,
+                 int32_t* piv, const int64_t* boff, T* B, int32_t* info) {
+  hipError_t e = ensure_batch_list(h, batch);
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? LUPP_ERR_ALLOC : hip_status(e);
+  return launch_batched<T>(h, batch, dn, aoff, A, poff, piv, boff, B, info, h->batch->list, h->batch->meta);
+}
+
+}  // namespace
+
+// At handle creation, on the handle's device: the class streams and events,
+// the persistent grids, and the device address of the scratch array.  No
+// device memory is allocated here.
+hipError_t setup_batched(lupp_handle_t h) {
+  LUPP_TRY(lookup_scratch(h->device));
+  BatchWs* w = new (std::nothrow) BatchWs();
+  if (!w) return hipErrorOutOfMemory;
+  h->batch = w;
+  for (int c = 0; c < kBatchClasses; ++c) {
+    LUPP_TRY(hipStreamCreateWithFlags(&w->streams[c], hipStreamNonBlocking));
+    LUPP_TRY(hipEventCreateWithFlags(&w->join[c], hipEventDisableTiming));
+  }
+  LUPP_TRY(hipEventCreateWithFlags(&w->fork, hipEventDisableTiming));
+  LUPP_TRY(setup_class_kernels<double>(h, w, 0));
+  LUPP_TRY(setup_class_kernels<float>(h, w, 1));
+  return hipSuccess;
+}
+
+namespace {
 
 template <typename T>
 int batched_entry(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_t* aoff, T* A,
@@ -632,6 +684,28 @@ int lupp_sgesv_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const 
 int lupp_dgetrf_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_t* dA_off, double* dA,
                         const int64_t* dipiv_off, int32_t* dipiv, int32_t* dinfo) {
   return lupp::batched_entry<double>(h, batch, dn, dA_off, dA, dipiv_off, dipiv, nullptr, nullptr, dinfo, false);
+}
+
+int lupp_dgesv_batched_noalloc(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_t* dA_off,
+                                double* dA, const int64_t* dipiv_off, int32_t* dipiv, const int64_t* dB_off,
+                                double* dB, int32_t* dinfo) {
+  if (!h) return -1;
+  if (batch < 0) return -2;
+  if (batch > lupp::kNoAllocMaxBatch) return LUPP_ERR_UNSUPPORTED;
+  if (batch == 0) return LUPP_OK;
+  if (!dn) return -3;
+  if (!dA_off) return -4;
+  if (!dA) return -5;
+  if (!dipiv_off) return -6;
+  if (!dipiv) return -7;
+  if (!dB_off) return -8;
+  if (!dB) return -9;
+  if (!dinfo) return -10;
+  if (!h->batch || h->device < 0 || h->device >= lupp::kMaxDevices) return LUPP_ERR_INTERNAL;
+  int32_t* list = lupp::g_scratch[h->device];
+  if (!list) return LUPP_ERR_INTERNAL;
+  return lupp::launch_batched<double>(h, batch, dn, dA_off, dA, dipiv_off, dipiv, dB_off, dB, dinfo, list,
+                                      list + lupp::kNoAllocMaxBatch);
 }
 
 int lupp_sgetrf_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_t* dA_off, float* dA,

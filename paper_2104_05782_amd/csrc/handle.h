@@ -91,6 +91,9 @@ hipError_t getrs(lupp_handle_t h, int64_t n, int64_t nrhs, const T* LU, int64_t 
                  int64_t ldb);
 void free_mixed(lupp_handle_t h);
 void free_batched(lupp_handle_t h);
+// Batched path set-up at handle creation: class streams and events, grids, and
+// the device address of the allocation-free entry point's scratch array.
+hipError_t setup_batched(lupp_handle_t h);
 
 }  // namespace lupp
 

@@ -564,9 +564,11 @@ int lupp_create(lupp_handle_t* h) {
   lupp_handle_st* p = new (std::nothrow) lupp_handle_st();
   if (!p) return LUPP_ERR_ALLOC;
   hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) e = lupp::setup_batched(p);
   if (e != hipSuccess) {
+    lupp::free_batched(p);
     delete p;
-    return lupp::hip_status(e);
+    return e == hipErrorOutOfMemory ? LUPP_ERR_ALLOC : lupp::hip_status(e);
   }
   *h = p;
   return LUPP_OK;
