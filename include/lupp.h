@@ -308,7 +308,8 @@ int lupp_dgesv_mixed(lupp_handle_t h, int64_t n, int64_t nrhs, const double* dA,
  * applies the same factorization (partial pivoting, LAPACK conventions, the
  * elimination step of Section 4.1 taken one column at a time) to a batch of
  * small systems at once, one workgroup per system with the system held in
- * registers.
+ * registers, scheduled by size class as the handle's schedule says
+ * (lupp_batched_set_schedule below).
  *
  *   batch       number of systems (>= 0)
  *   dn          device int32[batch]: order n_i of system i, 0 <= n_i <= 128
@@ -358,6 +359,45 @@ int lupp_sgesv_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const 
 int lupp_dgesv_batched_noalloc(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_t* dA_off,
                                double* dA, const int64_t* dipiv_off, int32_t* dipiv,
                                const int64_t* dB_off, double* dB, int32_t* dinfo);
+
+/*
+ * Schedules of the batched calls, and the autotuner that chooses them.
+ *
+ * The systems of a batched call are sorted into size classes by their order
+ * (class c holds the orders in (nmax[c-1], nmax[c]], nmax[-1] = 0); each class
+ * is one persistent launch of a kernel shape (wavefronts per system, rows per
+ * lane slot group, columns per wavefront) with a grid of grid_pct percent of
+ * the workgroups of that shape that fit on the device at once.  The classes
+ * run concurrently on streams of the handle.  Every shape computes the same
+ * factors, pivots and solutions bit for bit; schedules differ only in speed.
+ * Each handle holds one schedule for FP64 (fp32 = 0) and one for FP32
+ * (fp32 = 1), initially four classes (orders <= 32, 64, 96, 128).  The
+ * package's autotuner (paper_2104_05782_amd/autotune.py) chooses schedules by
+ * timing HIP-graph replays of the batched call over candidate class splits,
+ * shapes and grids, and keeps its choice per GPU architecture.
+ */
+#define LUPP_BATCH_MAX_CLASSES 6
+typedef struct lupp_batched_schedule {
+  int32_t nclass;                             /* 1 .. LUPP_BATCH_MAX_CLASSES       */
+  int32_t nmax[LUPP_BATCH_MAX_CLASSES];       /* increasing; nmax[nclass-1] = 128 */
+  int32_t shape[LUPP_BATCH_MAX_CLASSES];      /* 0 .. lupp_batched_shape_count()-1,
+                                                 holding orders up to nmax[c]    */
+  int32_t grid_pct[LUPP_BATCH_MAX_CLASSES];   /* 1 .. 100                         */
+} lupp_batched_schedule;
+
+/* Number of compiled kernel shapes, and shape v's geometry: wavefronts per
+ * system, row capacity (64 or 128), columns per wavefront, largest order it
+ * holds.  Host only.  lupp_batched_shape returns -1 for v out of range. */
+int lupp_batched_shape_count(void);
+int lupp_batched_shape(int32_t v, int32_t* nw, int32_t* rows, int32_t* cols, int32_t* nmax);
+
+/* The handle's schedule for FP64 (fp32 = 0) or FP32 (fp32 = 1).  set with
+ * s = NULL restores the initial schedule.  A schedule takes effect for calls
+ * made after it is set.  Errors: -2 fp32, -3 out NULL (get) or an invalid
+ * schedule (set: bounds not increasing or not ending at 128, a shape that
+ * cannot hold its class, grid_pct outside 1..100). */
+int lupp_batched_get_schedule(lupp_handle_t h, int32_t fp32, lupp_batched_schedule* out);
+int lupp_batched_set_schedule(lupp_handle_t h, int32_t fp32, const lupp_batched_schedule* s);
 
 /* Factorization only (no right-hand sides). */
 int lupp_dgetrf_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_t* dA_off,

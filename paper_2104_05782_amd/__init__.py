@@ -15,6 +15,8 @@ from ._binding import (  # noqa: F401
     IrOpts,
     IrReport,
     LuppError,
+    BatchedSchedule,
+    batched_shapes,
     Handle,
     colmajor,
     default_handle,

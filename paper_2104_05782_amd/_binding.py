@@ -68,6 +68,46 @@ for _name in ("lupp_dgesv_batched", "lupp_sgesv_batched", "lupp_dgesv_batched_no
 for _name in ("lupp_dgetrf_batched", "lupp_sgetrf_batched"):
     getattr(_lib, _name).argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]
 BATCH_MAX_N = 128
+BATCH_MAX_CLASSES = 6
+
+
+class BatchedSchedule(ctypes.Structure):
+    """lupp_batched_schedule."""
+    _fields_ = [("nclass", ctypes.c_int32), ("nmax", ctypes.c_int32 * BATCH_MAX_CLASSES),
+                ("shape", ctypes.c_int32 * BATCH_MAX_CLASSES), ("grid_pct", ctypes.c_int32 * BATCH_MAX_CLASSES)]
+
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_lib.lupp_batched_shape_count.argtypes = []
+_lib.lupp_batched_shape.argtypes = [ctypes.c_int32, _i32p, _i32p, _i32p, _i32p]
+_lib.lupp_batched_get_schedule.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(BatchedSchedule)]
+_lib.lupp_batched_set_schedule.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(BatchedSchedule)]
+
+
+def batched_shapes() -> list[dict]:
+    """The compiled kernel shapes of the batched path (host only)."""
+    out = []
+    for v in range(_lib.lupp_batched_shape_count()):
+        nw, rows, cols, nmax = (ctypes.c_int32() for _ in range(4))
+        _check(_lib.lupp_batched_shape(v, ctypes.byref(nw), ctypes.byref(rows), ctypes.byref(cols),
+                                       ctypes.byref(nmax)), "lupp_batched_shape")
+        out.append({"wavefronts": nw.value, "rows": rows.value, "cols": cols.value, "nmax": nmax.value})
+    return out
+
+
+def _sched_to_dict(s: BatchedSchedule) -> dict:
+    k = s.nclass
+    return {"nclass": k, "nmax": list(s.nmax[:k]), "shape": list(s.shape[:k]), "grid_pct": list(s.grid_pct[:k])}
+
+
+def _sched_from_dict(d: dict) -> BatchedSchedule:
+    s = BatchedSchedule()
+    s.nclass = int(d["nclass"])
+    for c in range(min(max(s.nclass, 0), BATCH_MAX_CLASSES)):  # the library validates nclass
+        s.nmax[c] = int(d["nmax"][c])
+        s.shape[c] = int(d["shape"][c])
+        s.grid_pct[c] = int(d["grid_pct"][c])
+    return s
 PHASES = {"panel": 0, "laswp": 1, "trsm": 2, "update": 3, "update_big": 4, "panel_leaf": 5, "panel_swap": 6,
           "panel_trsm": 7, "panel_gemm": 8}
 
@@ -90,11 +130,16 @@ def _check(rc: int, where: str):
 class Handle:
     """Owns a lupp handle (workspace) on the current device."""
 
-    def __init__(self):
+    def __init__(self, tuned: bool = True):
+        """tuned: install the cached batched schedules of this device's
+        architecture (paper_2104_05782_amd/autotune.py), if any."""
         p = _vp()
         _check(_lib.lupp_create(ctypes.byref(p)), "lupp_create")
         self._p = p
         self.device = torch.cuda.current_device()
+        if tuned:
+            from .autotune import apply_cached
+            apply_cached(self)
 
     @property
     def ptr(self):
@@ -119,6 +164,20 @@ class Handle:
     def inject_fault(self, what: int):
         """lupp_test_inject_fault (test hook of lupp_sync's error paths)."""
         _check(_lib.lupp_test_inject_fault(self._p, what), "lupp_test_inject_fault")
+
+    def batched_schedule(self, dtype: str) -> dict:
+        """The handle's batched schedule for "f64" or "f32"."""
+        s = BatchedSchedule()
+        _check(_lib.lupp_batched_get_schedule(self._p, int(dtype == "f32"), ctypes.byref(s)),
+               "lupp_batched_get_schedule")
+        return _sched_to_dict(s)
+
+    def set_batched_schedule(self, dtype: str, sched: dict | None):
+        """Install a schedule (dict as returned by batched_schedule); None
+        restores the initial one."""
+        s = _sched_from_dict(sched) if sched is not None else None
+        _check(_lib.lupp_batched_set_schedule(self._p, int(dtype == "f32"), ctypes.byref(s) if s else None),
+               "lupp_batched_set_schedule")
 
     def timing_summary(self, phase: str, reset: bool = False):
         """(count, ms, flops) recorded for a phase (see lupp_timing_summary)."""

@@ -9,25 +9,30 @@
 // substitution with U then gives x (skipped, as in LAPACK's gesv, when a
 // pivot is exactly zero).
 //
-// Scheduling: a binning kernel sorts the systems into four size classes
-// (n <= 32, 64, 96, 128), each served by one persistent launch whose
-// workgroups (1, 2 in FP64 or 1 in FP32, 4, 4 wavefronts) take the class's
-// systems in round robin (no shared counter: thousands of workgroups
-// contending for one global atomic cost more than the small systems
-// themselves).  A
-// CU's register file (512 KB) holds several systems of every class, where its
-// LDS (160 KB) would hold one of the largest.  The classes are launched on
-// four streams so that the short classes fill the CUs the long ones leave
-// idle.  No host synchronization or allocation happens per call
+// Scheduling: a binning kernel sorts the systems into size classes (up to
+// six, by upper bounds on n), each served by one persistent launch of a
+// kernel shape (wavefronts per system, row slots per lane, columns per
+// wavefront) whose workgroups take the class's systems in round robin (no
+// shared counter: thousands of workgroups contending for one global atomic
+// cost more than the small systems themselves).  A CU's register file
+// (512 KB) holds several systems of every class, where its LDS (160 KB) would
+// hold one of the largest.  The classes are launched on their own streams so
+// that the short classes fill the CUs the long ones leave idle (measured: one
+// launch of the largest shape for the whole batch takes 1.5x the time of the
+// per-class launches).  The class bounds, the shape of each class and its grid
+// form the handle's schedule, which the package's autotuner chooses by timing
+// graph replays of this call; the default is four classes (n <= 32, 64, 96,
+// 128).  No host synchronization or allocation happens per call
 // (graph-capturable once the workspace exists for the batch size).
 #include <mutex>
+#include <utility>
 
 #include "handle.h"
 #include "wave.h"
 
 namespace lupp {
 
-constexpr int kBatchClasses = 4;
+constexpr int kMaxClasses = 6;
 constexpr int kBatchMaxN = 128;
 // Bound on a wavefront's wait for a published step (iterations of a ~64-cycle
 // sleep, about 0.1 s): a wait that long means a fault in the schedule, and the
@@ -35,41 +40,75 @@ constexpr int kBatchMaxN = 128;
 constexpr int kSpinLimit = 1 << 22;
 constexpr int kStalled = -1000;
 
+// Kernel shapes: NW wavefronts per system, R row slots per lane (rows l and
+// l + 64), C columns per wavefront; a shape holds orders up to
+// min(64 R, NW C - 1) (b is one more column).
+struct Shape {
+  int nw, r, c;
+};
+constexpr Shape kShapes[] = {{1, 1, 17}, {1, 1, 33}, {2, 1, 33}, {1, 1, 65}, {4, 1, 17},
+                             {4, 2, 25}, {2, 2, 49}, {8, 2, 13}, {4, 2, 33}, {8, 2, 17}};
+constexpr int kNumShapes = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
+constexpr int shape_nmax(int v) {
+  return 64 * kShapes[v].r < kShapes[v].nw * kShapes[v].c - 1 ? 64 * kShapes[v].r : kShapes[v].nw * kShapes[v].c - 1;
+}
+
+// Schedule of one precision: class c holds the orders in (ub[c-1], ub[c]].
+struct Schedule {
+  int nclass = 0;
+  int ub[kMaxClasses] = {};
+  int shape[kMaxClasses] = {};
+  int grid_pct[kMaxClasses] = {};
+};
+
 // Workspace of the batched path: per-class system lists and counters.
 struct BatchWs {
   int64_t capacity = 0;
   int32_t* list = nullptr;  // capacity entries: system ids grouped by class
-  int32_t* meta = nullptr;  // [0,4) counts, [4,8) offsets
-  hipStream_t streams[kBatchClasses] = {};
-  hipEvent_t fork = nullptr, join[kBatchClasses] = {};
-  int grid[2][kBatchClasses] = {};  // persistent grid per (precision, class)
+  int32_t* meta = nullptr;  // [0, kMaxClasses) counts, [kMaxClasses, 2 kMaxClasses) offsets
+  hipStream_t streams[kMaxClasses] = {};
+  hipEvent_t fork = nullptr, join[kMaxClasses] = {};
+  int occ[2][kNumShapes] = {};  // resident workgroups per device, per (precision, shape)
+  Schedule sched[2];            // FP64, FP32
+};
+
+// Class bounds as a kernel argument.
+struct ClassBounds {
+  int nclass;
+  int ub[kMaxClasses];
 };
 
 namespace {
 
-__device__ __forceinline__ int size_class(int n) { return n <= 32 ? 0 : (n <= 64 ? 1 : (n <= 96 ? 2 : 3)); }
+__device__ __forceinline__ int size_class(int n, const ClassBounds& cb) {
+  int c = 0;
+#pragma unroll
+  for (int q = 0; q < kMaxClasses - 1; ++q)
+    if (q < cb.nclass - 1 && n > cb.ub[q]) c = q + 1;
+  return c;
+}
 
 // Sort systems into size classes.  One workgroup; the
 // counters are updated once per wavefront and class (ballot + popcount), not
 // once per system.
 __global__ __launch_bounds__(1024) void k_batch_bin(int32_t batch, const int32_t* __restrict__ dn,
                                                     int32_t* __restrict__ list, int32_t* __restrict__ meta,
-                                                    int32_t* __restrict__ info) {
-  __shared__ int cnt[kBatchClasses], cur[kBatchClasses], off[kBatchClasses];
+                                                    int32_t* __restrict__ info, ClassBounds cb) {
+  __shared__ int cnt[kMaxClasses], cur[kMaxClasses], off[kMaxClasses];
   const int tid = threadIdx.x, lane = tid & 63;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  if (tid < kBatchClasses) cnt[tid] = 0;
+  if (tid < kMaxClasses) cnt[tid] = 0;
   __syncthreads();
   for (int base = 0; base < batch; base += 1024) {
     const int i = base + tid;
     int c = -1;
     if (i < batch) {
       const int n = dn[i];
-      if (n >= 1 && n <= kBatchMaxN) c = size_class(n);
+      if (n >= 1 && n <= kBatchMaxN) c = size_class(n, cb);
       else info[i] = (n == 0) ? 0 : -1;  // empty system: nothing to do; bad order: rejected
     }
 #pragma unroll
-    for (int q = 0; q < kBatchClasses; ++q) {
+    for (int q = 0; q < kMaxClasses; ++q) {
       const uint64_t b = __ballot(c == q);
       if (lane == 0 && b) atomicAdd(&cnt[q], __popcll(b));
     }
@@ -77,11 +116,11 @@ __global__ __launch_bounds__(1024) void k_batch_bin(int32_t batch, const int32_t
   __syncthreads();
   if (tid == 0) {
     int o = 0;
-    for (int c = 0; c < kBatchClasses; ++c) {
+    for (int c = 0; c < kMaxClasses; ++c) {
       off[c] = o;
       cur[c] = 0;
       meta[c] = cnt[c];
-      meta[4 + c] = o;
+      meta[kMaxClasses + c] = o;
       o += cnt[c];
     }
   }
@@ -91,10 +130,10 @@ __global__ __launch_bounds__(1024) void k_batch_bin(int32_t batch, const int32_t
     int c = -1;
     if (i < batch) {
       const int n = dn[i];
-      if (n >= 1 && n <= kBatchMaxN) c = size_class(n);
+      if (n >= 1 && n <= kBatchMaxN) c = size_class(n, cb);
     }
 #pragma unroll
-    for (int q = 0; q < kBatchClasses; ++q) {
+    for (int q = 0; q < kMaxClasses; ++q) {
       const uint64_t b = __ballot(c == q);
       if (!b) continue;
       int at = 0;
@@ -203,7 +242,7 @@ __global__ __launch_bounds__(64 * NW, (kMinWaves<R, C>)) void k_batch_lu(int cls
   // step k + kRing, published by its owner only after every wavefront has
   // published a later step than k (each owns one of any NW consecutive
   // steps), hence has read slot k; kRing >= NW + 1 suffices.
-  constexpr int kRing = 8;
+  constexpr int kRing = NW < 8 ? 8 : 16;
   static_assert(kRing >= NW + 1, "ring of published steps too short");
   __shared__ T s_l[kRing][64 * R];  // multipliers
   __shared__ int s_pp[kRing][4];    // pivot slot, pivot's logical row, pivot nonzero
@@ -212,7 +251,7 @@ __global__ __launch_bounds__(64 * NW, (kMinWaves<R, C>)) void k_batch_lu(int cls
   __shared__ int s_info;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int count = meta[cls], first = meta[4 + cls];
+  const int count = meta[cls], first = meta[kMaxClasses + cls];
 
   // systems of the class in round robin over the persistent workgroups
   for (int q = blockIdx.x; q < count; q += gridDim.x) {
@@ -486,33 +525,58 @@ __global__ __launch_bounds__(64 * NW, (kMinWaves<R, C>)) void k_batch_lu(int cls
   }
 }
 
-// size classes: (wavefronts, row slots per lane, columns per wavefront)
-template <typename T>
-const void* batch_kernel(int cls) {
-  switch (cls) {
-    case 0: return (const void*)k_batch_lu<T, 1, 1, 33>;
-    case 1:  // one wavefront in FP32; in FP64 its 163 VGPRs pack worse beside the other classes
-      if constexpr (sizeof(T) == 4) return (const void*)k_batch_lu<T, 1, 1, 65>;
-      return (const void*)k_batch_lu<T, 2, 1, 33>;
-    case 2: return (const void*)k_batch_lu<T, 4, 2, 25>;
-    default: return (const void*)k_batch_lu<T, 4, 2, 33>;
-  }
+template <typename T, int V>
+constexpr const void* shape_kernel_of() {
+  return (const void*)k_batch_lu<T, kShapes[V].nw, kShapes[V].r, kShapes[V].c>;
+}
+template <typename T, int... V>
+const void* shape_kernel_at(int v, std::integer_sequence<int, V...>) {
+  const void* table[] = {shape_kernel_of<T, V>()...};
+  return table[v];
 }
 template <typename T>
-int class_threads(int cls) {
-  return cls == 0 ? 64 : (cls == 1 ? (sizeof(T) == 4 ? 64 : 128) : 256);
+const void* shape_kernel(int v) {
+  return shape_kernel_at<T>(v, std::make_integer_sequence<int, kNumShapes>());
+}
+inline int shape_threads(int v) { return 64 * kShapes[v].nw; }
+
+// The default schedule (four classes; measured by hand before the sweep
+// existed): FP64 1x33, 2x33, 4x(2x25), 4x(2x33); FP32 the same with one
+// wavefront of 65 columns for n <= 64.
+Schedule default_schedule(int prec) {
+  Schedule d;
+  d.nclass = 4;
+  const int ub[4] = {32, 64, 96, 128};
+  const int sh[2][4] = {{1, 2, 5, 8}, {1, 3, 5, 8}};
+  for (int c = 0; c < 4; ++c) {
+    d.ub[c] = ub[c];
+    d.shape[c] = sh[prec][c];
+    d.grid_pct[c] = 100;
+  }
+  return d;
+}
+
+bool schedule_valid(const Schedule& s) {
+  if (s.nclass < 1 || s.nclass > kMaxClasses) return false;
+  int prev = 0;
+  for (int c = 0; c < s.nclass; ++c) {
+    if (s.ub[c] <= prev || s.ub[c] > kBatchMaxN) return false;
+    if (s.shape[c] < 0 || s.shape[c] >= kNumShapes || shape_nmax(s.shape[c]) < s.ub[c]) return false;
+    if (s.grid_pct[c] < 1 || s.grid_pct[c] > 100) return false;
+    prev = s.ub[c];
+  }
+  return s.ub[s.nclass - 1] == kBatchMaxN;
 }
 
 template <typename T>
-hipError_t setup_class_kernels(lupp_handle_t h, BatchWs* w, int prec) {
+hipError_t setup_shape_occupancy(lupp_handle_t h, BatchWs* w, int prec) {
   int ncu = 0;
   LUPP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
-  for (int c = 0; c < kBatchClasses; ++c) {
-    const void* f = batch_kernel<T>(c);
+  for (int v = 0; v < kNumShapes; ++v) {
     int occ = 0;
-    LUPP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, class_threads<T>(c), 0));
+    LUPP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, shape_kernel<T>(v), shape_threads(v), 0));
     if (occ < 1) return hipErrorInvalidConfiguration;
-    w->grid[prec][c] = occ * ncu;
+    w->occ[prec][v] = occ * ncu;
   }
   return hipSuccess;
 }
@@ -522,7 +586,7 @@ hipError_t setup_class_kernels(lupp_handle_t h, BatchWs* w, int prec) {
 void free_batched(lupp_handle_t h) {
   BatchWs* w = h->batch;
   if (!w) return;
-  for (int c = 0; c < kBatchClasses; ++c) {
+  for (int c = 0; c < kMaxClasses; ++c) {
     if (w->streams[c]) (void)hipStreamSynchronize(w->streams[c]);
     if (w->join[c]) (void)hipEventDestroy(w->join[c]);
     if (w->streams[c]) (void)hipStreamDestroy(w->streams[c]);
@@ -544,7 +608,7 @@ namespace {
 // array's name to a kernel: it uses the device address looked up once per
 // device at handle creation (g_scratch).
 constexpr int64_t kNoAllocMaxBatch = 1 << 20;
-constexpr int kScratchMeta = 64;  // ints after the list: meta[0, 8), padded to 256 bytes
+constexpr int kScratchMeta = 64;  // ints after the list: meta[0, 2 kMaxClasses), padded to 256 bytes
 __device__ __align__(256) int32_t scratch[kNoAllocMaxBatch + kScratchMeta];
 
 constexpr int kMaxDevices = 64;
@@ -571,7 +635,7 @@ hipError_t ensure_batch_list(lupp_handle_t h, int64_t batch) {
   if (!w) return hipErrorNotInitialized;
   if (batch <= w->capacity && w->list) return hipSuccess;
   LUPP_TRY(hipStreamSynchronize(h->stream));
-  for (int c = 0; c < kBatchClasses; ++c) LUPP_TRY(hipStreamSynchronize(w->streams[c]));
+  for (int c = 0; c < kMaxClasses; ++c) LUPP_TRY(hipStreamSynchronize(w->streams[c]));
   if (w->list) (void)hipFree(w->list);
   w->list = nullptr;
   w->capacity = 0;
@@ -593,24 +657,31 @@ int launch_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int6
   BatchWs* w = h->batch;
   hipStream_t s = h->stream;
   const int prec = sizeof(T) == 8 ? 0 : 1;
-  hipLaunchKernelGGL(k_batch_bin, dim3(1), dim3(1024), 0, s, batch, dn, list, meta, info);
+  const Schedule& sc = w->sched[prec];
+  ClassBounds cb{};
+  cb.nclass = sc.nclass;
+  for (int c = 0; c < kMaxClasses; ++c) cb.ub[c] = c < sc.nclass ? sc.ub[c] : kBatchMaxN;
+  hipLaunchKernelGGL(k_batch_bin, dim3(1), dim3(1024), 0, s, batch, dn, list, meta, info, cb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_status(e);
   e = hipEventRecord(w->fork, s);
   if (e != hipSuccess) return hip_status(e);
   // largest class first: it holds most of the work
-  for (int c = kBatchClasses - 1; c >= 0; --c) {
-    hipStream_t sc = w->streams[c];
-    e = hipStreamWaitEvent(sc, w->fork, 0);
+  for (int c = sc.nclass - 1; c >= 0; --c) {
+    hipStream_t st = w->streams[c];
+    e = hipStreamWaitEvent(st, w->fork, 0);
     if (e != hipSuccess) return hip_status(e);
-    const void* f = batch_kernel<T>(c);
+    const int v = sc.shape[c];
+    const void* f = shape_kernel<T>(v);
     const int32_t* cmeta = meta;
     const int32_t* clist = list;
     void* args[] = {(void*)&c, (void*)&dn, (void*)&aoff, (void*)&A, (void*)&poff, (void*)&piv, (void*)&boff,
                     (void*)&B, (void*)&info, (void*)&clist, (void*)&cmeta};
-    e = hipLaunchKernel(f, dim3(w->grid[prec][c]), dim3(class_threads<T>(c)), args, 0, sc);
+    int grid = (int)((int64_t)w->occ[prec][v] * sc.grid_pct[c] / 100);
+    if (grid < 1) grid = 1;
+    e = hipLaunchKernel(f, dim3(grid), dim3(shape_threads(v)), args, 0, st);
     if (e != hipSuccess) return hip_status(e);
-    e = hipEventRecord(w->join[c], sc);
+    e = hipEventRecord(w->join[c], st);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, w->join[c], 0);
     if (e != hipSuccess) return hip_status(e);
   }
@@ -635,13 +706,15 @@ hipError_t setup_batched(lupp_handle_t h) {
   BatchWs* w = new (std::nothrow) BatchWs();
   if (!w) return hipErrorOutOfMemory;
   h->batch = w;
-  for (int c = 0; c < kBatchClasses; ++c) {
+  for (int c = 0; c < kMaxClasses; ++c) {
     LUPP_TRY(hipStreamCreateWithFlags(&w->streams[c], hipStreamNonBlocking));
     LUPP_TRY(hipEventCreateWithFlags(&w->join[c], hipEventDisableTiming));
   }
   LUPP_TRY(hipEventCreateWithFlags(&w->fork, hipEventDisableTiming));
-  LUPP_TRY(setup_class_kernels<double>(h, w, 0));
-  LUPP_TRY(setup_class_kernels<float>(h, w, 1));
+  LUPP_TRY(setup_shape_occupancy<double>(h, w, 0));
+  LUPP_TRY(setup_shape_occupancy<float>(h, w, 1));
+  w->sched[0] = default_schedule(0);
+  w->sched[1] = default_schedule(1);
   return hipSuccess;
 }
 
@@ -668,6 +741,59 @@ int batched_entry(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64
 }  // namespace lupp
 
 extern "C" {
+
+int lupp_batched_shape(int32_t v, int32_t* nw, int32_t* rows, int32_t* cols, int32_t* nmax) {
+  if (v < 0 || v >= lupp::kNumShapes) return -1;
+  if (nw) *nw = lupp::kShapes[v].nw;
+  if (rows) *rows = 64 * lupp::kShapes[v].r;
+  if (cols) *cols = lupp::kShapes[v].c;
+  if (nmax) *nmax = lupp::shape_nmax(v);
+  return LUPP_OK;
+}
+
+int lupp_batched_shape_count(void) { return lupp::kNumShapes; }
+
+namespace {
+void to_c(const lupp::Schedule& s, lupp_batched_schedule* o) {
+  *o = lupp_batched_schedule{};
+  o->nclass = s.nclass;
+  for (int c = 0; c < s.nclass; ++c) {
+    o->nmax[c] = s.ub[c];
+    o->shape[c] = s.shape[c];
+    o->grid_pct[c] = s.grid_pct[c];
+  }
+}
+}  // namespace
+
+int lupp_batched_get_schedule(lupp_handle_t h, int32_t fp32, lupp_batched_schedule* out) {
+  if (!h) return -1;
+  if (fp32 != 0 && fp32 != 1) return -2;
+  if (!out) return -3;
+  if (!h->batch) return LUPP_ERR_INTERNAL;
+  to_c(h->batch->sched[fp32], out);
+  return LUPP_OK;
+}
+
+int lupp_batched_set_schedule(lupp_handle_t h, int32_t fp32, const lupp_batched_schedule* s) {
+  if (!h) return -1;
+  if (fp32 != 0 && fp32 != 1) return -2;
+  if (!h->batch) return LUPP_ERR_INTERNAL;
+  if (!s) {
+    h->batch->sched[fp32] = lupp::default_schedule(fp32);
+    return LUPP_OK;
+  }
+  lupp::Schedule t;
+  t.nclass = s->nclass;
+  if (t.nclass < 1 || t.nclass > lupp::kMaxClasses) return -3;
+  for (int c = 0; c < t.nclass; ++c) {
+    t.ub[c] = s->nmax[c];
+    t.shape[c] = s->shape[c];
+    t.grid_pct[c] = s->grid_pct[c];
+  }
+  if (!lupp::schedule_valid(t)) return -3;
+  h->batch->sched[fp32] = t;
+  return LUPP_OK;
+}
 
 int lupp_dgesv_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_t* dA_off, double* dA,
                        const int64_t* dipiv_off, int32_t* dipiv, const int64_t* dB_off, double* dB,
