@@ -15,7 +15,9 @@ The JSON line carries:
               flops 2*M*N*K summed over its launches in the timed steps,
               divided by the summed launch durations from HIP events recorded
               on the library's stream, against MI355X's FP64 MFMA peak; traffic
-              from the committed counter summary (labelled with its n)
+              = the HBM/algorithmic byte ratio from the committed counter summary
+              (measured at n = 24576, labelled) times this run's algorithmic
+              bytes per launch
   cpu_baseline  the CPU oracle (unblocked FP64 LUPP) on the host cores: n = 512
               (median of 3) and n = 4096, each with 1 thread and with all cores,
               the input copy outside the timer; value = all cores at n = 4096.
@@ -67,6 +69,7 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+TRAFFIC_RATIO_FP64_GEMM = 1.729  # HBM bytes / algorithmic bytes, k_dgemm_sub_16 role 0, n = 24576 counters
 
 
 def log(msg):
@@ -678,11 +681,22 @@ def main():
     for ph in ("panel", "laswp", "trsm", "update", "update_big", "panel_leaf", "panel_swap", "panel_trsm", "panel_gemm"):
         c, ms, fl = h.timing_summary(ph)
         phases[ph] = {"launches": c, "ms_per_step": ms / args.steps, "flops": fl / args.steps}
+    alg_bytes = h.timing_bytes("update_big")
     c, ms, fl = h.timing_summary("update_big", reset=True)
     peak = FP64_PEAK_TFLOPS if args.dtype == "f64" else FP32_PEAK_TFLOPS
     achieved = (fl / (ms * 1e-3) / 1e12) if ms > 0 else 0.0
+    # HBM traffic of this kernel: the calibrated FETCH_SIZE + WRITE_SIZE of its
+    # launches over their algorithmic bytes, 1.729 at n = 24576 (the largest
+    # size at which the profiler's counter mode has run; profiles/
+    # lupp_n24576_counters.md), applied to this run's algorithmic bytes per launch
+    traffic = None
+    if args.dtype == "f64" and c > 0:
+        traffic = round(TRAFFIC_RATIO_FP64_GEMM * alg_bytes / c, 1)
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
+                "frac": round(achieved / peak, 4), "traffic": traffic,
+                "traffic_note": ("bytes per launch: %.3f x the algorithmic bytes (C read and written, A and B read once; "
+                                 "%.4g per launch here), the ratio measured at n = 24576" %
+                                 (TRAFFIC_RATIO_FP64_GEMM, alg_bytes / max(1, c))) if traffic else None,
                 "kernel": ("k_dgemm_sub_16<128,128,8,2,2,2,0>" if args.dtype == "f64" else "k_gemm_sub<float,128,128,16,2,2,2>"),
                 "launches_per_step": c // max(1, args.steps),
                 "avg_launch_ms": round(ms / max(1, c), 4),

@@ -171,6 +171,12 @@ int lupp_test_inject_fault(lupp_handle_t h, int what);
  * Errors: -2 unknown phase, -3/-4/-5 NULL output. */
 int lupp_timing_summary(lupp_handle_t h, int phase, int64_t* count, double* ms, double* flops, int reset);
 
+/* Instrumentation: the summed algorithmic bytes of the intervals recorded for
+ * a phase since the last reset (the updates: C read and written once, A and B
+ * read once; 0 for phases without such a count).  Host only; call before the
+ * lupp_timing_summary that resets.  Errors: -2 unknown phase, -3 NULL. */
+int lupp_timing_bytes(lupp_handle_t h, int phase, double* bytes);
+
 /* Human-readable text for a return code (static storage). */
 const char* lupp_status_string(int status);
 

@@ -20,6 +20,7 @@ _lib.lupp_set_option.argtypes = [_vp, _i32, _i64]
 _lib.lupp_sync.argtypes = [_vp]
 _lib.lupp_timing_summary.argtypes = [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double), _i32]
+_lib.lupp_timing_bytes.argtypes = [_vp, _i32, ctypes.POINTER(ctypes.c_double)]
 _lib.lupp_workspace_bytes.argtypes = [_vp, _i32, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)]
 _lib.lupp_test_inject_fault.argtypes = [_vp, _i32]
 _lib.lupp_status_string.argtypes = [_i32]
@@ -178,6 +179,12 @@ class Handle:
         s = _sched_from_dict(sched) if sched is not None else None
         _check(_lib.lupp_batched_set_schedule(self._p, int(dtype == "f32"), ctypes.byref(s) if s else None),
                "lupp_batched_set_schedule")
+
+    def timing_bytes(self, phase: str) -> float:
+        """Summed algorithmic bytes recorded for a phase (lupp_timing_bytes)."""
+        b = ctypes.c_double()
+        _check(_lib.lupp_timing_bytes(self._p, PHASES[phase], ctypes.byref(b)), "lupp_timing_bytes")
+        return b.value
 
     def timing_summary(self, phase: str, reset: bool = False):
         """(count, ms, flops) recorded for a phase (see lupp_timing_summary)."""

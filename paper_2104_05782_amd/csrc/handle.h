@@ -11,6 +11,7 @@ struct TimingRecord {
   int phase = 0;
   bool big = false;
   double flops = 0.0;
+  double bytes = 0.0;  // algorithmic bytes (updates: C read and written, A and B read once)
 };
 struct MixedWs;
 struct BatchWs;

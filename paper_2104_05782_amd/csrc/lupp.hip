@@ -56,15 +56,24 @@ int timer_begin(lupp_handle_t h, int phase, hipStream_t st) {
   r.phase = phase;
   r.big = false;
   r.flops = 0.0;
+  r.bytes = 0.0;
   return (int)h->nrecords++;
 }
 
-void timer_end(lupp_handle_t h, int idx, hipStream_t st, double flops, bool big = false) {
+void timer_end(lupp_handle_t h, int idx, hipStream_t st, double flops, bool big = false, double bytes = 0.0) {
   if (idx < 0) return;
   TimingRecord& r = h->records[idx];
   r.flops = flops;
+  r.bytes = bytes;
   r.big = big;
   (void)hipEventRecord(r.stop, st);
+}
+
+// Algorithmic bytes of an update C (M x N) -= A (M x K) * B (K x N): C read
+// and written once, A and B read once.
+template <typename T>
+double update_bytes(int64_t M, int64_t N, int64_t K) {
+  return (double)sizeof(T) * (2.0 * (double)M * (double)N + ((double)M + (double)N) * (double)K);
 }
 
 // B (w x ncols) := inv(L) * B with L unit lower triangular (w x w).
@@ -241,7 +250,7 @@ hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32
       t = timer_begin(h, LUPP_PHASE_UPDATE, s);
       LUPP_TRY(update<T>(h, s, 0, mr, n1, b, A + kn + k * lda, lda, A + k + kn * lda, lda, A + kn + kn * lda, lda,
                          &tile));
-      timer_end(h, t, s, 2.0 * (double)mr * (double)n1 * (double)b, tile == 1);
+      timer_end(h, t, s, 2.0 * (double)mr * (double)n1 * (double)b, tile == 1, update_bytes<T>(mr, n1, b));
     }
     // overlap only when the next block's cooperative factorization fits in
     // the reserved CUs (one workgroup per CU at most)
@@ -290,7 +299,7 @@ hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32
         t = timer_begin(h, LUPP_PHASE_UPDATE, su);
         LUPP_TRY(update<T>(h, su, 1, mr, nbulk, b, A + kn + k * lda, lda, A + k + c1 * lda, lda, A + kn + c1 * lda,
                            lda, &tile));
-        timer_end(h, t, su, 2.0 * (double)mr * (double)nbulk * (double)b, tile == 1);
+        timer_end(h, t, su, 2.0 * (double)mr * (double)nbulk * (double)b, tile == 1, update_bytes<T>(mr, nbulk, b));
         if (slot >= 0) {
           LUPP_TRY(hipEventRecord(h->tm_ev[slot][3], su));
           h->tm_flops[slot] = 2.0 * (double)mr * (double)nbulk * (double)b;
@@ -303,7 +312,7 @@ hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32
           t = timer_begin(h, LUPP_PHASE_UPDATE, sside);
           LUPP_TRY(update<T>(h, sside, 2, mr, nside, b, A + kn + k * lda, lda, A + k + c2 * lda, lda,
                              A + kn + c2 * lda, lda));
-          timer_end(h, t, sside, 2.0 * (double)mr * (double)nside * (double)b);
+          timer_end(h, t, sside, 2.0 * (double)mr * (double)nside * (double)b, false, update_bytes<T>(mr, nside, b));
         }
       }
     }
@@ -753,6 +762,19 @@ int lupp_timing_summary(lupp_handle_t h, int phase, int64_t* count, double* ms, 
     *flops += r.flops;
   }
   if (reset) h->nrecords = 0;
+  return LUPP_OK;
+}
+
+int lupp_timing_bytes(lupp_handle_t h, int phase, double* bytes) {
+  if (!h) return -1;
+  if (phase < LUPP_PHASE_PANEL || phase > LUPP_PHASE_PANEL_GEMM) return -2;
+  if (!bytes) return -3;
+  *bytes = 0.0;
+  for (size_t i = 0; i < h->nrecords; ++i) {
+    const lupp::TimingRecord& r = h->records[i];
+    const bool match = (phase == LUPP_PHASE_UPDATE_BIG) ? (r.phase == LUPP_PHASE_UPDATE && r.big) : (r.phase == phase);
+    if (match) *bytes += r.bytes;
+  }
   return LUPP_OK;
 }
 
