@@ -49,6 +49,9 @@ The JSON line carries:
               written, pivots written, sizes and offsets read); the size-class
               schedule is the one the library's autotuner chooses live on this
               GPU (recorded, with the initial schedule's time for comparison)
+  dataflow    the headline factorization by the dataflow (algorithm-by-blocks)
+              runtime at lookahead depth 2 and 4: time, pivots against the
+              headline run's
   large       n = 65536 (diagonally dominant recipe drawn on the device): plain FP64
               factorization + solve against the FP8-update GMRES-IR solve (wall
               times, effective TFLOP/s, backward errors, forward error against
@@ -405,6 +408,37 @@ def kappa_leg(torch, lupp, systems, x_true, refs):
             "runs": res}
 
 
+def dataflow_leg(torch, lupp, A0, A, fn, ref_ipiv, nb, depths=(2, 4)):
+    """The same factorization by the dataflow (algorithm-by-blocks) runtime,
+    lookahead depth d: one untimed and one timed call per depth; pivots
+    compared with the headline run's."""
+    n = A0.shape[0]
+    runs = []
+    for d in depths:
+        hd = lupp.Handle()
+        hd.set_option(4, d)
+        if nb:
+            hd.set_option(1, nb)
+        ipd = torch.empty_like(ref_ipiv)
+        infd = torch.empty(1, dtype=torch.int32, device="cuda")
+        ms = None
+        for r in range(2):
+            A.copy_(A0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn(A, ipd, infd, handle=hd)
+            hd.sync()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+        hd.close()
+        runs.append({"depth": d, "ms": round(ms, 3), "tflops": round(2.0 / 3.0 * n ** 3 / (ms * 1e-3) / 1e12, 3),
+                     "info": int(infd.item()), "ipiv_equal_to_headline": bool(torch.equal(ipd, ref_ipiv))})
+    out = {"workload": "the headline factorization (n=%d) by the dataflow runtime, lookahead depth d "
+                       "(one call after one untimed call, input restored outside the timer)" % n, "runs": runs}
+    log("dataflow: %s" % out)
+    return out
+
+
 def large_leg(torch, lupp, n, seed):
     """FP8-update GMRES-IR solve against plain FP64 LUPP + solve at a large n,
     on the diagonally dominant recipe drawn on the device (torch's seeded
@@ -591,6 +625,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solve leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched small-systems leg")
     ap.add_argument("--no-large", action="store_true", help="skip the large mixed-precision leg")
+    ap.add_argument("--no-dataflow", action="store_true", help="skip the dataflow-runtime leg")
     ap.add_argument("--no-c2", action="store_true", help="skip the FP64/FP32 size sweep")
     ap.add_argument("--no-kappa", action="store_true", help="skip the kappa (n=4096) mixed-precision leg")
     ap.add_argument("--large-n", type=int, default=65536)
@@ -703,6 +738,10 @@ def main():
                 "flops_per_launch": fl / max(1, c)}
     h.set_option(3, 0)
 
+    dataflow = None
+    if not args.no_dataflow and not args.profile_once:
+        dataflow = dataflow_leg(torch, lupp, A0, A, fn, ipiv.clone(), args.nb)
+
     check = None
     if not args.no_check:
         inf = int(info.item())
@@ -791,6 +830,7 @@ def main():
         "mixed": mixed,
         "batched": batched,
         "large": large,
+        "dataflow": dataflow,
     }
     print(json.dumps(out), flush=True)
     h.close()

@@ -61,8 +61,17 @@ enum {
                               (16 .. 256, a multiple of 16; default 128); wider blocks
                               split recursively with a triangular solve and a GEMM      */
   LUPP_OPT_TIMING = 3,     /* 1: record HIP events around every phase of xGETRF (below)    */
-  LUPP_OPT_LOOKAHEAD = 4,  /* 1 (default): factor the next column block on a second stream
-                              while the trailing update runs; 0: one stream, in order      */
+  LUPP_OPT_LOOKAHEAD = 4,  /* lookahead depth d (0..16).  1 (default): factor the next
+                              column block on a second stream while the trailing update
+                              runs; 0: one stream, in order.  d >= 2: the dataflow
+                              (algorithm-by-blocks) runtime: the loop becomes tasks on
+                              column blocks whose dependencies are derived from the blocks
+                              each task reads and writes, issued onto CU-partitioned
+                              streams with event waits, the column-block chain free to run
+                              up to d steps ahead of the large updates (the paper's
+                              Sections 4.1 and 4.4).  Factors and pivots are identical for
+                              every d.  d >= 2 needs the deferred interchanges (below);
+                              where they do not apply, d = 1 is used                       */
   LUPP_OPT_UPDATE_PREC = 5, /* lupp_sgetrf only: format of the operands of the trailing
                               update A22 -= A21*U12, one of LUPP_PREC_* (default FP32).  The
                               column-block factorization and U12 stay FP32; the products are

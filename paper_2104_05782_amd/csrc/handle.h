@@ -39,6 +39,8 @@ struct lupp_handle_st {
   int panel_cus = 0;                // CUs reserved for the panel while they overlap
   hipStream_t side2 = nullptr;      // the same pair for panels of up to 64 workgroups
   hipStream_t bulk2 = nullptr;
+  hipStream_t look = nullptr;       // lookahead updates of the dataflow runtime, on the bulk CUs
+  hipStream_t look2 = nullptr;      // the same beside the 64-CU panel stream
   int panel_cus2 = 0;
   int ncu = 0;                      // compute units of the device
   hipEvent_t ev_cols = nullptr;     // next block's columns updated (main -> side, bulk)
@@ -59,6 +61,7 @@ struct lupp_handle_st {
   int update_prec = 0;              // LUPP_PREC_* of sgetrf's trailing update
   int* lp_scale[3] = {nullptr, nullptr, nullptr};  // block exponents: next-block, bulk and side updates
   int64_t lp_scale_cap = 0;         // ints in each of lp_scale[0..2]
+  std::vector<hipEvent_t> dag_events;  // task completion events of the dataflow runtime (reused)
   lupp::TrsvState trsv{};           // one-launch triangular solve state (flags on demand)
   lupp::MixedWs* mixed = nullptr;   // workspace of lupp_dgesv_mixed
   lupp::BatchWs* batch = nullptr;   // workspace and streams of the batched path

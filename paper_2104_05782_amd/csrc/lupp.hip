@@ -19,6 +19,8 @@
 #include <type_traits>
 #include <vector>
 
+#include <algorithm>
+
 #include "handle.h"
 
 namespace lupp {
@@ -208,10 +210,18 @@ hipError_t factor_block(lupp_handle_t h, hipStream_t st, int64_t m, int64_t k, i
 // algorithm-by-blocks; Section 4.4, the runtime's dataflow order); here the
 // dataflow is fixed and expressed with two streams and two events per step.
 template <typename T>
+hipError_t getrf_dag(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32_t* ipiv, int32_t* info,
+                     int depth);
+
+template <typename T>
 hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32_t* ipiv, int32_t* info) {
   hipStream_t s = h->stream;
-  LUPP_TRY(set_int(s, info, 0));
   const int64_t p = m < n ? m : n;
+  // lookahead deeper than one step: the dataflow runtime (needs the lookahead
+  // streams and the deferred interchanges of the finished columns)
+  if (h->lookahead >= 2 && p > 0 && h->side && h->bulk && h->look && ensure_defer(h, m, n, sizeof(T)))
+    return getrf_dag<T>(h, m, n, A, lda, ipiv, info, h->lookahead);
+  LUPP_TRY(set_int(s, info, 0));
   if (p == 0) return hipSuccess;
   const bool la = h->lookahead && h->side && h->bulk;
   const int64_t J = (p + h->nb - 1) / h->nb;
@@ -337,6 +347,183 @@ hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32
   return hipSuccess;
 }
 
+// ---------------------------------------------------------------- algorithm-by-blocks
+// The dataflow form of the same factorization: the paper's algorithm-by-
+// blocks (Section 4.1) with its runtime's two parts (Section 4.4, the
+// analyzer and the dispatcher).  The blocked loop is unrolled into tasks on
+// operands, the analyzer derives each task's predecessors from the operands
+// it reads and writes (read after write, write after read, write after
+// write), and the dispatcher issues the tasks in a priority order onto HIP
+// streams, turning each dependency on a task of another stream into an event
+// wait, so that the GPU runs every task as soon as its inputs are final.
+//
+// Operands: column block j of width nb (object j, rows from the block's
+// step down) and the interchange record of step k (object J + k).  Tasks:
+//   START        zeroes info; writes every object (everything follows it);
+//   PANEL(k)     factors column block k and composes its interchanges into
+//                the step's record; writes k and J + k;
+//   UPD(k, a, b) the record's interchanges, U := inv(L11) U and the update
+//                A22 -= L21 U on the columns of blocks a .. b-1 right of the
+//                factored block; reads k and J + k, writes a .. b-1 (a = k
+//                only for the tail of a last factored block narrower than nb);
+//   LEFT         the deferred interchanges of the finished blocks; reads
+//                J .. 2J-1, writes 0 .. J-2.
+// With lookahead depth d, step k's update of block k+1 and of blocks
+// k+2 .. k+d are tasks of their own, the rest one task (one large update), so
+// the chain of column blocks may run up to d steps ahead of the large
+// updates.  Streams: the column blocks on a CU-masked panel stream; the next
+// block's update on the caller's stream (nothing else runs then on the
+// panel's CUs: the next column block waits for it); the other lookahead
+// blocks' updates and the large updates on two streams masked to the CUs
+// outside the panel's, so that they never slow the column block down.  Partial pivoting is
+// unchanged: every column block spans the full remaining height, and each
+// task computes exactly what the same step computes in the loop above, in
+// the same order per entry (the factors are identical bit for bit).
+struct DagTask {
+  int kind;             // 0 start, 1 panel, 2 update, 3 left interchanges
+  int64_t k, a, b;      // step; column blocks [a, b)
+  hipStream_t stream;
+  std::vector<int> reads, writes, deps;
+};
+
+// Analyzer: predecessors of every task from its read and write sets.
+void dag_analyze(std::vector<DagTask>& t, int nobj) {
+  std::vector<int> last_writer(nobj, -1);
+  std::vector<std::vector<int>> readers(nobj);
+  for (int i = 0; i < (int)t.size(); ++i) {
+    std::vector<int>& d = t[i].deps;
+    for (int o : t[i].reads)
+      if (last_writer[o] >= 0) d.push_back(last_writer[o]);  // read after write
+    for (int o : t[i].writes) {
+      if (last_writer[o] >= 0) d.push_back(last_writer[o]);  // write after write
+      for (int r : readers[o]) d.push_back(r);               // write after read
+    }
+    std::sort(d.begin(), d.end());
+    d.erase(std::unique(d.begin(), d.end()), d.end());
+    d.erase(std::remove(d.begin(), d.end(), i), d.end());
+    for (int o : t[i].reads) readers[o].push_back(i);
+    for (int o : t[i].writes) {
+      last_writer[o] = i;
+      readers[o].clear();
+    }
+  }
+}
+
+hipError_t dag_events(lupp_handle_t h, size_t count) {
+  while (h->dag_events.size() < count) {
+    hipEvent_t e = nullptr;
+    LUPP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    h->dag_events.push_back(e);
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t getrf_dag(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32_t* ipiv, int32_t* info,
+                     int depth) {
+  hipStream_t s = h->stream;
+  const int64_t p = m < n ? m : n;
+  const int64_t nb = h->nb;
+  const int64_t J = (p + nb - 1) / nb;   // column blocks that are factored
+  const int64_t JN = (n + nb - 1) / nb;  // column blocks of the matrix
+  const int NOBJ = (int)(JN + J);
+  SwapPairs* step_pairs = (SwapPairs*)h->defer_buf;
+  // the panel stream of step k (rows left: m - k nb), or null when its
+  // cooperative factorization exceeds the reserved CUs (it then runs on the
+  // caller's stream)
+  auto pair_of = [&](int64_t k) {
+    const int G = panel_groups(m - k * nb);
+    return (G <= h->panel_cus) ? 0 : (h->side2 && h->bulk2 && h->look2 && G <= h->panel_cus2) ? 1 : -1;
+  };
+  std::vector<DagTask> t;
+  auto add = [&](int kind, int64_t k, int64_t a, int64_t b, hipStream_t st) -> DagTask& {
+    t.push_back(DagTask{kind, k, a, b, st, {}, {}, {}});
+    return t.back();
+  };
+  {
+    DagTask& st = add(0, 0, 0, 0, s);
+    for (int o = 0; o < NOBJ; ++o) st.writes.push_back(o);
+  }
+  for (int64_t k = 0; k < J; ++k) {
+    const int pr = pair_of(k);
+    DagTask& pt = add(1, k, k, k + 1, pr == 0 ? h->side : pr == 1 ? h->side2 : s);
+    pt.writes = {(int)k, (int)(JN + k)};
+    // the columns right of the factored block: [k nb + b, n), from object a0
+    // on (a0 = k when the last factored block is narrower than nb)
+    const int64_t kn = k * nb + ((p - k * nb < nb) ? (p - k * nb) : nb);
+    if (kn >= n) continue;
+    const int64_t a0 = kn / nb;
+    // the large update runs beside the next step's column block: the bulk
+    // stream whose CUs are disjoint from that block's panel stream
+    const int prn = (k + 1 < J) ? pair_of(k + 1) : 0;
+    hipStream_t sb = prn == 1 ? h->bulk2 : h->bulk;
+    hipStream_t sl = prn == 1 ? h->look2 : h->look;
+    const int64_t la = a0 + depth < JN ? a0 + depth : JN;  // end of the lookahead blocks
+    const int64_t cut[4] = {a0, a0 + 1 < la ? a0 + 1 : la, la, JN};
+    for (int q = 0; q < 3; ++q) {
+      if (cut[q] >= cut[q + 1]) continue;
+      DagTask& u = add(2, k, cut[q], cut[q + 1], q == 0 ? s : q == 1 ? sl : sb);
+      u.reads = {(int)k, (int)(JN + k)};
+      for (int64_t j = cut[q]; j < cut[q + 1]; ++j) u.writes.push_back((int)j);
+    }
+  }
+  if (J >= 2) {
+    DagTask& lt = add(3, 0, 0, 0, s);
+    for (int64_t k = 0; k < J; ++k) lt.reads.push_back((int)(JN + k));
+    for (int64_t j = 0; j < J - 1; ++j) lt.writes.push_back((int)j);
+  }
+  dag_analyze(t, NOBJ);
+  LUPP_TRY(dag_events(h, t.size()));
+
+  // Dispatcher: list order is the priority (each step's column block, then
+  // the update of the next block, the lookahead blocks, the large update).
+  for (size_t i = 0; i < t.size(); ++i) {
+    const DagTask& x = t[i];
+    for (int d : x.deps)
+      if (t[d].stream != x.stream) LUPP_TRY(hipStreamWaitEvent(x.stream, h->dag_events[d], 0));
+    const int64_t k0 = x.k * nb;
+    const int64_t b = (p - k0 < nb) ? (p - k0) : nb;
+    if (x.kind == 0) {
+      LUPP_TRY(set_int(s, info, 0));
+    } else if (x.kind == 1) {
+      LUPP_TRY(factor_block<T>(h, x.stream, m, k0, b, A, lda, ipiv, info));
+      const int tt = timer_begin(h, LUPP_PHASE_LASWP, x.stream);
+      LUPP_TRY(swap_pairs(x.stream, ipiv, k0, k0 + b, m, step_pairs + x.k));
+      timer_end(h, tt, x.stream, 0.0);
+    } else if (x.kind == 2) {
+      const int64_t kn = k0 + b, mr = m - kn;
+      const int64_t c0 = (x.a * nb > kn) ? x.a * nb : kn, c1 = (x.b * nb < n) ? x.b * nb : n, nc = c1 - c0;
+      const SwapPairs* sp = step_pairs + x.k;
+      int tt = timer_begin(h, LUPP_PHASE_LASWP, x.stream);
+      LUPP_TRY(apply_pairs<T>(x.stream, A, lda, c0, c1, 0, 0, sp, 2 * b));
+      timer_end(h, tt, x.stream, 0.0);
+      tt = timer_begin(h, LUPP_PHASE_TRSM, x.stream);
+      LUPP_TRY(trsm_lower_unit<T>(x.stream, b, nc, A + k0 + k0 * lda, lda, A + k0 + c0 * lda, lda));
+      timer_end(h, tt, x.stream, (double)b * (double)b * (double)nc);
+      if (mr > 0) {
+        int tile = -1;
+        tt = timer_begin(h, LUPP_PHASE_UPDATE, x.stream);
+        LUPP_TRY(update<T>(h, x.stream, x.stream == s ? 0 : 1, mr, nc, b, A + kn + k0 * lda, lda, A + k0 + c0 * lda,
+                           lda, A + kn + c0 * lda, lda, &tile));
+        timer_end(h, tt, x.stream, 2.0 * (double)mr * (double)nc * (double)b, tile == 1, update_bytes<T>(mr, nc, b));
+      }
+    } else {
+      const int tt = timer_begin(h, LUPP_PHASE_LASWP, s);
+      int32_t* g = (int32_t*)((char*)h->defer_buf + (size_t)J * sizeof(SwapPairs));
+      int32_t* gmap = g + 2 * m;
+      LUPP_TRY(left_maps(s, step_pairs, J, m, nb, g, gmap));
+      LUPP_TRY(left_gather<T>(s, A, lda, m, nb, J, gmap));
+      timer_end(h, tt, s, 0.0);
+    }
+    LUPP_TRY(hipEventRecord(h->dag_events[i], x.stream));
+  }
+  // the caller's stream ends after every task (LEFT and the last steps'
+  // tasks on other streams)
+  for (size_t i = 0; i < t.size(); ++i)
+    if (t[i].stream != s) LUPP_TRY(hipStreamWaitEvent(s, h->dag_events[i], 0));
+  return hipSuccess;
+}
+
 // Solve with the factors: the interchanges in runs of at most kMaxSwaps
 // (composed per run, applied to all right-hand sides at once), then the two
 // triangular solves -- for one or two right-hand sides the one-launch
@@ -375,6 +562,8 @@ hipError_t ensure_lp_scale(lupp_handle_t h, int64_t m, int64_t n) {
   if (h->bulk) LUPP_TRY(hipStreamSynchronize(h->bulk));
   if (h->side) LUPP_TRY(hipStreamSynchronize(h->side));
   if (h->bulk2) LUPP_TRY(hipStreamSynchronize(h->bulk2));
+  if (h->look) LUPP_TRY(hipStreamSynchronize(h->look));
+  if (h->look2) LUPP_TRY(hipStreamSynchronize(h->look2));
   if (h->side2) LUPP_TRY(hipStreamSynchronize(h->side2));
   if (h->lp_scale[0]) (void)hipFree(h->lp_scale[0]);
   h->lp_scale[0] = h->lp_scale[1] = h->lp_scale[2] = nullptr;
@@ -468,6 +657,8 @@ hipError_t ensure_workspace(lupp_handle_t h) {
   }
   if (hipExtStreamCreateWithCUMask(&h->side, (uint32_t)mside.size(), mside.data()) != hipSuccess) h->side = nullptr;
   if (hipExtStreamCreateWithCUMask(&h->bulk, (uint32_t)mbulk.size(), mbulk.data()) != hipSuccess) h->bulk = nullptr;
+  // the dataflow runtime's lookahead updates: the bulk CUs, their own queue
+  if (hipExtStreamCreateWithCUMask(&h->look, (uint32_t)mbulk.size(), mbulk.data()) != hipSuccess) h->look = nullptr;
   if (ncu >= 2 * kLookaheadPanelCUs2) {
     std::vector<uint32_t> m2s((ncu + 31) / 32, 0u), m2b((ncu + 31) / 32, 0u);
     for (int c = 0; c < ncu; ++c) {
@@ -476,6 +667,7 @@ hipError_t ensure_workspace(lupp_handle_t h) {
     }
     if (hipExtStreamCreateWithCUMask(&h->side2, (uint32_t)m2s.size(), m2s.data()) != hipSuccess) h->side2 = nullptr;
     if (hipExtStreamCreateWithCUMask(&h->bulk2, (uint32_t)m2b.size(), m2b.data()) != hipSuccess) h->bulk2 = nullptr;
+    if (hipExtStreamCreateWithCUMask(&h->look2, (uint32_t)m2b.size(), m2b.data()) != hipSuccess) h->look2 = nullptr;
     if (h->side2 && h->bulk2) h->panel_cus2 = kLookaheadPanelCUs2;
   }
   if (!h->side || !h->bulk || hipEventCreateWithFlags(&h->ev_cols, hipEventDisableTiming) != hipSuccess ||
@@ -596,6 +788,9 @@ int lupp_destroy(lupp_handle_t h) {
   if (h->bulk) (void)hipStreamSynchronize(h->bulk);
   if (h->side2) (void)hipStreamSynchronize(h->side2);
   if (h->bulk2) (void)hipStreamSynchronize(h->bulk2);
+  if (h->look) (void)hipStreamSynchronize(h->look);
+  if (h->look2) (void)hipStreamSynchronize(h->look2);
+  for (hipEvent_t e : h->dag_events) (void)hipEventDestroy(e);
   if (h->ev_cols) (void)hipEventDestroy(h->ev_cols);
   if (h->ev_panel) (void)hipEventDestroy(h->ev_panel);
   if (h->ev_bulk) (void)hipEventDestroy(h->ev_bulk);
@@ -607,6 +802,8 @@ int lupp_destroy(lupp_handle_t h) {
   if (h->bulk) (void)hipStreamDestroy(h->bulk);
   if (h->side2) (void)hipStreamDestroy(h->side2);
   if (h->bulk2) (void)hipStreamDestroy(h->bulk2);
+  if (h->look) (void)hipStreamDestroy(h->look);
+  if (h->look2) (void)hipStreamDestroy(h->look2);
   if (h->slots) (void)hipFree(h->slots);
   if (h->defer_buf) (void)hipFree(h->defer_buf);
   if (h->lp_scale[0]) (void)hipFree(h->lp_scale[0]);
@@ -639,7 +836,7 @@ int lupp_set_option(lupp_handle_t h, int option, int64_t value) {
       h->timing = value != 0;
       return LUPP_OK;
     case LUPP_OPT_LOOKAHEAD:
-      if (value != 0 && value != 1) return -3;
+      if (value < 0 || value > 16) return -3;
       h->lookahead = (int)value;
       return LUPP_OK;
     case LUPP_OPT_UPDATE_PREC:
@@ -666,6 +863,8 @@ int lupp_sync(lupp_handle_t h) {
   if (e == hipSuccess && h->bulk) e = hipStreamSynchronize(h->bulk);
   if (e == hipSuccess && h->side2) e = hipStreamSynchronize(h->side2);
   if (e == hipSuccess && h->bulk2) e = hipStreamSynchronize(h->bulk2);
+  if (e == hipSuccess && h->look) e = hipStreamSynchronize(h->look);
+  if (e == hipSuccess && h->look2) e = hipStreamSynchronize(h->look2);
   if (e != hipSuccess) return lupp::hip_status(e);
   if (h->slots) {
     int32_t err = 0;
@@ -746,6 +945,8 @@ int lupp_timing_summary(lupp_handle_t h, int phase, int64_t* count, double* ms, 
   if (e == hipSuccess && h->bulk) e = hipStreamSynchronize(h->bulk);
   if (e == hipSuccess && h->side2) e = hipStreamSynchronize(h->side2);
   if (e == hipSuccess && h->bulk2) e = hipStreamSynchronize(h->bulk2);
+  if (e == hipSuccess && h->look) e = hipStreamSynchronize(h->look);
+  if (e == hipSuccess && h->look2) e = hipStreamSynchronize(h->look2);
   if (e != hipSuccess) return lupp::hip_status(e);
   *count = 0;
   *ms = 0.0;
