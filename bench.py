@@ -52,6 +52,9 @@ The JSON line carries:
   dataflow    the headline factorization by the dataflow (algorithm-by-blocks)
               runtime at lookahead depth 2 and 4: time, pivots against the
               headline run's
+  qr          Householder QR (lupp_dgeqrf, compact WY) at n = 4096, 8192,
+              16384: TFLOP/s on 4/3 n^3, column-block and update time, probe
+              residual of Q R x against A x
   large       n = 65536 (diagonally dominant recipe drawn on the device): plain FP64
               factorization + solve against the FP8-update GMRES-IR solve (wall
               times, effective TFLOP/s, backward errors, forward error against
@@ -439,6 +442,59 @@ def dataflow_leg(torch, lupp, A0, A, fn, ref_ipiv, nb, depths=(2, 4)):
     return out
 
 
+def qr_leg(torch, lupp, seed, sizes=(4096, 8192, 16384)):
+    """Householder QR (lupp_dgeqrf) of A iid U(-1,1) drawn on the device:
+    best of two calls after one untimed call; TFLOP/s on 4/3 n^3; the
+    column-block and update shares from the library's phase events; a
+    probe of ||A x - Q (R x)|| with Q applied on the device by torch."""
+    runs = []
+    for n in sizes:
+        g = torch.Generator(device="cuda").manual_seed(seed + n)
+        A0 = torch.empty((n, n), dtype=torch.float64, device="cuda").t().uniform_(-1.0, 1.0, generator=g)
+        A = torch.empty_like(A0.t()).t()
+        tau = torch.empty(n, dtype=torch.float64, device="cuda")
+        h = lupp.Handle()
+        ts = []
+        for r in range(3):
+            A.copy_(A0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lupp.lupp_dgeqrf(A, tau, h)
+            h.sync()
+            torch.cuda.synchronize()
+            if r:
+                ts.append(time.perf_counter() - t0)
+        h.set_option(3, 1)
+        A.copy_(A0)
+        lupp.lupp_dgeqrf(A, tau, h)
+        h.sync()
+        pc, pms, _ = h.timing_summary("panel")
+        uc, ums, ufl = h.timing_summary("update", reset=True)
+        h.close()
+        # probe: x random, y = R x, then Q y by the reflectors in reverse order
+        x = torch.rand((n, 4), generator=g, dtype=torch.float64, device="cuda") * 2 - 1
+        y = torch.triu(A) @ x
+        for j in range(n - 1, -1, -1):
+            v = A[j:, j].clone()
+            v[0] = 1.0
+            y[j:] -= tau[j] * torch.outer(v, v @ y[j:])
+            if j % 2048 == 0:
+                torch.cuda.synchronize()
+        res = float((A0 @ x - y).abs().max() / (n * 2.0 ** -53 * A0.abs().sum(0).max() * x.abs().max()))
+        ms = min(ts) * 1e3
+        runs.append({"n": n, "ms": round(ms, 3), "tflops": round(4.0 / 3.0 * n ** 3 / (ms * 1e-3) / 1e12, 3),
+                     "frac_fp64_peak": round(4.0 / 3.0 * n ** 3 / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+                     "panel_ms": round(pms, 2), "panel_launches": pc, "update_ms": round(ums, 2),
+                     "update_tflops": round(ufl / (ums * 1e-3) / 1e12, 3) if ums > 0 else None,
+                     "probe_scaled_residual": res})
+        del A, A0
+        torch.cuda.empty_cache()
+    out = {"workload": "Householder QR, A iid U(-1,1) (device-drawn, seed + n), best of 2 after 1 warmup; "
+                       "flops 4/3 n^3", "runs": runs}
+    log("qr: %s" % out)
+    return out
+
+
 def large_leg(torch, lupp, n, seed):
     """FP8-update GMRES-IR solve against plain FP64 LUPP + solve at a large n,
     on the diagonally dominant recipe drawn on the device (torch's seeded
@@ -626,6 +682,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched small-systems leg")
     ap.add_argument("--no-large", action="store_true", help="skip the large mixed-precision leg")
     ap.add_argument("--no-dataflow", action="store_true", help="skip the dataflow-runtime leg")
+    ap.add_argument("--no-qr", action="store_true", help="skip the Householder QR leg")
     ap.add_argument("--no-c2", action="store_true", help="skip the FP64/FP32 size sweep")
     ap.add_argument("--no-kappa", action="store_true", help="skip the kappa (n=4096) mixed-precision leg")
     ap.add_argument("--large-n", type=int, default=65536)
@@ -788,6 +845,13 @@ def main():
             torch.cuda.empty_cache()
             mixed["n16384"] = mixed16_leg(torch, lupp, args.seed)
 
+    qrres = None
+    if not args.no_qr and not args.profile_once:
+        A = None
+        torch.cuda.empty_cache()
+        log("qr leg")
+        qrres = qr_leg(torch, lupp, args.seed)
+
     batched = None
     if not args.no_batched:
         log("batched leg")
@@ -831,6 +895,7 @@ def main():
         "batched": batched,
         "large": large,
         "dataflow": dataflow,
+        "qr": qrres,
     }
     print(json.dumps(out), flush=True)
     h.close()

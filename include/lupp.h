@@ -420,6 +420,30 @@ int lupp_dgetrf_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const
 int lupp_sgetrf_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_t* dA_off,
                         float* dA, const int64_t* dipiv_off, int32_t* dipiv, int32_t* dinfo);
 
+/*
+ * Householder QR factorization A = Q R of an m x n FP64 matrix, in place
+ * (the paper's HQR, Section 2.2: R upper triangular, V unit lower triangular
+ * holding the Householder vectors, one scalar per vector), blocked with the
+ * compact WY form of Section 2.3.  Conventions of LAPACK's dgeqrf:
+ *   - reflector j is H_j = I - tau_j v_j v_j^T with v_j[j] = 1, v_j zero above
+ *     row j; it maps column j's entries from row j down to beta e_j with
+ *     beta = -sign(alpha) ||x||_2 (sign(0) = +1); tau_j = 0 (H_j = I) when the
+ *     entries below the diagonal are already zero;
+ *   - on return R is on and above the diagonal of A, v_j[j+1:] below it, and
+ *     Q = H_1 H_2 ... H_k, k = min(m, n);
+ *   - dtau: device double[k].
+ * Per block of 32 columns: the block's reflectors (one cooperative launch,
+ * one exchange between workgroups per column), T with H_1 ... H_b =
+ * I - V T V^T, and the trailing columns A2 := A2 - V (T^T (V^T A2)) as matrix
+ * products.  Sums of squares are formed without scaling: entries whose
+ * squares overflow are outside the contract.  Asynchronous on the handle's
+ * stream; the column-block kernel's workgroups wait for each other (bounded
+ * waits, an expiry reported by lupp_sync as LUPP_ERR_INTERNAL).
+ * Size limit: m <= 131072 (LUPP_ERR_UNSUPPORTED beyond).
+ * Errors: -2 m, -3 n, -4 dA, -5 lda, -6 dtau.
+ */
+int lupp_dgeqrf(lupp_handle_t h, int64_t m, int64_t n, double* dA, int64_t lda, double* dtau);
+
 #ifdef __cplusplus
 }
 #endif

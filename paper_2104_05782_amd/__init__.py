@@ -25,6 +25,8 @@ from ._binding import (  # noqa: F401
     lupp_sgetrf,
     lupp_sgetrs,
     getrf,
+    geqrf,
+    lupp_dgeqrf,
     getrs,
     gesv_batched,
     gesv_mixed,

@@ -27,6 +27,7 @@ _lib.lupp_status_string.argtypes = [_i32]
 _lib.lupp_status_string.restype = ctypes.c_char_p
 for _name in ("lupp_dgetrf", "lupp_sgetrf"):
     getattr(_lib, _name).argtypes = [_vp, _i64, _i64, _vp, _i64, _vp, _vp]
+_lib.lupp_dgeqrf.argtypes = [_vp, _i64, _i64, _vp, _i64, _vp]
 for _name in ("lupp_dgetrs", "lupp_sgetrs"):
     getattr(_lib, _name).argtypes = [_vp, _char, _i64, _i64, _vp, _i64, _vp, _vp, _i64]
 
@@ -391,6 +392,26 @@ def gesv_batched(n, A, a_off, B=None, b_off=None, handle: Handle | None = None):
     info = torch.zeros(max(1, n.numel()), dtype=torch.int32, device=A.device)
     lupp_xgesv_batched(n, A, a_off, ipiv, p_off, B, b_off, info, handle)
     return ipiv, p_off, info
+
+
+def lupp_dgeqrf(A, tau, handle: Handle | None = None):
+    """Householder QR in place of column-major float64 A; tau float64[min(m, n)]."""
+    _dev(A, torch.float64, "A")
+    _dev(tau, torch.float64, "tau")
+    m, n = A.shape
+    if tau.numel() < min(m, n):
+        raise ValueError("tau needs min(m, n) entries")
+    h = _prep(handle)
+    _check(_lib.lupp_dgeqrf(h.ptr, m, n, A.data_ptr(), _lead(A), tau.data_ptr()), "lupp_dgeqrf")
+
+
+def geqrf(A: torch.Tensor, handle: Handle | None = None) -> torch.Tensor:
+    """Factor column-major float64 A in place (R above, Householder vectors
+    below the diagonal); returns tau."""
+    m, n = A.shape
+    tau = torch.empty(max(1, min(m, n)), dtype=torch.float64, device=A.device)
+    lupp_dgeqrf(A, tau, handle)
+    return tau[:min(m, n)]
 
 
 def getrf(A: torch.Tensor, handle: Handle | None = None):

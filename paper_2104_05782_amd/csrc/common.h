@@ -58,6 +58,17 @@ struct LeafSlots {
   uint64_t rowj[2][2 * kLeafMaxWidth];              // the diagonal row before the interchange
 };
 
+// Exchange records of the Householder panel kernel: per column (by parity)
+// and workgroup 64 tagged words carrying 32 partial sums as 32-bit halves,
+// and the diagonal row (32 values) published by workgroup 0.
+constexpr int kQrMaxGroups = 256;
+struct QrSlots {
+  int32_t err;  // set when a bounded wait expires
+  int32_t pad_[63];
+  uint64_t rec[2][kQrMaxGroups][64];
+  uint64_t rowj[2][64];
+};
+
 // Row movement of a run of consecutive interchanges k1..k2-1 (k2 - k1 <=
 // kMaxSwaps), composed into one permutation: after the run, row dst[q] holds
 // what row src[q] held before it.  The first k2 - k1 entries are the rows

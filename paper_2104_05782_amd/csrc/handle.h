@@ -15,6 +15,14 @@ struct TimingRecord {
 };
 struct MixedWs;
 struct BatchWs;
+// Workspace of the QR path: the panel's exchange records, the explicit V,
+// G, T, W and the partials of the row-chunked products.
+struct QrWs {
+  QrSlots* slots = nullptr;
+  uint32_t epoch = 0;
+  double* buf = nullptr;
+  size_t bytes = 0;
+};
 }  // namespace lupp
 
 struct lupp_handle_st {
@@ -65,6 +73,7 @@ struct lupp_handle_st {
   lupp::TrsvState trsv{};           // one-launch triangular solve state (flags on demand)
   lupp::MixedWs* mixed = nullptr;   // workspace of lupp_dgesv_mixed
   lupp::BatchWs* batch = nullptr;   // workspace and streams of the batched path
+  lupp::QrWs* qr = nullptr;         // workspace of the Householder QR
 };
 
 namespace lupp {
@@ -95,6 +104,12 @@ hipError_t getrs(lupp_handle_t h, int64_t n, int64_t nrhs, const T* LU, int64_t 
                  int64_t ldb);
 void free_mixed(lupp_handle_t h);
 void free_batched(lupp_handle_t h);
+void free_qr(lupp_handle_t h);
+// Householder QR of an m x n matrix on the handle's stream (arguments checked).
+hipError_t geqrf(lupp_handle_t h, int64_t m, int64_t n, double* A, int64_t lda, double* tau);
+size_t qr_workspace_bytes(int64_t m, int64_t n);
+int timer_begin(lupp_handle_t h, int phase, hipStream_t st);
+void timer_end(lupp_handle_t h, int idx, hipStream_t st, double flops, bool big = false, double bytes = 0.0);
 // Batched path set-up at handle creation: class streams and events, grids, and
 // the device address of the allocation-free entry point's scratch array.
 hipError_t setup_batched(lupp_handle_t h);

@@ -24,22 +24,6 @@
 #include "handle.h"
 
 namespace lupp {
-namespace {
-
-constexpr int kLookaheadPanelCUs = 32;
-constexpr int kLookaheadPanelCUs2 = 64;  // second pair, for panels of 33 to 64 workgroups
-
-// Epoch of the panel kernel's progress flags: every launch uses flag values
-// above all values written before; the flags are cleared before wrap-around.
-inline hipError_t next_epoch(lupp_handle_t h, hipStream_t st, int w, uint32_t* out) {
-  if (h->epoch > 0xF0000000u) {
-    LUPP_TRY(reset_flags(st, h->slots));
-    h->epoch = 0;
-  }
-  *out = h->epoch;
-  h->epoch += (uint32_t)w + 1u;
-  return hipSuccess;
-}
 
 // Phase timing: HIP events on the handle's stream around a phase's launches.
 int timer_begin(lupp_handle_t h, int phase, hipStream_t st) {
@@ -62,13 +46,30 @@ int timer_begin(lupp_handle_t h, int phase, hipStream_t st) {
   return (int)h->nrecords++;
 }
 
-void timer_end(lupp_handle_t h, int idx, hipStream_t st, double flops, bool big = false, double bytes = 0.0) {
+void timer_end(lupp_handle_t h, int idx, hipStream_t st, double flops, bool big, double bytes) {
   if (idx < 0) return;
   TimingRecord& r = h->records[idx];
   r.flops = flops;
   r.bytes = bytes;
   r.big = big;
   (void)hipEventRecord(r.stop, st);
+}
+
+namespace {
+
+constexpr int kLookaheadPanelCUs = 32;
+constexpr int kLookaheadPanelCUs2 = 64;  // second pair, for panels of 33 to 64 workgroups
+
+// Epoch of the panel kernel's progress flags: every launch uses flag values
+// above all values written before; the flags are cleared before wrap-around.
+inline hipError_t next_epoch(lupp_handle_t h, hipStream_t st, int w, uint32_t* out) {
+  if (h->epoch > 0xF0000000u) {
+    LUPP_TRY(reset_flags(st, h->slots));
+    h->epoch = 0;
+  }
+  *out = h->epoch;
+  h->epoch += (uint32_t)w + 1u;
+  return hipSuccess;
 }
 
 // Algorithmic bytes of an update C (M x N) -= A (M x K) * B (K x N): C read
@@ -810,6 +811,7 @@ int lupp_destroy(lupp_handle_t h) {
   if (h->trsv.flags) (void)hipFree(h->trsv.flags);
   lupp::free_mixed(h);
   lupp::free_batched(h);
+  lupp::free_qr(h);
   delete h;
   return rc;
 }
@@ -874,6 +876,16 @@ int lupp_sync(lupp_handle_t h) {
       const int32_t zero = 0;
       (void)hipMemcpy(&h->slots->err, &zero, sizeof(zero), hipMemcpyHostToDevice);
       (void)lupp::take_trsv_error(h);
+      return LUPP_ERR_INTERNAL;
+    }
+  }
+  if (h->qr && h->qr->slots) {
+    int32_t qerr = 0;
+    e = hipMemcpy(&qerr, &h->qr->slots->err, sizeof(qerr), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return lupp::hip_status(e);
+    if (qerr) {
+      const int32_t zero = 0;
+      (void)hipMemcpy(&h->qr->slots->err, &zero, sizeof(zero), hipMemcpyHostToDevice);
       return LUPP_ERR_INTERNAL;
     }
   }
