@@ -24,6 +24,10 @@
 //      from G and tau: T[j][j] = tau_j, T[:j, j] = -tau_j T[:j, :j] G[:j, j].
 //   4. k_qr_trmm: W := T^T W.
 //   5. A2 -= V W on the FP64 MFMA GEMM of the LU path.
+// Steps 2-5 update only the rest of a 128-column outer block; the columns
+// right of it get one update per outer block with its 128 reflectors
+// (k_qr_larft_big builds that T; T^T W and V W both run on the GEMM, K = 128),
+// so the trailing matrix is read and written once per 128 columns.
 #include "handle.h"
 #include "wave.h"
 
@@ -32,6 +36,7 @@ namespace lupp {
 namespace {
 
 constexpr int kQrW = 32;         // block width (columns per panel launch)
+constexpr int kQrNB = 128;       // outer block width (columns per trailing update)
 constexpr int kQrThreads = 512;  // rows per workgroup of the panel kernel
 constexpr long kQrSpin = 1L << 22;
 
@@ -231,74 +236,147 @@ __global__ __launch_bounds__(NT) void k_qr_panel(int64_t r, int w, double* __res
   }
 }
 
-// Partials of W = V^T X over row chunks: V is r x 32 (ldv), X is r x N (ldx);
-// workgroup (tile, chunk) writes part[chunk][32 x 64 tile] (column-major 32 x
-// N per chunk).  Four wavefronts, each 16 rows x 32 columns of the tile (two
-// 16x16 MFMA accumulators); LDS tiles of 32 rows.
+// Partials of W = V^T X over row chunks: V is r x LDW (ldv), X is r x N
+// (ldx); workgroup (tile, chunk) computes all LDW rows of W for 64 columns
+// (X is read once) and writes part[chunk] (column-major LDW x N per chunk).
+// Four wavefronts: for LDW = 128 each takes 32 rows x 64 columns (8 MFMA
+// accumulators of 16x16), for LDW = 32 each 16 rows x 32 columns (2).  LDS
+// tiles of 32 rows, double-buffered: the next tile's loads are in flight
+// while the current one is multiplied.
 constexpr int kTnCols = 64, kTnK = 32;
+template <int LDW>
 __global__ __launch_bounds__(256) void k_qr_tn(int64_t r, int64_t N, const double* __restrict__ V, int64_t ldv,
                                                const double* __restrict__ X, int64_t ldx, int64_t rows_per_chunk,
                                                double* __restrict__ part) {
   typedef Mfma<double> MF;
-  __shared__ double sV[kTnK][kQrW + 1];
-  __shared__ double sX[kTnK][kTnCols + 1];
+  constexpr int WR = LDW == 128 ? 32 : 16;  // rows of W per wavefront
+  constexpr int WC = LDW == 128 ? 64 : 32;  // columns per wavefront
+  constexpr int FI = WR / 16, FJ = WC / 16;
+  constexpr int EV = kTnK * LDW / 256, EX = kTnK * kTnCols / 256;
+  __shared__ double sV[2][kTnK][LDW + 1];
+  __shared__ double sX[2][kTnK][kTnCols + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t c0 = (int64_t)blockIdx.x * kTnCols;
   const int64_t chunk = blockIdx.y;
   const int64_t r0 = chunk * rows_per_chunk;
   const int64_t r1 = (r0 + rows_per_chunk < r) ? r0 + rows_per_chunk : r;
-  const int wi = (wave & 1) * 16, wc = (wave >> 1) * 32;  // this wavefront's rows of W and columns of the tile
-  MF::v4 acc[2];
+  const int wi = LDW == 128 ? 32 * wave : (wave & 1) * 16;
+  const int wc = LDW == 128 ? 0 : (wave >> 1) * 32;
+  MF::v4 acc[FI][FJ];
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int a = 0; a < FI; ++a)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[t][q] = 0.0;
-  for (int64_t k0 = r0; k0 < r1; k0 += kTnK) {
-    // V tile: 32 rows x 32 columns, X tile: 32 rows x 64 columns (row index fastest)
+    for (int t = 0; t < FJ; ++t)
 #pragma unroll
-    for (int e = tid; e < kTnK * kQrW; e += 256) {
-      const int kk = e % kTnK, c = e / kTnK;
+      for (int q = 0; q < 4; ++q) acc[a][t][q] = 0.0;
+  double rv[EV], rx[EX];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < EV; ++u) {
+      const int e = tid + 256 * u, kk = e % kTnK, c = e / kTnK;
       const int64_t row = k0 + kk;
-      sV[kk][c] = row < r1 ? V[row + (int64_t)c * ldv] : 0.0;
+      rv[u] = row < r1 ? V[row + (int64_t)c * ldv] : 0.0;
     }
 #pragma unroll
-    for (int e = tid; e < kTnK * kTnCols; e += 256) {
-      const int kk = e % kTnK, c = e / kTnK;
+    for (int u = 0; u < EX; ++u) {
+      const int e = tid + 256 * u, kk = e % kTnK, c = e / kTnK;
       const int64_t row = k0 + kk, col = c0 + c;
-      sX[kk][c] = (row < r1 && col < N) ? X[row + col * ldx] : 0.0;
+      rx[u] = (row < r1 && col < N) ? X[row + col * ldx] : 0.0;
     }
-    __syncthreads();
-    const int lr = lane & 15, lk = lane >> 4;
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < EV; ++u) {
+      const int e = tid + 256 * u;
+      sV[buf][e % kTnK][e / kTnK] = rv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < EX; ++u) {
+      const int e = tid + 256 * u;
+      sX[buf][e % kTnK][e / kTnK] = rx[u];
+    }
+  };
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t nsteps = (r1 - r0 + kTnK - 1) / kTnK;
+  if (nsteps > 0) {
+    gload(r0);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int64_t st = 0; st < nsteps; ++st) {
+    const int buf = (int)(st & 1);
+    if (st + 1 < nsteps) gload(r0 + (st + 1) * kTnK);
 #pragma unroll
     for (int kk = 0; kk < kTnK; kk += 4) {
-      const double va = sV[kk + lk][wi + lr];  // A = V^T: A[i][k] = V[k][i]
+      double va[FI], xb[FJ];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const double xb = sX[kk + lk][wc + 16 * t + lr];  // B[k][c] = X[k][c]
-        acc[t] = MF::mma(va, xb, acc[t]);
-      }
+      for (int a = 0; a < FI; ++a) va[a] = sV[buf][kk + lk][wi + 16 * a + lr];  // A = V^T: A[i][k] = V[k][i]
+#pragma unroll
+      for (int t = 0; t < FJ; ++t) xb[t] = sX[buf][kk + lk][wc + 16 * t + lr];  // B[k][c] = X[k][c]
+#pragma unroll
+      for (int a = 0; a < FI; ++a)
+#pragma unroll
+        for (int t = 0; t < FJ; ++t) acc[a][t] = MF::mma(va[a], xb[t], acc[a][t]);
     }
+    if (st + 1 < nsteps) sstore(buf ^ 1);
     __syncthreads();
   }
-  // lane holds D[4q + (lane >> 4)][lane & 15]: W row wi + 4q + (lane >> 4), column wc + 16t + (lane & 15)
-  double* out = part + chunk * (int64_t)kQrW * N;
+  // lane holds D[4q + (lane >> 4)][lane & 15] of each 16x16 product
+  double* out = part + chunk * (int64_t)LDW * N;
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int a = 0; a < FI; ++a)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int row = wi + 4 * q + (lane >> 4);
-      const int64_t col = c0 + wc + 16 * t + (lane & 15);
-      if (col < N) out[row + col * kQrW] = acc[t][q];
-    }
+    for (int t = 0; t < FJ; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = wi + 16 * a + 4 * q + (lane >> 4);
+        const int64_t col = c0 + wc + 16 * t + (lane & 15);
+        if (col < N) out[row + col * LDW] = acc[a][t][q];
+      }
 }
 
-// W = sum of the chunk partials, in chunk order (32 x N, column-major).
-__global__ void k_qr_reduce(int64_t N, int nchunk, const double* __restrict__ part, double* __restrict__ Wm) {
+// W = sum of the chunk partials, in chunk order (ldw x N, column-major).
+__global__ void k_qr_reduce(int64_t N, int ldw, int nchunk, const double* __restrict__ part, double* __restrict__ Wm) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)kQrW * N) return;
+  if (e >= (int64_t)ldw * N) return;
   double t = 0.0;
-  for (int c = 0; c < nchunk; ++c) t += part[(int64_t)c * kQrW * N + e];
+  for (int c = 0; c < nchunk; ++c) t += part[(int64_t)c * ldw * N + e];
   Wm[e] = t;
+}
+
+// -T^T of the compact WY form of up to 128 reflectors (the 128-column outer
+// block), from G = V^T V (128 x 128) and tau (b values): T[j][j] = tau_j,
+// T[:j, j] = -tau_j T[:j, :j] G[:j, j], one column after the other, then
+// written transposed and negated (128 x 128, column-major) for the product
+// W := T^T W = 0 - (-T^T) W on the GEMM.
+__global__ __launch_bounds__(kQrNB) void k_qr_larft_big(int b, const double* __restrict__ Gm,
+                                                        const double* __restrict__ tau, double* __restrict__ Tneg) {
+  __shared__ double sT[kQrNB][kQrNB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kQrNB * kQrNB; e += kQrNB) sT[e % kQrNB][e / kQrNB] = 0.0;
+  __syncthreads();
+  for (int j = 0; j < b; ++j) {
+    const double tj = tau[j];
+    double t = 0.0;
+    if (tid < j) {
+      for (int l = tid; l < j; ++l) t += sT[tid][l] * Gm[l + j * kQrNB];
+      t = -tj * t;
+    }
+    __syncthreads();
+    if (tid < j) sT[tid][j] = t;
+    if (tid == j) sT[j][j] = tj;
+    __syncthreads();
+  }
+  // Tneg[i][l] = -T[l][i]
+  for (int e = tid; e < kQrNB * kQrNB; e += kQrNB) {
+    const int i = e % kQrNB, l = e / kQrNB;
+    Tneg[e] = -sT[l][i];
+  }
+}
+
+__global__ void k_qr_zero(int64_t count, double* __restrict__ x) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
+    x[e] = 0.0;
 }
 
 // T of the compact WY form from G = V^T V (32 x 32) and tau (b values, the
@@ -364,16 +442,20 @@ int64_t tn_chunks(int64_t r, int64_t N) {
   return ch < 1 ? 1 : ch;
 }
 
+// out (ldw x N) = V^T X for V of ldw (32 or 128) columns.
 hipError_t tn(hipStream_t s, int64_t r, int64_t N, const double* V, int64_t ldv, const double* X, int64_t ldx,
-              double* part, double* out) {
+              int ldw, double* part, double* out) {
   const int64_t ch = tn_chunks(r, N);
   int64_t rpc = (r + ch - 1) / ch;
   rpc = (rpc + kTnK - 1) / kTnK * kTnK;
   const int64_t nch = (r + rpc - 1) / rpc;
-  hipLaunchKernelGGL(k_qr_tn, dim3((unsigned)((N + kTnCols - 1) / kTnCols), (unsigned)nch), dim3(256), 0, s, r, N, V,
-                     ldv, X, ldx, rpc, part);
-  const int64_t tot = (int64_t)kQrW * N;
-  hipLaunchKernelGGL(k_qr_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, N, (int)nch, part, out);
+  const dim3 grid((unsigned)((N + kTnCols - 1) / kTnCols), (unsigned)nch);
+  if (ldw == kQrNB)
+    hipLaunchKernelGGL(k_qr_tn<kQrNB>, grid, dim3(256), 0, s, r, N, V, ldv, X, ldx, rpc, part);
+  else
+    hipLaunchKernelGGL(k_qr_tn<kQrW>, grid, dim3(256), 0, s, r, N, V, ldv, X, ldx, rpc, part);
+  const int64_t tot = (int64_t)ldw * N;
+  hipLaunchKernelGGL(k_qr_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, N, ldw, (int)nch, part, out);
   return hipGetLastError();
 }
 
@@ -387,10 +469,13 @@ void free_qr(lupp_handle_t h) {
   h->qr = nullptr;
 }
 
+// Vbig (m x 128), G and -T^T (128 x 128 each), G32 and T32, W and W2
+// (128 x n each), the chunk partials (at most 512 / tiles + 1 chunks of
+// ldw x N with tiles = N / 64, so at most 128 x (32768 + n) values).
 size_t qr_workspace_bytes(int64_t m, int64_t n) {
-  const int64_t chmax = 512;
-  return sizeof(QrSlots) + sizeof(double) * (size_t)((int64_t)kQrW * m + 3 * kQrW * kQrW + kQrW * n +
-                                                     chmax * kQrW * (n > kQrW ? n : kQrW) + 64);
+  const int64_t nn = n > kQrNB ? n : kQrNB;
+  return sizeof(QrSlots) + sizeof(double) * (size_t)((int64_t)kQrNB * m + 2 * kQrNB * kQrNB + 2 * kQrW * kQrW +
+                                                     2 * kQrNB * nn + kQrNB * (32768 + nn) + 256);
 }
 
 namespace {
@@ -421,45 +506,80 @@ hipError_t ensure_qr(lupp_handle_t h, int64_t m, int64_t n) {
 }  // namespace
 
 // P = A (m x n, in place): R on and above the diagonal, the Householder
-// vectors below it, tau[min(m, n)].
+// vectors below it, tau[min(m, n)].  Outer blocks of 128 columns: each is
+// factored as four 32-column blocks (the panel kernel, and the compact WY
+// update of the block's remaining columns), then the trailing columns get one
+// 128-column compact WY update: W = V^T A2, W := T^T W, A2 -= V W.
 hipError_t geqrf(lupp_handle_t h, int64_t m, int64_t n, double* A, int64_t lda, double* tau) {
   const int64_t k = m < n ? m : n;
   if (k == 0) return hipSuccess;
   LUPP_TRY(ensure_qr(h, m, n));
   QrWs* q = h->qr;
   hipStream_t s = h->stream;
-  double* Vb = q->buf;                       // m x 32
-  double* Gm = Vb + (int64_t)kQrW * m;       // 32 x 32
-  double* Tm = Gm + kQrW * kQrW;             // 32 x 32
-  double* Wm = Tm + kQrW * kQrW;             // 32 x n
-  double* part = Wm + (int64_t)kQrW * n + kQrW * kQrW;
-  for (int64_t j0 = 0; j0 < k; j0 += kQrW) {
-    const int b = (int)((k - j0 < kQrW) ? (k - j0) : kQrW);
+  const int64_t nn = n > kQrNB ? n : kQrNB;
+  double* Vb = q->buf;                        // m x 128 (ld r of the outer block)
+  double* Gb = Vb + (int64_t)kQrNB * m;       // 128 x 128
+  double* Tn = Gb + kQrNB * kQrNB;            // 128 x 128: -T^T
+  double* G32 = Tn + kQrNB * kQrNB;           // 32 x 32
+  double* T32 = G32 + kQrW * kQrW;            // 32 x 32
+  double* Wm = T32 + kQrW * kQrW;             // 128 x n
+  double* W2 = Wm + (int64_t)kQrNB * nn;      // 128 x n
+  double* part = W2 + (int64_t)kQrNB * nn;
+  for (int64_t j0 = 0; j0 < k; j0 += kQrNB) {
+    const int64_t B = (k - j0 < kQrNB) ? (k - j0) : kQrNB;
     const int64_t r = m - j0;
-    const int G = (int)((r + kQrThreads - 1) / kQrThreads);
-    if (G > kQrMaxGroups) return hipErrorInvalidValue;
-    if (q->epoch > 0xF0000000u) {
-      hipLaunchKernelGGL(k_qr_reset, dim3(1), dim3(256), 0, s, q->slots);
+    const int64_t n2 = n - j0 - B;
+    if (n2 > 0) {  // the outer block's V, zero above each panel's rows
+      const int64_t cnt = r * kQrNB;
+      hipLaunchKernelGGL(k_qr_zero, dim3((unsigned)((cnt + 255) / 256 < 4096 ? (cnt + 255) / 256 : 4096)), dim3(256), 0,
+                         s, cnt, Vb);
       LUPP_TRY(hipGetLastError());
-      q->epoch = 0;
     }
-    const int t = timer_begin(h, LUPP_PHASE_PANEL, s);
-    hipLaunchKernelGGL(k_qr_panel<kQrThreads>, dim3(G), dim3(kQrThreads), 0, s, r, b, A + j0 + j0 * lda, lda,
-                       tau + j0, Vb, r, q->slots, q->epoch);
-    LUPP_TRY(hipGetLastError());
-    timer_end(h, t, s, 0.0);
-    q->epoch += (uint32_t)b + 1u;
-    const int64_t n2 = n - j0 - b;
+    for (int64_t p0 = 0; p0 < B; p0 += kQrW) {
+      const int b = (int)((B - p0 < kQrW) ? (B - p0) : kQrW);
+      const int64_t c = j0 + p0, rp = m - c;
+      const int G = (int)((rp + kQrThreads - 1) / kQrThreads);
+      if (G > kQrMaxGroups) return hipErrorInvalidValue;
+      if (q->epoch > 0xF0000000u) {
+        hipLaunchKernelGGL(k_qr_reset, dim3(1), dim3(256), 0, s, q->slots);
+        LUPP_TRY(hipGetLastError());
+        q->epoch = 0;
+      }
+      double* Vp = Vb + p0 + p0 * r;  // this panel's V: rows p0.., columns p0.. of the outer block's V (ld r)
+      const int t = timer_begin(h, LUPP_PHASE_PANEL, s);
+      hipLaunchKernelGGL(k_qr_panel<kQrThreads>, dim3(G), dim3(kQrThreads), 0, s, rp, b, A + c + c * lda, lda, tau + c,
+                         Vp, r, q->slots, q->epoch);
+      LUPP_TRY(hipGetLastError());
+      timer_end(h, t, s, 0.0);
+      q->epoch += (uint32_t)b + 1u;
+      // the outer block's remaining columns (or, for a last outer block with
+      // no trailing columns, every column right of the panel)
+      const int64_t ce = (n2 > 0) ? j0 + B : n;
+      const int64_t nb2 = ce - c - b;
+      if (nb2 <= 0) continue;
+      double* Ab = A + c + (c + b) * lda;
+      const int tu = timer_begin(h, LUPP_PHASE_PANEL_GEMM, s);
+      LUPP_TRY(tn(s, rp, kQrW, Vp, r, Vp, r, kQrW, part, G32));
+      hipLaunchKernelGGL(k_qr_larft, dim3(1), dim3(64), 0, s, b, G32, tau + c, T32);
+      LUPP_TRY(tn(s, rp, nb2, Vp, r, Ab, lda, kQrW, part, Wm));
+      hipLaunchKernelGGL(k_qr_trmm, dim3((unsigned)((nb2 + 255) / 256)), dim3(256), 0, s, nb2, T32, Wm);
+      LUPP_TRY(hipGetLastError());
+      LUPP_TRY(gemm_sub<double>(s, rp, nb2, kQrW, Vp, r, Wm, kQrW, Ab, lda, nullptr, 2));
+      timer_end(h, tu, s, 4.0 * (double)rp * (double)nb2 * (double)b);
+    }
     if (n2 <= 0) continue;
-    double* A2 = A + j0 + (j0 + b) * lda;
+    double* A2 = A + j0 + (j0 + B) * lda;
     const int tu = timer_begin(h, LUPP_PHASE_UPDATE, s);
-    LUPP_TRY(tn(s, r, kQrW, Vb, r, Vb, r, part, Gm));
-    hipLaunchKernelGGL(k_qr_larft, dim3(1), dim3(64), 0, s, b, Gm, tau + j0, Tm);
-    LUPP_TRY(tn(s, r, n2, Vb, r, A2, lda, part, Wm));
-    hipLaunchKernelGGL(k_qr_trmm, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, n2, Tm, Wm);
+    LUPP_TRY(tn(s, r, kQrNB, Vb, r, Vb, r, kQrNB, part, Gb));
+    hipLaunchKernelGGL(k_qr_larft_big, dim3(1), dim3(kQrNB), 0, s, (int)B, Gb, tau + j0, Tn);
+    LUPP_TRY(tn(s, r, n2, Vb, r, A2, lda, kQrNB, part, Wm));
+    const int64_t cnt = (int64_t)kQrNB * n2;
+    hipLaunchKernelGGL(k_qr_zero, dim3((unsigned)((cnt + 255) / 256 < 4096 ? (cnt + 255) / 256 : 4096)), dim3(256), 0, s,
+                       cnt, W2);
     LUPP_TRY(hipGetLastError());
-    LUPP_TRY(gemm_sub<double>(s, r, n2, kQrW, Vb, r, Wm, kQrW, A2, lda, nullptr, 0));
-    timer_end(h, tu, s, 4.0 * (double)r * (double)n2 * (double)b);
+    LUPP_TRY(gemm_sub<double>(s, kQrNB, n2, kQrNB, Tn, kQrNB, Wm, kQrNB, W2, kQrNB, nullptr, 2));  // W2 = T^T W
+    LUPP_TRY(gemm_sub<double>(s, r, n2, kQrNB, Vb, r, W2, kQrNB, A2, lda, nullptr, 0));           // A2 -= V W2
+    timer_end(h, tu, s, 4.0 * (double)r * (double)n2 * (double)B);
   }
   return hipSuccess;
 }
