@@ -444,6 +444,38 @@ int lupp_sgetrf_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const
  */
 int lupp_dgeqrf(lupp_handle_t h, int64_t m, int64_t n, double* dA, int64_t lda, double* dtau);
 
+/*
+ * Randomized UTV factorization (randUTV, the paper's Section 3.2) of a square
+ * n x n FP64 matrix: A = U T V^T with U, V orthogonal and T upper triangular,
+ * built b = 64 columns at a time.  With T22 = T[k0:, k0:] at step i
+ * (k0 = 64 i):
+ *   1. Y = (T22^T T22)^q T22^T G_i, G_i = G[k0:, k0:k0+64] (the Gaussian draws
+ *      are an input: G is n x n, device); Householder QR of Y (as
+ *      lupp_dgeqrf); T[:, k0:] and V[:, k0:] multiplied by its Q from the
+ *      right;
+ *   2. Householder QR of T22's first 64 columns, Q^T applied to T22 (entries
+ *      below the diagonal become exactly 0), U[:, k0:] times Q;
+ *   3. SVD of the 64 x 64 diagonal block (one-sided Jacobi, singular values in
+ *      decreasing order): the block becomes diag(sigma), Us^T multiplies the
+ *      block row right of it, Vs the block column above it, U and V get Us
+ *      and Vs.
+ * The last step, with at most 64 columns left, is step 3 on the whole block.
+ * The diagonal of T approximates the singular values of A (the better, the
+ * larger q).
+ *   dA  device n x n, lda >= max(1, n): A on entry, T on return
+ *   q   power steps, 0 .. 16
+ *   dG  device n x n, ldg >= max(1, n), read only
+ *   dU, dV  device n x n (ldu, ldv >= max(1, n)), written; either may be NULL
+ *           (that factor is then not formed)
+ * Singular vectors of each small SVD are fixed up to sign, so T's rows and
+ * columns and U's and V's columns are determined up to sign.  Asynchronous on
+ * the handle's stream; workspace in the handle (about 8 n x 64 + n x 128
+ * values beside the QR path's).  Size limit: n <= 131072.
+ * Errors: -2 n, -3 dA, -4 lda, -5 q, -6 dG, -7 ldg, -9 ldu, -11 ldv.
+ */
+int lupp_drandutv(lupp_handle_t h, int64_t n, double* dA, int64_t lda, int32_t q, const double* dG, int64_t ldg,
+                  double* dU, int64_t ldu, double* dV, int64_t ldv);
+
 #ifdef __cplusplus
 }
 #endif

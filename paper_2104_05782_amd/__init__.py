@@ -26,6 +26,8 @@ from ._binding import (  # noqa: F401
     lupp_sgetrs,
     getrf,
     geqrf,
+    randutv,
+    lupp_drandutv,
     lupp_dgeqrf,
     getrs,
     gesv_batched,

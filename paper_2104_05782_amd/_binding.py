@@ -28,6 +28,7 @@ _lib.lupp_status_string.restype = ctypes.c_char_p
 for _name in ("lupp_dgetrf", "lupp_sgetrf"):
     getattr(_lib, _name).argtypes = [_vp, _i64, _i64, _vp, _i64, _vp, _vp]
 _lib.lupp_dgeqrf.argtypes = [_vp, _i64, _i64, _vp, _i64, _vp]
+_lib.lupp_drandutv.argtypes = [_vp, _i64, _vp, _i64, ctypes.c_int32, _vp, _i64, _vp, _i64, _vp, _i64]
 for _name in ("lupp_dgetrs", "lupp_sgetrs"):
     getattr(_lib, _name).argtypes = [_vp, _char, _i64, _i64, _vp, _i64, _vp, _vp, _i64]
 
@@ -412,6 +413,36 @@ def geqrf(A: torch.Tensor, handle: Handle | None = None) -> torch.Tensor:
     tau = torch.empty(max(1, min(m, n)), dtype=torch.float64, device=A.device)
     lupp_dgeqrf(A, tau, handle)
     return tau[:min(m, n)]
+
+
+def lupp_drandutv(A, G, q: int, U=None, V=None, handle: Handle | None = None):
+    """randUTV in place of column-major float64 A (n x n) -> T; U and V
+    (column-major n x n float64, or None) receive the orthogonal factors; G
+    (n x n) holds the Gaussian draws."""
+    n = A.shape[0]
+    _dev(A, torch.float64, "A")
+    _dev(G, torch.float64, "G")
+    if A.shape != (n, n) or G.shape[0] < n or G.shape[1] < n:
+        raise ValueError("A must be n x n and G at least n x n")
+    for X, what in ((U, "U"), (V, "V")):
+        if X is not None:
+            _dev(X, torch.float64, what)
+            if X.shape != (n, n):
+                raise ValueError("%s must be n x n" % what)
+    h = _prep(handle)
+    _check(_lib.lupp_drandutv(h.ptr, n, A.data_ptr(), _lead(A), int(q), G.data_ptr(), _lead(G),
+                              U.data_ptr() if U is not None else None, _lead(U) if U is not None else 1,
+                              V.data_ptr() if V is not None else None, _lead(V) if V is not None else 1),
+           "lupp_drandutv")
+
+
+def randutv(A: torch.Tensor, G: torch.Tensor, q: int = 1, handle: Handle | None = None):
+    """(U, T, V) of A = U T V^T (A is overwritten by T and returned as T)."""
+    n = A.shape[0]
+    U = torch.empty((n, n), dtype=torch.float64, device=A.device).t()
+    V = torch.empty((n, n), dtype=torch.float64, device=A.device).t()
+    lupp_drandutv(A, G, q, U, V, handle)
+    return U, A, V
 
 
 def getrf(A: torch.Tensor, handle: Handle | None = None):

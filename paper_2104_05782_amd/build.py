@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "liblupp.so")
-SOURCES = ["lupp.hip", "mixed.hip", "gemm.hip", "gemm_lp.hip", "panel.hip", "aux.hip", "trsm.hip", "refine.hip", "batched.hip", "qr.hip"]
+SOURCES = ["lupp.hip", "mixed.hip", "gemm.hip", "gemm_lp.hip", "panel.hip", "aux.hip", "trsm.hip", "refine.hip", "batched.hip", "qr.hip", "utv.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", INCLUDE, "-I", CSRC]

@@ -15,6 +15,7 @@ struct TimingRecord {
 };
 struct MixedWs;
 struct BatchWs;
+struct UtvWs;
 // Workspace of the QR path: the panel's exchange records, the explicit V,
 // G, T, W and the partials of the row-chunked products.
 struct QrWs {
@@ -22,6 +23,7 @@ struct QrWs {
   uint32_t epoch = 0;
   double* buf = nullptr;
   size_t bytes = 0;
+  int64_t m = 0, n = 0;  // the shape the buffer layout is set for (last ensure_qr)
 };
 }  // namespace lupp
 
@@ -74,6 +76,7 @@ struct lupp_handle_st {
   lupp::MixedWs* mixed = nullptr;   // workspace of lupp_dgesv_mixed
   lupp::BatchWs* batch = nullptr;   // workspace and streams of the batched path
   lupp::QrWs* qr = nullptr;         // workspace of the Householder QR
+  lupp::UtvWs* utv = nullptr;       // workspace of randUTV
 };
 
 namespace lupp {
@@ -105,9 +108,22 @@ hipError_t getrs(lupp_handle_t h, int64_t n, int64_t nrhs, const T* LU, int64_t 
 void free_mixed(lupp_handle_t h);
 void free_batched(lupp_handle_t h);
 void free_qr(lupp_handle_t h);
+void free_utv(lupp_handle_t h);
 // Householder QR of an m x n matrix on the handle's stream (arguments checked).
 hipError_t geqrf(lupp_handle_t h, int64_t m, int64_t n, double* A, int64_t lda, double* tau);
 size_t qr_workspace_bytes(int64_t m, int64_t n);
+// QR workspace laid out for an m x n problem (grown on demand).
+hipError_t ensure_qr(lupp_handle_t h, int64_t m, int64_t n);
+// One 128-column outer block of the Householder QR (see qr.hip); V (r x 128,
+// ld r) at qr_v(h) and -T^T (128 x 128) at qr_tneg(h) afterwards.
+hipError_t qr_outer(lupp_handle_t h, int64_t r, int64_t ncols, double* A, int64_t lda, double* tau, int64_t B,
+                    bool keep_wy);
+// out (ldw x N) = V^T X, V r x ldw (ldw 32, 64 or 128); part: chunk partials.
+hipError_t qr_tn(hipStream_t s, int64_t r, int64_t N, const double* V, int64_t ldv, const double* X, int64_t ldx,
+                 int ldw, double* part, double* out);
+inline double* qr_v(lupp_handle_t h);
+inline double* qr_tneg(lupp_handle_t h);
+inline double* qr_part(lupp_handle_t h);
 int timer_begin(lupp_handle_t h, int phase, hipStream_t st);
 void timer_end(lupp_handle_t h, int idx, hipStream_t st, double flops, bool big = false, double bytes = 0.0);
 // Batched path set-up at handle creation: class streams and events, grids, and
@@ -127,4 +143,15 @@ size_t getrf_workspace_bytes(lupp_handle_t h, int64_t m, int64_t n, size_t elem)
 size_t trsv_workspace_bytes(int64_t n);
 size_t mixed_workspace_bytes(int64_t n, int64_t restart);
 size_t batch_workspace_bytes(int64_t batch);
+}  // namespace lupp
+
+namespace lupp {
+// Views into the QR workspace (layout of qr_outer: V, G, -T^T, G32, T32, W,
+// W2, chunk partials).
+inline double* qr_v(lupp_handle_t h) { return h->qr->buf; }
+inline double* qr_tneg(lupp_handle_t h) { return h->qr->buf + 128 * h->qr->m + 128 * 128; }
+inline double* qr_part(lupp_handle_t h) {
+  const int64_t nn = h->qr->n > 128 ? h->qr->n : 128;
+  return h->qr->buf + 128 * h->qr->m + 2 * 128 * 128 + 2 * 32 * 32 + 2 * 128 * nn;
+}
 }  // namespace lupp

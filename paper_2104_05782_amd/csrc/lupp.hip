@@ -812,6 +812,7 @@ int lupp_destroy(lupp_handle_t h) {
   lupp::free_mixed(h);
   lupp::free_batched(h);
   lupp::free_qr(h);
+  lupp::free_utv(h);
   delete h;
   return rc;
 }

@@ -249,8 +249,8 @@ __global__ __launch_bounds__(256) void k_qr_tn(int64_t r, int64_t N, const doubl
                                                const double* __restrict__ X, int64_t ldx, int64_t rows_per_chunk,
                                                double* __restrict__ part) {
   typedef Mfma<double> MF;
-  constexpr int WR = LDW == 128 ? 32 : 16;  // rows of W per wavefront
-  constexpr int WC = LDW == 128 ? 64 : 32;  // columns per wavefront
+  constexpr int WR = LDW >= 64 ? LDW / 4 : 16;  // rows of W per wavefront
+  constexpr int WC = LDW >= 64 ? 64 : 32;       // columns per wavefront
   constexpr int FI = WR / 16, FJ = WC / 16;
   constexpr int EV = kTnK * LDW / 256, EX = kTnK * kTnCols / 256;
   __shared__ double sV[2][kTnK][LDW + 1];
@@ -260,8 +260,8 @@ __global__ __launch_bounds__(256) void k_qr_tn(int64_t r, int64_t N, const doubl
   const int64_t chunk = blockIdx.y;
   const int64_t r0 = chunk * rows_per_chunk;
   const int64_t r1 = (r0 + rows_per_chunk < r) ? r0 + rows_per_chunk : r;
-  const int wi = LDW == 128 ? 32 * wave : (wave & 1) * 16;
-  const int wc = LDW == 128 ? 0 : (wave >> 1) * 32;
+  const int wi = LDW >= 64 ? WR * wave : (wave & 1) * 16;
+  const int wc = LDW >= 64 ? 0 : (wave >> 1) * 32;
   MF::v4 acc[FI][FJ];
 #pragma unroll
   for (int a = 0; a < FI; ++a)
@@ -442,8 +442,10 @@ int64_t tn_chunks(int64_t r, int64_t N) {
   return ch < 1 ? 1 : ch;
 }
 
-// out (ldw x N) = V^T X for V of ldw (32 or 128) columns.
-hipError_t tn(hipStream_t s, int64_t r, int64_t N, const double* V, int64_t ldv, const double* X, int64_t ldx,
+}  // namespace
+
+// out (ldw x N) = V^T X for V of ldw (32, 64 or 128) columns.
+hipError_t qr_tn(hipStream_t s, int64_t r, int64_t N, const double* V, int64_t ldv, const double* X, int64_t ldx,
               int ldw, double* part, double* out) {
   const int64_t ch = tn_chunks(r, N);
   int64_t rpc = (r + ch - 1) / ch;
@@ -452,12 +454,16 @@ hipError_t tn(hipStream_t s, int64_t r, int64_t N, const double* V, int64_t ldv,
   const dim3 grid((unsigned)((N + kTnCols - 1) / kTnCols), (unsigned)nch);
   if (ldw == kQrNB)
     hipLaunchKernelGGL(k_qr_tn<kQrNB>, grid, dim3(256), 0, s, r, N, V, ldv, X, ldx, rpc, part);
+  else if (ldw == 64)
+    hipLaunchKernelGGL(k_qr_tn<64>, grid, dim3(256), 0, s, r, N, V, ldv, X, ldx, rpc, part);
   else
     hipLaunchKernelGGL(k_qr_tn<kQrW>, grid, dim3(256), 0, s, r, N, V, ldv, X, ldx, rpc, part);
   const int64_t tot = (int64_t)ldw * N;
   hipLaunchKernelGGL(k_qr_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, N, ldw, (int)nch, part, out);
   return hipGetLastError();
 }
+
+namespace {
 
 }  // namespace
 
@@ -480,6 +486,8 @@ size_t qr_workspace_bytes(int64_t m, int64_t n) {
 
 namespace {
 
+}  // namespace
+
 hipError_t ensure_qr(lupp_handle_t h, int64_t m, int64_t n) {
   if (!h->qr) {
     h->qr = new (std::nothrow) QrWs();
@@ -500,10 +508,91 @@ hipError_t ensure_qr(lupp_handle_t h, int64_t m, int64_t n) {
     LUPP_TRY(hipMalloc(&q->buf, need));
     q->bytes = need;
   }
+  q->m = m;
+  q->n = n;
   return hipSuccess;
 }
 
-}  // namespace
+
+// One outer block: factor the first B <= 128 columns of the r x ncols
+// matrix A (32-column blocks with their compact WY updates inside the outer
+// block) and apply Q^T to the columns B .. ncols-1 with one 128-column
+// compact WY update.  Leaves in the workspace the outer block's V (r x 128,
+// explicit: unit diagonal, zeros above, zero columns beyond B) and -T^T of
+// its compact WY form (128 x 128) whenever there are trailing columns or
+// keep_wy is set.
+hipError_t qr_outer(lupp_handle_t h, int64_t r, int64_t ncols, double* A, int64_t lda, double* tau, int64_t B,
+                    bool keep_wy) {
+  QrWs* q = h->qr;
+  hipStream_t s = h->stream;
+  const int64_t m = q->m, n = q->n;
+  const int64_t nn = n > kQrNB ? n : kQrNB;
+  double* Vb = q->buf;                        // m x 128 (ld r of the outer block)
+  double* Gb = Vb + (int64_t)kQrNB * m;       // 128 x 128
+  double* Tn = Gb + kQrNB * kQrNB;            // 128 x 128: -T^T
+  double* G32 = Tn + kQrNB * kQrNB;           // 32 x 32
+  double* T32 = G32 + kQrW * kQrW;            // 32 x 32
+  double* Wm = T32 + kQrW * kQrW;             // 128 x n
+  double* W2 = Wm + (int64_t)kQrNB * nn;      // 128 x n
+  double* part = W2 + (int64_t)kQrNB * nn;
+  const int64_t n2 = ncols - B;
+  const bool wy = n2 > 0 || keep_wy;
+  if (wy) {  // the outer block's V, zero above each panel's rows
+    const int64_t cnt = r * kQrNB;
+    hipLaunchKernelGGL(k_qr_zero, dim3((unsigned)((cnt + 255) / 256 < 4096 ? (cnt + 255) / 256 : 4096)), dim3(256), 0,
+                       s, cnt, Vb);
+    LUPP_TRY(hipGetLastError());
+  }
+  for (int64_t p0 = 0; p0 < B; p0 += kQrW) {
+    const int b = (int)((B - p0 < kQrW) ? (B - p0) : kQrW);
+    const int64_t rp = r - p0;
+    const int G = (int)((rp + kQrThreads - 1) / kQrThreads);
+    if (G > kQrMaxGroups) return hipErrorInvalidValue;
+    if (q->epoch > 0xF0000000u) {
+      hipLaunchKernelGGL(k_qr_reset, dim3(1), dim3(256), 0, s, q->slots);
+      LUPP_TRY(hipGetLastError());
+      q->epoch = 0;
+    }
+    double* Vp = Vb + p0 + p0 * r;  // this panel's V: rows p0.., columns p0.. of the outer block's V (ld r)
+    const int t = timer_begin(h, LUPP_PHASE_PANEL, s);
+    hipLaunchKernelGGL(k_qr_panel<kQrThreads>, dim3(G), dim3(kQrThreads), 0, s, rp, b, A + p0 + p0 * lda, lda,
+                       tau + p0, Vp, r, q->slots, q->epoch);
+    LUPP_TRY(hipGetLastError());
+    timer_end(h, t, s, 0.0);
+    q->epoch += (uint32_t)b + 1u;
+    // the outer block's remaining columns (or, for an outer block with no
+    // trailing columns, every column right of the panel)
+    const int64_t ce = (n2 > 0) ? B : ncols;
+    const int64_t nb2 = ce - p0 - b;
+    if (nb2 <= 0) continue;
+    double* Ab = A + p0 + (p0 + b) * lda;
+    const int tu = timer_begin(h, LUPP_PHASE_PANEL_GEMM, s);
+    LUPP_TRY(qr_tn(s, rp, kQrW, Vp, r, Vp, r, kQrW, part, G32));
+    hipLaunchKernelGGL(k_qr_larft, dim3(1), dim3(64), 0, s, b, G32, tau + p0, T32);
+    LUPP_TRY(qr_tn(s, rp, nb2, Vp, r, Ab, lda, kQrW, part, Wm));
+    hipLaunchKernelGGL(k_qr_trmm, dim3((unsigned)((nb2 + 255) / 256)), dim3(256), 0, s, nb2, T32, Wm);
+    LUPP_TRY(hipGetLastError());
+    LUPP_TRY(gemm_sub<double>(s, rp, nb2, kQrW, Vp, r, Wm, kQrW, Ab, lda, nullptr, 2));
+    timer_end(h, tu, s, 4.0 * (double)rp * (double)nb2 * (double)b);
+  }
+  if (!wy) return hipSuccess;
+  const int tu = timer_begin(h, LUPP_PHASE_UPDATE, s);
+  LUPP_TRY(qr_tn(s, r, kQrNB, Vb, r, Vb, r, kQrNB, part, Gb));
+  hipLaunchKernelGGL(k_qr_larft_big, dim3(1), dim3(kQrNB), 0, s, (int)B, Gb, tau, Tn);
+  LUPP_TRY(hipGetLastError());
+  if (n2 > 0) {
+    double* A2 = A + B * lda;
+    LUPP_TRY(qr_tn(s, r, n2, Vb, r, A2, lda, kQrNB, part, Wm));
+    const int64_t cnt = (int64_t)kQrNB * n2;
+    hipLaunchKernelGGL(k_qr_zero, dim3((unsigned)((cnt + 255) / 256 < 4096 ? (cnt + 255) / 256 : 4096)), dim3(256), 0, s,
+                       cnt, W2);
+    LUPP_TRY(hipGetLastError());
+    LUPP_TRY(gemm_sub<double>(s, kQrNB, n2, kQrNB, Tn, kQrNB, Wm, kQrNB, W2, kQrNB, nullptr, 2));  // W2 = T^T W
+    LUPP_TRY(gemm_sub<double>(s, r, n2, kQrNB, Vb, r, W2, kQrNB, A2, lda, nullptr, 0));           // A2 -= V W2
+  }
+  timer_end(h, tu, s, 4.0 * (double)r * (double)n2 * (double)B);
+  return hipSuccess;
+}
 
 // P = A (m x n, in place): R on and above the diagonal, the Householder
 // vectors below it, tau[min(m, n)].  Outer blocks of 128 columns: each is
@@ -514,72 +603,9 @@ hipError_t geqrf(lupp_handle_t h, int64_t m, int64_t n, double* A, int64_t lda, 
   const int64_t k = m < n ? m : n;
   if (k == 0) return hipSuccess;
   LUPP_TRY(ensure_qr(h, m, n));
-  QrWs* q = h->qr;
-  hipStream_t s = h->stream;
-  const int64_t nn = n > kQrNB ? n : kQrNB;
-  double* Vb = q->buf;                        // m x 128 (ld r of the outer block)
-  double* Gb = Vb + (int64_t)kQrNB * m;       // 128 x 128
-  double* Tn = Gb + kQrNB * kQrNB;            // 128 x 128: -T^T
-  double* G32 = Tn + kQrNB * kQrNB;           // 32 x 32
-  double* T32 = G32 + kQrW * kQrW;            // 32 x 32
-  double* Wm = T32 + kQrW * kQrW;             // 128 x n
-  double* W2 = Wm + (int64_t)kQrNB * nn;      // 128 x n
-  double* part = W2 + (int64_t)kQrNB * nn;
   for (int64_t j0 = 0; j0 < k; j0 += kQrNB) {
     const int64_t B = (k - j0 < kQrNB) ? (k - j0) : kQrNB;
-    const int64_t r = m - j0;
-    const int64_t n2 = n - j0 - B;
-    if (n2 > 0) {  // the outer block's V, zero above each panel's rows
-      const int64_t cnt = r * kQrNB;
-      hipLaunchKernelGGL(k_qr_zero, dim3((unsigned)((cnt + 255) / 256 < 4096 ? (cnt + 255) / 256 : 4096)), dim3(256), 0,
-                         s, cnt, Vb);
-      LUPP_TRY(hipGetLastError());
-    }
-    for (int64_t p0 = 0; p0 < B; p0 += kQrW) {
-      const int b = (int)((B - p0 < kQrW) ? (B - p0) : kQrW);
-      const int64_t c = j0 + p0, rp = m - c;
-      const int G = (int)((rp + kQrThreads - 1) / kQrThreads);
-      if (G > kQrMaxGroups) return hipErrorInvalidValue;
-      if (q->epoch > 0xF0000000u) {
-        hipLaunchKernelGGL(k_qr_reset, dim3(1), dim3(256), 0, s, q->slots);
-        LUPP_TRY(hipGetLastError());
-        q->epoch = 0;
-      }
-      double* Vp = Vb + p0 + p0 * r;  // this panel's V: rows p0.., columns p0.. of the outer block's V (ld r)
-      const int t = timer_begin(h, LUPP_PHASE_PANEL, s);
-      hipLaunchKernelGGL(k_qr_panel<kQrThreads>, dim3(G), dim3(kQrThreads), 0, s, rp, b, A + c + c * lda, lda, tau + c,
-                         Vp, r, q->slots, q->epoch);
-      LUPP_TRY(hipGetLastError());
-      timer_end(h, t, s, 0.0);
-      q->epoch += (uint32_t)b + 1u;
-      // the outer block's remaining columns (or, for a last outer block with
-      // no trailing columns, every column right of the panel)
-      const int64_t ce = (n2 > 0) ? j0 + B : n;
-      const int64_t nb2 = ce - c - b;
-      if (nb2 <= 0) continue;
-      double* Ab = A + c + (c + b) * lda;
-      const int tu = timer_begin(h, LUPP_PHASE_PANEL_GEMM, s);
-      LUPP_TRY(tn(s, rp, kQrW, Vp, r, Vp, r, kQrW, part, G32));
-      hipLaunchKernelGGL(k_qr_larft, dim3(1), dim3(64), 0, s, b, G32, tau + c, T32);
-      LUPP_TRY(tn(s, rp, nb2, Vp, r, Ab, lda, kQrW, part, Wm));
-      hipLaunchKernelGGL(k_qr_trmm, dim3((unsigned)((nb2 + 255) / 256)), dim3(256), 0, s, nb2, T32, Wm);
-      LUPP_TRY(hipGetLastError());
-      LUPP_TRY(gemm_sub<double>(s, rp, nb2, kQrW, Vp, r, Wm, kQrW, Ab, lda, nullptr, 2));
-      timer_end(h, tu, s, 4.0 * (double)rp * (double)nb2 * (double)b);
-    }
-    if (n2 <= 0) continue;
-    double* A2 = A + j0 + (j0 + B) * lda;
-    const int tu = timer_begin(h, LUPP_PHASE_UPDATE, s);
-    LUPP_TRY(tn(s, r, kQrNB, Vb, r, Vb, r, kQrNB, part, Gb));
-    hipLaunchKernelGGL(k_qr_larft_big, dim3(1), dim3(kQrNB), 0, s, (int)B, Gb, tau + j0, Tn);
-    LUPP_TRY(tn(s, r, n2, Vb, r, A2, lda, kQrNB, part, Wm));
-    const int64_t cnt = (int64_t)kQrNB * n2;
-    hipLaunchKernelGGL(k_qr_zero, dim3((unsigned)((cnt + 255) / 256 < 4096 ? (cnt + 255) / 256 : 4096)), dim3(256), 0, s,
-                       cnt, W2);
-    LUPP_TRY(hipGetLastError());
-    LUPP_TRY(gemm_sub<double>(s, kQrNB, n2, kQrNB, Tn, kQrNB, Wm, kQrNB, W2, kQrNB, nullptr, 2));  // W2 = T^T W
-    LUPP_TRY(gemm_sub<double>(s, r, n2, kQrNB, Vb, r, W2, kQrNB, A2, lda, nullptr, 0));           // A2 -= V W2
-    timer_end(h, tu, s, 4.0 * (double)r * (double)n2 * (double)B);
+    LUPP_TRY(qr_outer(h, m - j0, n - j0, A + j0 + j0 * lda, lda, tau + j0, B, false));
   }
   return hipSuccess;
 }

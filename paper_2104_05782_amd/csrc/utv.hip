@@ -1,0 +1,384 @@
+// Randomized UTV factorization (randUTV, the paper's Section 3.2): A = U T V^T
+// for a square A, U and V orthogonal, T upper triangular, built b = 64 columns
+// at a time.  Step i (k0 = i b, T22 = T[k0:, k0:]):
+//   V_alpha: Y = (T22^T T22)^q T22^T G_i (matrix products: G_i^T T22 and
+//            P^T T22 on the transposed-product kernel of the QR path, T22 Y on
+//            the GEMM), then the Householder QR of Y; T[:, k0:] and V[:, k0:]
+//            are multiplied by its Q from the right;
+//   U_alpha: the Householder QR of T22's first b columns, applied to the rest
+//            of T22 (the QR path's outer block), and U[:, k0:] times its Q;
+//   U_beta, V_beta: the SVD of the b x b diagonal block (one-sided Jacobi in
+//            one workgroup), which becomes diag(sigma); Us^T and Vs go to the
+//            block row and column of T, Us to U, Vs to V.
+// Products with Q = I - V T V^T from the right are X Q = X - ((X V) T) V^T,
+// three GEMMs.  The Gaussian draws are an input (G, n x n: step i uses
+// G[k0:, k0:k0+b]), so the method's random numbers come from the caller.
+#include "handle.h"
+#include "wave.h"
+
+namespace lupp {
+
+namespace {
+
+constexpr int kUtvB = 64;  // block size b
+constexpr int kUtvMaxSweeps = 40;
+
+// dst (cols x rows, ldd) = scale * src^T (src rows x cols, lds)
+__global__ void k_utv_transpose(int64_t rows, int64_t cols, const double* __restrict__ src, int64_t lds,
+                                double* __restrict__ dst, int64_t ldd, double scale) {
+  __shared__ double t[32][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 32, c0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 8 rows of 32
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t r = r0 + tx, c = c0 + j;
+    t[j][tx] = (r < rows && c < cols) ? src[r + c * lds] : 0.0;
+  }
+  __syncthreads();
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t c = c0 + tx, r = r0 + j;  // dst(c, r) = src(r, c)
+    if (r < rows && c < cols) dst[c + r * ldd] = scale * t[tx][j];
+  }
+}
+
+// dst (rows x cols) = scale * src
+__global__ void k_utv_scale_copy(int64_t rows, int64_t cols, const double* __restrict__ src, int64_t lds,
+                                 double* __restrict__ dst, int64_t ldd, double scale) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e % rows, c = e / rows;
+    dst[r + c * ldd] = scale * src[r + c * lds];
+  }
+}
+
+__global__ void k_utv_fill(int64_t rows, int64_t cols, double* __restrict__ x, int64_t ld, double v) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+    x[e % rows + (e / rows) * ld] = v;
+}
+
+// the strictly lower part of the first w columns of a rows x w block := 0
+__global__ void k_utv_zero_lower(int64_t rows, int w, double* __restrict__ x, int64_t ld) {
+  const int64_t total = rows * w;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e % rows, c = e / rows;
+    if (r > c) x[r + c * ld] = 0.0;
+  }
+}
+
+// The w x w block (w <= 64) := diag(sigma)
+__global__ void k_utv_set_diag(int w, const double* __restrict__ sigma, double* __restrict__ x, int64_t ld) {
+  for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
+    const int r = e % w, c = e / w;
+    x[r + (int64_t)c * ld] = (r == c) ? sigma[r] : 0.0;
+  }
+}
+
+__device__ __forceinline__ double xsum(double v, int lane) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)u, m, 64);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(u >> 32), m, 64);
+    v += __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+  }
+  (void)lane;
+  return v;
+}
+
+// SVD of a w x w block M (w <= 64, ld) by one-sided Jacobi (Hestenes): the
+// columns of M are rotated in pairs until they are mutually orthogonal,
+// M Vs = Us diag(sigma); the same rotations accumulate Vs.  Pairs follow a
+// round-robin tournament (32 disjoint pairs per round, 63 rounds per sweep;
+// columns beyond w are zero and never rotated with another); a pair is rotated
+// when |a_p . a_q| > 1e-15 sqrt(|a_p|^2 |a_q|^2), with tan(theta) from
+// zeta = (|a_q|^2 - |a_p|^2) / (2 a_p . a_q).  Sweeps stop when no pair was
+// rotated (at most 40).  Then sigma_j = |a_j|, sorted decreasing (ties by
+// index), Us[:, j] = a_j / sigma_j (0 when sigma_j = 0).  One workgroup of 256
+// threads: each wavefront takes 8 pairs of a round, lane = row.
+__global__ __launch_bounds__(256) void k_utv_svd(int w, const double* __restrict__ M, int64_t ld,
+                                                 double* __restrict__ sigma, double* __restrict__ Us,
+                                                 double* __restrict__ Vs, int* __restrict__ sweeps_out) {
+  constexpr int B = kUtvB;
+  __shared__ double sA[B][B + 1];  // [column][row]
+  __shared__ double sV[B][B + 1];
+  __shared__ double s_norm[B];
+  __shared__ int s_perm[B];
+  __shared__ int s_rot;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < B * B; e += 256) {
+    const int r = e % B, c = e / B;
+    sA[c][r] = (r < w && c < w) ? M[r + (int64_t)c * ld] : 0.0;
+    sV[c][r] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  int sweep = 0;
+  for (; sweep < kUtvMaxSweeps; ++sweep) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int round = 0; round < B - 1; ++round) {
+      for (int kk = 0; kk < 8; ++kk) {
+        const int k = wave * 8 + kk;
+        int p, q;
+        if (k == 0) {
+          p = round;
+          q = B - 1;
+        } else {
+          p = (round + k) % (B - 1);
+          q = (round - k + (B - 1)) % (B - 1);
+        }
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        const double ap = sA[p][lane], aq = sA[q][lane];
+        const double al = xsum(ap * ap, lane), be = xsum(aq * aq, lane), ga = xsum(ap * aq, lane);
+        if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+          sA[p][lane] = c * ap - sn * aq;
+          sA[q][lane] = sn * ap + c * aq;
+          const double vp = sV[p][lane], vq = sV[q][lane];
+          sV[p][lane] = c * vp - sn * vq;
+          sV[q][lane] = sn * vp + c * vq;
+          if (lane == 0) s_rot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int rot = s_rot;
+    __syncthreads();
+    if (!rot) break;
+  }
+  if (tid < B) {
+    double t = 0.0;
+    for (int r = 0; r < B; ++r) t += sA[tid][r] * sA[tid][r];
+    s_norm[tid] = sqrt(t);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int j = 0; j < B; ++j) s_perm[j] = j;
+    for (int j = 0; j < w; ++j) {  // selection by decreasing norm, lowest index on ties
+      int best = j;
+      for (int l = j + 1; l < w; ++l)
+        if (s_norm[s_perm[l]] > s_norm[s_perm[best]]) best = l;
+      const int t = s_perm[j];
+      s_perm[j] = s_perm[best];
+      s_perm[best] = t;
+    }
+    if (sweeps_out) *sweeps_out = sweep;
+  }
+  __syncthreads();
+  for (int e = tid; e < B * B; e += 256) {
+    const int r = e % B, j = e / B;
+    const int c = s_perm[j];
+    const double sg = s_norm[c];
+    Us[r + j * B] = (j < w && r < w && sg > 0.0) ? sA[c][r] / sg : 0.0;
+    Vs[r + j * B] = (j < w && r < w) ? sV[c][r] : 0.0;
+    if (r == 0 && j < w) sigma[j] = sg;
+  }
+}
+
+inline unsigned grid_for(int64_t count) {
+  const int64_t g = (count + 255) / 256;
+  return (unsigned)(g < 4096 ? (g > 0 ? g : 1) : 4096);
+}
+
+}  // namespace
+
+// Workspace of randUTV (beyond the QR path's): Y and P (n x 64), Z (64 x n),
+// the right-application products (n x 128 twice, 128 x n), T's positive form
+// (128 x 128), the SVD outputs and the block-product staging (n x 64).
+struct UtvWs {
+  double* buf = nullptr;
+  size_t bytes = 0;
+};
+
+namespace {
+
+struct UtvBufs {
+  double *Y, *P, *Z, *XV, *M, *Vt, *Tp, *sig, *Us, *Vs, *NUsT, *tmp, *tau;
+  int* sweeps;
+};
+
+hipError_t ensure_utv(lupp_handle_t h, int64_t n, UtvBufs* b) {
+  const int64_t B = kUtvB;
+  const size_t need = sizeof(double) * (size_t)(2 * n * B + B * n + 2 * n * 128 + 128 * n + 128 * 128 + B +
+                                                3 * B * B + n * B + 128 + 64);
+  if (!h->utv) {
+    h->utv = new (std::nothrow) UtvWs();
+    if (!h->utv) return hipErrorOutOfMemory;
+  }
+  if (need > h->utv->bytes) {
+    LUPP_TRY(hipStreamSynchronize(h->stream));
+    if (h->utv->buf) (void)hipFree(h->utv->buf);
+    h->utv->buf = nullptr;
+    h->utv->bytes = 0;
+    void* p = nullptr;
+    LUPP_TRY(hipMalloc(&p, need));
+    h->utv->buf = (double*)p;
+    h->utv->bytes = need;
+  }
+  double* x = h->utv->buf;
+  b->Y = x;
+  x += n * B;
+  b->P = x;
+  x += n * B;
+  b->Z = x;
+  x += B * n;
+  b->XV = x;
+  x += n * 128;
+  b->M = x;
+  x += n * 128;
+  b->Vt = x;
+  x += 128 * n;
+  b->Tp = x;
+  x += 128 * 128;
+  b->sig = x;
+  x += B;
+  b->Us = x;
+  x += B * B;
+  b->Vs = x;
+  x += B * B;
+  b->NUsT = x;
+  x += B * B;
+  b->tmp = x;
+  x += n * B;
+  b->tau = x;
+  x += 128;
+  b->sweeps = (int*)x;
+  return hipSuccess;
+}
+
+// X (rows x r, ldx) := X Q with Q = I - V T V^T the compact WY form left by
+// qr_outer (V: r x kb at qr_v, ld r; -T^T at qr_tneg, ld 128), kb = 64 or 128:
+// X V, then (X V) T, then X -= ((X V) T) V^T.
+hipError_t right_apply(lupp_handle_t h, const UtvBufs& b, int64_t rows, int64_t r, double* X, int64_t ldx, int kb,
+                       bool prepared) {
+  hipStream_t s = h->stream;
+  const double* V = qr_v(h);
+  if (!prepared) {  // T = -(-T^T)^T and V^T, once per Q
+    hipLaunchKernelGGL(k_utv_transpose, dim3(4, 4), dim3(256), 0, s, (int64_t)128, (int64_t)128, qr_tneg(h),
+                       (int64_t)128, b.Tp, (int64_t)128, -1.0);
+    hipLaunchKernelGGL(k_utv_transpose, dim3((unsigned)((r + 31) / 32), (unsigned)((kb + 31) / 32)), dim3(256), 0, s,
+                       r, (int64_t)kb, V, r, b.Vt, (int64_t)kb, 1.0);
+    LUPP_TRY(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_utv_fill, dim3(grid_for(rows * kb)), dim3(256), 0, s, rows, (int64_t)kb, b.XV, rows, 0.0);
+  hipLaunchKernelGGL(k_utv_fill, dim3(grid_for(rows * kb)), dim3(256), 0, s, rows, (int64_t)kb, b.M, rows, 0.0);
+  LUPP_TRY(hipGetLastError());
+  LUPP_TRY(gemm_sub<double>(s, rows, kb, r, X, ldx, V, r, b.XV, rows, nullptr, 2));      // XV = -X V
+  LUPP_TRY(gemm_sub<double>(s, rows, kb, kb, b.XV, rows, b.Tp, 128, b.M, rows, nullptr, 2));  // M = X V T
+  LUPP_TRY(gemm_sub<double>(s, rows, r, kb, b.M, rows, b.Vt, kb, X, ldx, nullptr, 2));  // X -= M V^T
+  return hipSuccess;
+}
+
+}  // namespace
+
+void free_utv(lupp_handle_t h) {
+  if (!h->utv) return;
+  if (h->utv->buf) (void)hipFree(h->utv->buf);
+  delete h->utv;
+  h->utv = nullptr;
+}
+
+// A (n x n) := T; U, V (n x n) formed when non-null; G: n x n Gaussian draws.
+hipError_t randutv(lupp_handle_t h, int64_t n, double* A, int64_t lda, int q, const double* G, int64_t ldg,
+                   double* U, int64_t ldu, double* V, int64_t ldv) {
+  constexpr int64_t B = kUtvB;
+  hipStream_t s = h->stream;
+  LUPP_TRY(ensure_qr(h, n, n));
+  UtvBufs b;
+  LUPP_TRY(ensure_utv(h, n, &b));
+  double* part = qr_part(h);
+  auto identity = [&](double* X, int64_t ld) -> hipError_t {
+    hipLaunchKernelGGL(k_utv_fill, dim3(grid_for(n * n)), dim3(256), 0, s, n, n, X, ld, 0.0);
+    hipLaunchKernelGGL(k_utv_fill, dim3(grid_for(n)), dim3(256), 0, s, (int64_t)1, n, X, ld + 1, 1.0);
+    return hipGetLastError();
+  };
+  if (U) LUPP_TRY(identity(U, ldu));
+  if (V) LUPP_TRY(identity(V, ldv));
+  // X (rows x w) := X Y (Y w x w, ld 64) through the GEMM: tmp = 0 - X (-Y)
+  auto times = [&](double* X, int64_t ldx, int64_t rows, int w, const double* Ysmall) -> hipError_t {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_utv_scale_copy, dim3(grid_for(B * B)), dim3(256), 0, s, B, B, Ysmall, B, b.XV, B, -1.0);
+    hipLaunchKernelGGL(k_utv_fill, dim3(grid_for(rows * w)), dim3(256), 0, s, rows, (int64_t)w, b.tmp, rows, 0.0);
+    LUPP_TRY(hipGetLastError());
+    LUPP_TRY(gemm_sub<double>(s, rows, w, w, X, ldx, b.XV, B, b.tmp, rows, nullptr, 2));
+    hipLaunchKernelGGL(k_utv_scale_copy, dim3(grid_for(rows * w)), dim3(256), 0, s, rows, (int64_t)w, b.tmp, rows, X,
+                       ldx, 1.0);
+    return hipGetLastError();
+  };
+  for (int64_t k0 = 0; k0 < n; k0 += B) {
+    const int64_t nr = n - k0;
+    double* T22 = A + k0 + k0 * lda;
+    int w = (int)B;
+    if (nr > B) {
+      // ---- V_alpha: the sketch Y = (T22^T T22)^q T22^T G_i, nr x 64
+      LUPP_TRY(qr_tn(s, nr, nr, G + k0 + k0 * ldg, ldg, T22, lda, 64, part, b.Z));  // Z = G_i^T T22
+      hipLaunchKernelGGL(k_utv_transpose, dim3(2, (unsigned)((nr + 31) / 32)), dim3(256), 0, s, B, nr, b.Z, B, b.Y,
+                         nr, 1.0);
+      LUPP_TRY(hipGetLastError());
+      for (int it = 0; it < q; ++it) {
+        hipLaunchKernelGGL(k_utv_fill, dim3(grid_for(nr * B)), dim3(256), 0, s, nr, B, b.P, nr, 0.0);
+        LUPP_TRY(hipGetLastError());
+        LUPP_TRY(gemm_sub<double>(s, nr, B, nr, T22, lda, b.Y, nr, b.P, nr, nullptr, 2));  // P = -T22 Y
+        LUPP_TRY(qr_tn(s, nr, nr, b.P, nr, T22, lda, 64, part, b.Z));                     // Z = P^T T22
+        hipLaunchKernelGGL(k_utv_transpose, dim3(2, (unsigned)((nr + 31) / 32)), dim3(256), 0, s, B, nr, b.Z, B, b.Y,
+                           nr, -1.0);  // Y = -Z^T = T22^T T22 Y
+        LUPP_TRY(hipGetLastError());
+      }
+      // Householder QR of Y; T[:, k0:] and V[:, k0:] times its Q
+      LUPP_TRY(qr_outer(h, nr, B, b.Y, nr, b.tau, B, true));
+      LUPP_TRY(right_apply(h, b, n, nr, A + k0 * lda, lda, 64, false));
+      if (V) LUPP_TRY(right_apply(h, b, n, nr, V + k0 * ldv, ldv, 64, true));
+      // ---- U_alpha: Householder QR of T22's first 64 columns, applied to
+      // the rest of T22; U[:, k0:] times its Q; the block column below the
+      // diagonal (the reflectors) becomes 0
+      LUPP_TRY(qr_outer(h, nr, nr, T22, lda, b.tau, B, true));
+      if (U) LUPP_TRY(right_apply(h, b, n, nr, U + k0 * ldu, ldu, 64, false));
+      hipLaunchKernelGGL(k_utv_zero_lower, dim3(grid_for(nr * B)), dim3(256), 0, s, nr, (int)B, T22, lda);
+      LUPP_TRY(hipGetLastError());
+    } else {
+      w = (int)nr;
+    }
+    // ---- U_beta, V_beta: SVD of the w x w diagonal block
+    hipLaunchKernelGGL(k_utv_svd, dim3(1), dim3(256), 0, s, w, T22, lda, b.sig, b.Us, b.Vs, b.sweeps);
+    hipLaunchKernelGGL(k_utv_transpose, dim3(2, 2), dim3(256), 0, s, B, B, b.Us, B, b.NUsT, B, -1.0);  // -Us^T
+    hipLaunchKernelGGL(k_utv_set_diag, dim3(1), dim3(256), 0, s, w, b.sig, T22, lda);
+    LUPP_TRY(hipGetLastError());
+    const int64_t nright = n - k0 - w;
+    if (nright > 0) {  // T[k0:k0+w, k0+w:] := Us^T T[k0:k0+w, k0+w:]
+      double* X = T22 + w * lda;
+      hipLaunchKernelGGL(k_utv_fill, dim3(grid_for(w * nright)), dim3(256), 0, s, (int64_t)w, nright, b.tmp, B, 0.0);
+      LUPP_TRY(hipGetLastError());
+      LUPP_TRY(gemm_sub<double>(s, w, nright, w, b.NUsT, B, X, lda, b.tmp, B, nullptr, 2));  // tmp = Us^T X
+      hipLaunchKernelGGL(k_utv_scale_copy, dim3(grid_for(w * nright)), dim3(256), 0, s, (int64_t)w, nright, b.tmp, B,
+                         X, lda, 1.0);
+      LUPP_TRY(hipGetLastError());
+    }
+    LUPP_TRY(times(A + k0 * lda, lda, k0, w, b.Vs));       // T[:k0, k0:k0+w] := T[:k0, k0:k0+w] Vs
+    if (U) LUPP_TRY(times(U + k0 * ldu, ldu, n, w, b.Us));  // U[:, k0:k0+w] := U[:, k0:k0+w] Us
+    if (V) LUPP_TRY(times(V + k0 * ldv, ldv, n, w, b.Vs));  // V[:, k0:k0+w] := V[:, k0:k0+w] Vs
+  }
+  return hipSuccess;
+}
+
+}  // namespace lupp
+
+extern "C" int lupp_drandutv(lupp_handle_t h, int64_t n, double* dA, int64_t lda, int32_t q, const double* dG,
+                             int64_t ldg, double* dU, int64_t ldu, double* dV, int64_t ldv) {
+  if (!h) return -1;
+  if (n < 0 || n > 131072) return -2;
+  if (!dA && n > 0) return -3;
+  if (lda < (n > 1 ? n : 1)) return -4;
+  if (q < 0 || q > 16) return -5;
+  if (!dG && n > 0) return -6;
+  if (ldg < (n > 1 ? n : 1)) return -7;
+  if (dU && ldu < (n > 1 ? n : 1)) return -9;
+  if (dV && ldv < (n > 1 ? n : 1)) return -11;
+  if (n == 0) return LUPP_OK;
+  const hipError_t e = lupp::randutv(h, n, dA, lda, q, dG, ldg, dU, ldu, dV, ldv);
+  return e == hipErrorOutOfMemory ? LUPP_ERR_ALLOC : lupp::hip_status(e);
+}
