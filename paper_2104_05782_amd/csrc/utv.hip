@@ -93,9 +93,10 @@ __device__ __forceinline__ double xsum(double v, int lane) {
 // when |a_p . a_q| > 1e-15 sqrt(|a_p|^2 |a_q|^2), with tan(theta) from
 // zeta = (|a_q|^2 - |a_p|^2) / (2 a_p . a_q).  Sweeps stop when no pair was
 // rotated (at most 40).  Then sigma_j = |a_j|, sorted decreasing (ties by
-// index), Us[:, j] = a_j / sigma_j (0 when sigma_j = 0).  One workgroup of 256
-// threads: each wavefront takes 8 pairs of a round, lane = row.
-__global__ __launch_bounds__(256) void k_utv_svd(int w, const double* __restrict__ M, int64_t ld,
+// index), Us[:, j] = a_j / sigma_j (0 when sigma_j = 0).  One workgroup of 1024
+// threads: each of the 16 wavefronts takes 2 pairs of a round, lane = row.
+constexpr int kSvdThreads = 1024;
+__global__ __launch_bounds__(kSvdThreads) void k_utv_svd(int w, const double* __restrict__ M, int64_t ld,
                                                  double* __restrict__ sigma, double* __restrict__ Us,
                                                  double* __restrict__ Vs, int* __restrict__ sweeps_out) {
   constexpr int B = kUtvB;
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(256) void k_utv_svd(int w, const double* __restrict
   __shared__ int s_perm[B];
   __shared__ int s_rot;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < B * B; e += 256) {
+  for (int e = tid; e < B * B; e += kSvdThreads) {
     const int r = e % B, c = e / B;
     sA[c][r] = (r < w && c < w) ? M[r + (int64_t)c * ld] : 0.0;
     sV[c][r] = (r == c) ? 1.0 : 0.0;
@@ -116,8 +117,8 @@ __global__ __launch_bounds__(256) void k_utv_svd(int w, const double* __restrict
     if (tid == 0) s_rot = 0;
     __syncthreads();
     for (int round = 0; round < B - 1; ++round) {
-      for (int kk = 0; kk < 8; ++kk) {
-        const int k = wave * 8 + kk;
+      for (int kk = 0; kk < 2; ++kk) {
+        const int k = wave * 2 + kk;
         int p, q;
         if (k == 0) {
           p = round;
@@ -170,7 +171,7 @@ __global__ __launch_bounds__(256) void k_utv_svd(int w, const double* __restrict
     if (sweeps_out) *sweeps_out = sweep;
   }
   __syncthreads();
-  for (int e = tid; e < B * B; e += 256) {
+  for (int e = tid; e < B * B; e += kSvdThreads) {
     const int r = e % B, j = e / B;
     const int c = s_perm[j];
     const double sg = s_norm[c];
@@ -344,7 +345,7 @@ hipError_t randutv(lupp_handle_t h, int64_t n, double* A, int64_t lda, int q, co
       w = (int)nr;
     }
     // ---- U_beta, V_beta: SVD of the w x w diagonal block
-    hipLaunchKernelGGL(k_utv_svd, dim3(1), dim3(256), 0, s, w, T22, lda, b.sig, b.Us, b.Vs, b.sweeps);
+    hipLaunchKernelGGL(k_utv_svd, dim3(1), dim3(kSvdThreads), 0, s, w, T22, lda, b.sig, b.Us, b.Vs, b.sweeps);
     hipLaunchKernelGGL(k_utv_transpose, dim3(2, 2), dim3(256), 0, s, B, B, b.Us, B, b.NUsT, B, -1.0);  // -Us^T
     hipLaunchKernelGGL(k_utv_set_diag, dim3(1), dim3(256), 0, s, w, b.sig, T22, lda);
     LUPP_TRY(hipGetLastError());
