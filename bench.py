@@ -55,6 +55,11 @@ The JSON line carries:
   qr          Householder QR (lupp_dgeqrf, compact WY) at n = 4096, 8192,
               16384: TFLOP/s on 4/3 n^3, column-block and update time, probe
               residual of Q R x against A x
+  randutv     randUTV (lupp_drandutv, block 64) at n = 2048, 4096, 8192 and
+              q = 0, 1, 2 (and q = 1 with U and V formed): times; at n = 2048
+              the identity A = U T V^T, orthogonality and diag(T) against the
+              singular values; the vendor SVD's time at n = 2048 as labelled
+              context (the paper's comparison point)
   large       n = 65536 (diagonally dominant recipe drawn on the device): plain FP64
               factorization + solve against the FP8-update GMRES-IR solve (wall
               times, effective TFLOP/s, backward errors, forward error against
@@ -495,6 +500,61 @@ def qr_leg(torch, lupp, seed, sizes=(4096, 8192, 16384)):
     return out
 
 
+def utv_leg(torch, lupp, seed, sizes=(2048, 4096, 8192), qs=(0, 1, 2)):
+    """randUTV (lupp_drandutv, b = 64) of A iid U(-1,1) drawn on the device,
+    Gaussian draws G from torch's generator: best of two calls per (n, q),
+    T only and (q = 1) with U and V formed; at n = 2048 the diagonal of T
+    against the singular values from torch.linalg.svdvals (rocSOLVER, a
+    labelled run-only comparison) and the identity A = U T V^T."""
+    runs = []
+    for n in sizes:
+        g = torch.Generator(device="cuda").manual_seed(seed + 7 * n)
+        A0 = torch.empty((n, n), dtype=torch.float64, device="cuda").t().uniform_(-1.0, 1.0, generator=g)
+        G = torch.empty((n, n), dtype=torch.float64, device="cuda").t().normal_(generator=g)
+        A = torch.empty_like(A0.t()).t()
+        U = torch.empty_like(A0.t()).t()
+        V = torch.empty_like(A0.t()).t()
+        h = lupp.Handle()
+        for q, uv in [(q, False) for q in qs] + [(1, True)]:
+            ts = []
+            for r in range(2):
+                A.copy_(A0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                lupp.lupp_drandutv(A, G, q, U if uv else None, V if uv else None, h)
+                h.sync()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            rec = {"n": n, "q": q, "uv": uv, "ms": round(min(ts) * 1e3, 2)}
+            if uv and n <= 2048:
+                s_ref = torch.linalg.svdvals(A0)
+                d = torch.diagonal(A)
+                rec["identity_scaled_residual"] = float((U @ A @ V.t() - A0).abs().max() /
+                                                        (n * 2.0 ** -53 * A0.abs().sum(0).max()))
+                rec["orthogonality_U"] = float((U.t() @ U - torch.eye(n, dtype=torch.float64, device="cuda")).abs().max())
+                rec["diag_T_vs_svdvals_max_rel_first_64"] = float(((d[:64] - s_ref[:64]).abs() / s_ref[:64]).max())
+                rec["diag_T_vs_svdvals_max_rel_all"] = float(((d - s_ref).abs() / s_ref).max())
+            runs.append(rec)
+        h.close()
+        del A, A0, G, U, V
+        torch.cuda.empty_cache()
+    # the vendor SVD at the smallest size, as labelled context (the paper's comparison point)
+    n = sizes[0]
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    A0 = torch.empty((n, n), dtype=torch.float64, device="cuda").uniform_(-1.0, 1.0, generator=g)
+    torch.linalg.svdvals(A0[:256, :256])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    torch.linalg.svd(A0)
+    torch.cuda.synchronize()
+    svd_ms = (time.perf_counter() - t0) * 1e3
+    out = {"workload": "randUTV, block 64, A iid U(-1,1) (device-drawn), G iid N(0,1); best of 2", "runs": runs,
+           "context_torch_linalg_svd_ms": {"n": n, "ms": round(svd_ms, 1),
+                                            "note": "rocSOLVER through torch, U S V^T formed; run only"}}
+    log("randutv: %s" % out)
+    return out
+
+
 def large_leg(torch, lupp, n, seed):
     """FP8-update GMRES-IR solve against plain FP64 LUPP + solve at a large n,
     on the diagonally dominant recipe drawn on the device (torch's seeded
@@ -683,6 +743,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the large mixed-precision leg")
     ap.add_argument("--no-dataflow", action="store_true", help="skip the dataflow-runtime leg")
     ap.add_argument("--no-qr", action="store_true", help="skip the Householder QR leg")
+    ap.add_argument("--no-utv", action="store_true", help="skip the randUTV leg")
     ap.add_argument("--no-c2", action="store_true", help="skip the FP64/FP32 size sweep")
     ap.add_argument("--no-kappa", action="store_true", help="skip the kappa (n=4096) mixed-precision leg")
     ap.add_argument("--large-n", type=int, default=65536)
@@ -852,6 +913,13 @@ def main():
         log("qr leg")
         qrres = qr_leg(torch, lupp, args.seed)
 
+    utvres = None
+    if not args.no_utv and not args.profile_once:
+        A = None
+        torch.cuda.empty_cache()
+        log("randutv leg")
+        utvres = utv_leg(torch, lupp, args.seed)
+
     batched = None
     if not args.no_batched:
         log("batched leg")
@@ -896,6 +964,7 @@ def main():
         "large": large,
         "dataflow": dataflow,
         "qr": qrres,
+        "randutv": utvres,
     }
     print(json.dumps(out), flush=True)
     h.close()
