@@ -80,7 +80,7 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
-TRAFFIC_RATIO_FP64_GEMM = 1.729  # HBM bytes / algorithmic bytes, k_dgemm_sub_16 role 0, n = 24576 counters
+TRAFFIC_RATIO_FP64_GEMM = 1.797  # HBM bytes / algorithmic bytes, k_dgemm_sub_16 role 0, n = 24576 counters
 
 
 def log(msg):
@@ -817,7 +817,9 @@ def main():
         step()
         torch.cuda.synchronize()
         log("warmup %d done" % w)
-    h.set_option(3, 1)  # record phase events during the timed steps
+    # events around the trailing updates during the timed steps (the roofline
+    # kernel's launch durations); the column-block chain stays uninstrumented
+    h.set_option(3, 2)
     h.timing_summary("panel", reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -830,16 +832,12 @@ def main():
     flops = 2.0 / 3.0 * float(n) ** 3
     value = flops / (ms_per_step * 1e-3) / 1e12
     log("timed %d steps: %.2f ms/step, %.2f TFLOP/s" % (args.steps, ms_per_step, value))
-    phases = {}
-    for ph in ("panel", "laswp", "trsm", "update", "update_big", "panel_leaf", "panel_swap", "panel_trsm", "panel_gemm"):
-        c, ms, fl = h.timing_summary(ph)
-        phases[ph] = {"launches": c, "ms_per_step": ms / args.steps, "flops": fl / args.steps}
     alg_bytes = h.timing_bytes("update_big")
     c, ms, fl = h.timing_summary("update_big", reset=True)
     peak = FP64_PEAK_TFLOPS if args.dtype == "f64" else FP32_PEAK_TFLOPS
     achieved = (fl / (ms * 1e-3) / 1e12) if ms > 0 else 0.0
     # HBM traffic of this kernel: the calibrated FETCH_SIZE + WRITE_SIZE of its
-    # launches over their algorithmic bytes, 1.729 at n = 24576 (the largest
+    # launches over their algorithmic bytes, 1.797 at n = 24576 (the largest
     # size at which the profiler's counter mode has run; profiles/
     # lupp_n24576_counters.md), applied to this run's algorithmic bytes per launch
     traffic = None
@@ -850,10 +848,22 @@ def main():
                 "traffic_note": ("bytes per launch: %.3f x the algorithmic bytes (C read and written, A and B read once; "
                                  "%.4g per launch here), the ratio measured at n = 24576" %
                                  (TRAFFIC_RATIO_FP64_GEMM, alg_bytes / max(1, c))) if traffic else None,
-                "kernel": ("k_dgemm_sub_16<128,128,8,2,2,2,0>" if args.dtype == "f64" else "k_gemm_sub<float,128,128,16,2,2,2>"),
+                "kernel": ("k_dgemm_sub_16<128,128,8,2,4,4,0>" if args.dtype == "f64" else "k_gemm_sub<float,128,128,16,2,2,2>"),
                 "launches_per_step": c // max(1, args.steps),
                 "avg_launch_ms": round(ms / max(1, c), 4),
                 "flops_per_launch": fl / max(1, c)}
+    # the phase breakdown, from one more step with every phase instrumented
+    # (after the timed region: its events slow the column-block chain by ~3%)
+    phases = {}
+    if not args.profile_once:
+        h.set_option(3, 1)
+        step()
+        for ph in ("panel", "laswp", "trsm", "update", "update_big", "panel_leaf", "panel_swap", "panel_trsm",
+                   "panel_gemm"):
+            pc, pms, pfl = h.timing_summary(ph)
+            phases[ph] = {"launches": pc, "ms_per_step": pms, "flops": pfl}
+        h.timing_summary("panel", reset=True)
+        phases["note"] = "one step after the timed region, every phase bracketed by HIP events"
     h.set_option(3, 0)
 
     dataflow = None

@@ -60,7 +60,10 @@ enum {
   LUPP_OPT_PANEL_LEAF = 2, /* widest column block factored in one cooperative launch
                               (16 .. 256, a multiple of 16; default 128); wider blocks
                               split recursively with a triangular solve and a GEMM      */
-  LUPP_OPT_TIMING = 3,     /* 1: record HIP events around every phase of xGETRF (below)    */
+  LUPP_OPT_TIMING = 3,     /* 1: record HIP events around every phase of xGETRF (below);
+                              2: around the trailing updates only (LUPP_PHASE_UPDATE and
+                              LUPP_PHASE_UPDATE_BIG), which leaves the latency-bound
+                              column-block chain uninstrumented                           */
   LUPP_OPT_LOOKAHEAD = 4,  /* lookahead depth d (0..16).  1 (default): factor the next
                               column block on a second stream while the trailing update
                               runs; 0: one stream, in order.  d >= 2: the dataflow
@@ -117,8 +120,9 @@ enum {
 /* Create a handle on the current HIP device.  The handle owns its workspace
  * (allocated on first use, freed by lupp_destroy) and borrows a stream
  * (default: the null stream).  Creation itself allocates no device memory: it
- * creates the batched path's streams and events and looks up the device
- * address of lupp_dgesv_batched_noalloc's scratch array on this device.
+ * looks up the device address of lupp_dgesv_batched_noalloc's scratch array
+ * on this device.  The first batched call on a handle creates the handle's
+ * class streams and events (no device memory).
  * Errors: -1 if h is NULL. */
 int lupp_create(lupp_handle_t* h);
 
@@ -360,7 +364,9 @@ int lupp_sgesv_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const 
  * lupp_dgesv_batched, but the class list and counters live in a fixed array
  * of the library (about 4 MiB per device, held until the process ends)
  * instead of handle workspace, so no call allocates or frees device memory
- * (the handle's streams were created by lupp_create).
+ * (the handle's first batched call creates its class streams, which is not a
+ * device allocation; a caller that captures graphs can make a first call
+ * outside the capture).
  *   batch <= 1048576 (LUPP_NOALLOC_MAX_BATCH); a larger batch returns
  *   LUPP_ERR_UNSUPPORTED before anything is launched.
  * Every call on one device shares that device's array: calls that may

@@ -635,7 +635,8 @@ hipError_t ensure_batch_list(lupp_handle_t h, int64_t batch) {
   if (!w) return hipErrorNotInitialized;
   if (batch <= w->capacity && w->list) return hipSuccess;
   LUPP_TRY(hipStreamSynchronize(h->stream));
-  for (int c = 0; c < kMaxClasses; ++c) LUPP_TRY(hipStreamSynchronize(w->streams[c]));
+  for (int c = 0; c < kMaxClasses; ++c)
+    if (w->streams[c]) LUPP_TRY(hipStreamSynchronize(w->streams[c]));
   if (w->list) (void)hipFree(w->list);
   w->list = nullptr;
   w->capacity = 0;
@@ -651,11 +652,25 @@ hipError_t ensure_batch_list(lupp_handle_t h, int64_t batch) {
 // Binning and the per-class launches on the handle's class streams (forked
 // from and joined to the handle's stream), with the class list and counters
 // at list / meta.  Launches only: no allocation, no host synchronization.
+// The class streams and their events, once per handle (no device memory).
+hipError_t ensure_class_streams(BatchWs* w) {
+  if (w->fork) return hipSuccess;
+  for (int c = 0; c < kMaxClasses; ++c) {
+    LUPP_TRY(hipStreamCreateWithFlags(&w->streams[c], hipStreamNonBlocking));
+    LUPP_TRY(hipEventCreateWithFlags(&w->join[c], hipEventDisableTiming));
+  }
+  return hipEventCreateWithFlags(&w->fork, hipEventDisableTiming);
+}
+
 template <typename T>
 int launch_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_t* aoff, T* A, const int64_t* poff,
                    int32_t* piv, const int64_t* boff, T* B, int32_t* info, int32_t* list, int32_t* meta) {
   BatchWs* w = h->batch;
   hipStream_t s = h->stream;
+  {
+    const hipError_t es = ensure_class_streams(w);
+    if (es != hipSuccess) return hip_status(es);
+  }
   const int prec = sizeof(T) == 8 ? 0 : 1;
   const Schedule& sc = w->sched[prec];
   ClassBounds cb{};
@@ -698,19 +713,16 @@ int gesv_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const int64_
 
 }  // namespace
 
-// At handle creation, on the handle's device: the class streams and events,
-// the persistent grids, and the device address of the scratch array.  No
-// device memory is allocated here.
+// At handle creation, on the handle's device: the persistent grids, the
+// schedules, and the device address of the scratch array.  No device memory
+// is allocated here; the class streams are created by the first batched call
+// (ensure_class_streams), so that a handle that never runs the batched path
+// holds no streams for it.
 hipError_t setup_batched(lupp_handle_t h) {
   LUPP_TRY(lookup_scratch(h->device));
   BatchWs* w = new (std::nothrow) BatchWs();
   if (!w) return hipErrorOutOfMemory;
   h->batch = w;
-  for (int c = 0; c < kMaxClasses; ++c) {
-    LUPP_TRY(hipStreamCreateWithFlags(&w->streams[c], hipStreamNonBlocking));
-    LUPP_TRY(hipEventCreateWithFlags(&w->join[c], hipEventDisableTiming));
-  }
-  LUPP_TRY(hipEventCreateWithFlags(&w->fork, hipEventDisableTiming));
   LUPP_TRY(setup_shape_occupancy<double>(h, w, 0));
   LUPP_TRY(setup_shape_occupancy<float>(h, w, 1));
   w->sched[0] = default_schedule(0);

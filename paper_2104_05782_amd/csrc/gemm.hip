@@ -167,11 +167,14 @@ __global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_gemm_sub(int64_t M, int
 
 // FP64 C -= A * B on v_mfma_f64_16x16x4f64: double-buffered LDS, peeled K
 // loop, accumulators started from -C, interior tiles unmasked.  Each
-// wavefront owns a WTM x WTN tile of 16x16 products (16 independent
-// accumulators for a 64x64 tile, enough to keep the matrix core busy with two
+// wavefront owns a WTM x WTN tile of 16x16 products (8 independent
+// accumulators for the 64x32 tile of the 8-wavefront 128x128 launch, four
 // wavefronts per SIMD).  The operands are passed swapped (B first), so each
 // lane holds 16 consecutive rows of a column of C and the stores coalesce.
-template <int BM, int BN, int BK, int WGM, int WGN, bool EDGE>
+// V = 2: interior tiles of 16-byte aligned operands stage A and B with
+// 16-byte loads (two rows of A, two k of B per thread); the k order of the
+// products, hence every result bit, is the same for V = 1 and V = 2.
+template <int BM, int BN, int BK, int WGM, int WGN, bool EDGE, int V = 1>
 __device__ __forceinline__ void dgemm16_body(int64_t M, int64_t N, int64_t K, const double* __restrict__ A,
                                              int64_t lda, const double* __restrict__ B, int64_t ldb,
                                              double* __restrict__ C, int64_t ldc, int64_t m0, int64_t n0,
@@ -184,15 +187,18 @@ __device__ __forceinline__ void dgemm16_body(int64_t M, int64_t N, int64_t K, co
   constexpr int PAD = 16;  // 128-byte k-row runs, 1152 B apart: two bank passes, no extra conflict
   constexpr int LDSA = BM + PAD, LDSB = BN + PAD;
   constexpr int SA = BK * LDSA, SB = BK * LDSB;
-  constexpr int EA = BM * BK / NT, EB = BK * BN / NT;
-  constexpr int KA = NT / BM;
-  constexpr int NB_ = NT / BK;
+  static_assert(V == 1 || (V == 2 && !EDGE), "16-byte staging on interior tiles only");
+  constexpr int TA = BM / V, TB = BK / V;  // threads per k-row of A, per column of B
+  constexpr int KA = NT / TA, NB_ = NT / TB;
+  constexpr int EA = BK / KA, EB = BN / NB_;
+  static_assert(KA * TA == NT && EA * KA == BK && NB_ * TB == NT && EB * NB_ == BN, "thread layout");
+  typedef double V2 __attribute__((ext_vector_type(2)));
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
 
-  const int ai = tid % BM, ak0 = tid / BM;
-  const int bk = tid % BK, bn0 = tid / BK;
+  const int ai = (tid % TA) * V, ak0 = tid / TA;
+  const int bk = (tid % TB) * V, bn0 = tid / TB;
   const bool arow_ok = !EDGE || (m0 + ai) < M;
   const T* pa = A + (arow_ok ? (m0 + ai) : (M - 1)) + (int64_t)ak0 * lda;
   const int64_t astep = (int64_t)KA * lda;
@@ -205,9 +211,23 @@ __device__ __forceinline__ void dgemm16_body(int64_t M, int64_t N, int64_t K, co
     pb[s] = B + (bcol_ok[s] ? gn : (N - 1)) * ldb + bk;
   }
 
-  T ra[EA], rb[EB];
+  T ra[EA * V], rb[EB * V];
   auto gload = [&](int64_t k0) {
-    if (!EDGE) {
+    if (V == 2) {
+      const T* q = pa + k0 * lda;
+#pragma unroll
+      for (int s = 0; s < EA; ++s) {
+        const V2 v = *reinterpret_cast<const V2*>(q + s * astep);
+        ra[2 * s] = v[0];
+        ra[2 * s + 1] = v[1];
+      }
+#pragma unroll
+      for (int s = 0; s < EB; ++s) {
+        const V2 v = *reinterpret_cast<const V2*>(pb[s] + k0);
+        rb[2 * s] = v[0];
+        rb[2 * s + 1] = v[1];
+      }
+    } else if (!EDGE) {
       const T* q = pa + k0 * lda;
 #pragma unroll
       for (int s = 0; s < EA; ++s) ra[s] = q[s * astep];
@@ -234,10 +254,25 @@ __device__ __forceinline__ void dgemm16_body(int64_t M, int64_t N, int64_t K, co
   auto sstore = [&](int buf) {
     T* a = sA + buf * SA + ak0 * LDSA + ai;
     T* b = sB + buf * SB + bk * LDSB + bn0;
+    if (V == 2) {
 #pragma unroll
-    for (int s = 0; s < EA; ++s) a[s * KA * LDSA] = ra[s];
+      for (int s = 0; s < EA; ++s) {
+        V2 v;
+        v[0] = ra[2 * s];
+        v[1] = ra[2 * s + 1];
+        *reinterpret_cast<V2*>(a + s * KA * LDSA) = v;
+      }
 #pragma unroll
-    for (int s = 0; s < EB; ++s) b[s * NB_] = rb[s];
+      for (int s = 0; s < EB; ++s) {
+        b[s * NB_] = rb[2 * s];
+        b[s * NB_ + LDSB] = rb[2 * s + 1];
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < EA; ++s) a[s * KA * LDSA] = ra[s];
+#pragma unroll
+      for (int s = 0; s < EB; ++s) b[s * NB_] = rb[s];
+    }
   };
 
   const int lr = lane & 15, lk = lane >> 4;
@@ -311,7 +346,7 @@ __global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_dgemm_sub_16(int64_t M,
                                                                       double* __restrict__ C, int64_t ldc,
                                                                       int tiles_m, int tiles_n) {
   constexpr int PAD = 16;
-  __shared__ double sA[2 * BK * (BM + PAD)];
+  __shared__ __attribute__((aligned(16))) double sA[2 * BK * (BM + PAD)];
   __shared__ double sB[2 * BK * (BN + PAD)];
   const int total = tiles_m * tiles_n;
   const int per_xcd = (total + kXcds - 1) / kXcds;
@@ -326,9 +361,13 @@ __global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_dgemm_sub_16(int64_t M,
   const int tm = first_m + within % gm;
   const int tn = within / gm;
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
-  if (m0 + BM <= M && n0 + BN <= N && K % BK == 0)
-    dgemm16_body<BM, BN, BK, WGM, WGN, false>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sA, sB);
-  else
+  const bool vec = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0 && ((lda | ldb) & 1) == 0;
+  if (m0 + BM <= M && n0 + BN <= N && K % BK == 0) {
+    if (vec)
+      dgemm16_body<BM, BN, BK, WGM, WGN, false, 2>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sA, sB);
+    else
+      dgemm16_body<BM, BN, BK, WGM, WGN, false, 1>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sA, sB);
+  } else
     dgemm16_body<BM, BN, BK, WGM, WGN, true>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sA, sB);
 }
 
@@ -375,9 +414,9 @@ hipError_t gemm_sub(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, 
   if constexpr (sizeof(T) == 8) {
     if (big_tiles >= 256 || (role == 1 && big_tiles >= 32)) {
       tile = 1;
-      if (role == 1) return launch_d16<128, 128, 8, 2, 2, 2, 1>(s, M, N, K, A, lda, B, ldb, C, ldc);
-      if (role == 2) return launch_d16<128, 128, 8, 2, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
-      return launch_d16<128, 128, 8, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
+      if (role == 1) return launch_d16<128, 128, 8, 2, 4, 4, 1>(s, M, N, K, A, lda, B, ldb, C, ldc);
+      if (role == 2) return launch_d16<128, 128, 8, 2, 4, 4, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
+      return launch_d16<128, 128, 8, 2, 4, 4>(s, M, N, K, A, lda, B, ldb, C, ldc);
     }
     tile = 2;
     return launch_d16<64, 64, 8, 2, 2, 4>(s, M, N, K, A, lda, B, ldb, C, ldc);

@@ -40,7 +40,7 @@ struct lupp_handle_st {
   size_t defer_bytes = 0;
   int defer = 1;                    // defer the finished columns' interchanges when the workspace allows
   uint32_t epoch = 0;
-  bool timing = false;
+  int timing = 0;  // LUPP_OPT_TIMING level
   std::vector<lupp::TimingRecord> records;  // events are created once and reused
   size_t nrecords = 0;
   int lookahead = 1;                // factor the next column block on a side stream
@@ -96,6 +96,8 @@ hipError_t ensure_workspace(lupp_handle_t h);
 // handle's nb; false when the deferral does not apply (the interchanges are
 // then applied to the finished columns at every step).
 bool ensure_defer(lupp_handle_t h, int64_t m, int64_t n, size_t elem);
+// Streams of the dataflow runtime's lookahead updates (on first use).
+bool ensure_look_streams(lupp_handle_t h);
 hipError_t ensure_lp_scale(lupp_handle_t h, int64_t m, int64_t n);
 // Flags of the one-launch triangular solve for n rows.
 hipError_t ensure_trsv(lupp_handle_t h, int64_t n);

@@ -25,9 +25,10 @@
 
 namespace lupp {
 
-// Phase timing: HIP events on the handle's stream around a phase's launches.
+// Phase timing: HIP events on the handle's stream around a phase's launches
+// (level 1: every phase; level 2: the trailing updates only).
 int timer_begin(lupp_handle_t h, int phase, hipStream_t st) {
-  if (!h->timing) return -1;
+  if (h->timing == 0 || (h->timing == 2 && phase != LUPP_PHASE_UPDATE)) return -1;
   if (h->nrecords == h->records.size()) {
     TimingRecord r;
     if (hipEventCreate(&r.start) != hipSuccess) return -1;
@@ -220,7 +221,8 @@ hipError_t getrf(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32
   const int64_t p = m < n ? m : n;
   // lookahead deeper than one step: the dataflow runtime (needs the lookahead
   // streams and the deferred interchanges of the finished columns)
-  if (h->lookahead >= 2 && p > 0 && h->side && h->bulk && h->look && ensure_defer(h, m, n, sizeof(T)))
+  if (h->lookahead >= 2 && p > 0 && h->side && h->bulk && ensure_look_streams(h) && h->look &&
+      ensure_defer(h, m, n, sizeof(T)))
     return getrf_dag<T>(h, m, n, A, lda, ipiv, info, h->lookahead);
   LUPP_TRY(set_int(s, info, 0));
   if (p == 0) return hipSuccess;
@@ -605,6 +607,27 @@ hipError_t ensure_trsv(lupp_handle_t h, int64_t n) {
   return hipSuccess;
 }
 
+// The dataflow runtime's lookahead-update streams, masked like the bulk
+// streams (created on its first use, so the loop path holds none).
+bool ensure_look_streams(lupp_handle_t h) {
+  if (h->look) return true;
+  const int ncu = h->ncu;
+  if (ncu <= 0 || h->panel_cus <= 0) return false;
+  std::vector<uint32_t> mb((ncu + 31) / 32, 0u), mb2((ncu + 31) / 32, 0u);
+  for (int c = 0; c < ncu; ++c) {
+    if (c >= h->panel_cus) mb[c / 32] |= 1u << (c % 32);
+    if (c >= kLookaheadPanelCUs2) mb2[c / 32] |= 1u << (c % 32);
+  }
+  if (hipExtStreamCreateWithCUMask(&h->look, (uint32_t)mb.size(), mb.data()) != hipSuccess) {
+    h->look = nullptr;
+    return false;
+  }
+  if (h->panel_cus2 > 0 &&
+      hipExtStreamCreateWithCUMask(&h->look2, (uint32_t)mb2.size(), mb2.data()) != hipSuccess)
+    h->look2 = nullptr;
+  return true;
+}
+
 bool ensure_defer(lupp_handle_t h, int64_t m, int64_t n, size_t elem) {
   const int64_t p = m < n ? m : n;
   const int64_t nb = h->nb;
@@ -658,8 +681,6 @@ hipError_t ensure_workspace(lupp_handle_t h) {
   }
   if (hipExtStreamCreateWithCUMask(&h->side, (uint32_t)mside.size(), mside.data()) != hipSuccess) h->side = nullptr;
   if (hipExtStreamCreateWithCUMask(&h->bulk, (uint32_t)mbulk.size(), mbulk.data()) != hipSuccess) h->bulk = nullptr;
-  // the dataflow runtime's lookahead updates: the bulk CUs, their own queue
-  if (hipExtStreamCreateWithCUMask(&h->look, (uint32_t)mbulk.size(), mbulk.data()) != hipSuccess) h->look = nullptr;
   if (ncu >= 2 * kLookaheadPanelCUs2) {
     std::vector<uint32_t> m2s((ncu + 31) / 32, 0u), m2b((ncu + 31) / 32, 0u);
     for (int c = 0; c < ncu; ++c) {
@@ -668,7 +689,6 @@ hipError_t ensure_workspace(lupp_handle_t h) {
     }
     if (hipExtStreamCreateWithCUMask(&h->side2, (uint32_t)m2s.size(), m2s.data()) != hipSuccess) h->side2 = nullptr;
     if (hipExtStreamCreateWithCUMask(&h->bulk2, (uint32_t)m2b.size(), m2b.data()) != hipSuccess) h->bulk2 = nullptr;
-    if (hipExtStreamCreateWithCUMask(&h->look2, (uint32_t)m2b.size(), m2b.data()) != hipSuccess) h->look2 = nullptr;
     if (h->side2 && h->bulk2) h->panel_cus2 = kLookaheadPanelCUs2;
   }
   if (!h->side || !h->bulk || hipEventCreateWithFlags(&h->ev_cols, hipEventDisableTiming) != hipSuccess ||
@@ -835,8 +855,8 @@ int lupp_set_option(lupp_handle_t h, int option, int64_t value) {
       h->block = (int)value;
       return LUPP_OK;
     case LUPP_OPT_TIMING:
-      if (value != 0 && value != 1) return -3;
-      h->timing = value != 0;
+      if (value < 0 || value > 2) return -3;
+      h->timing = (int)value;
       return LUPP_OK;
     case LUPP_OPT_LOOKAHEAD:
       if (value < 0 || value > 16) return -3;

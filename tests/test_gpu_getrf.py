@@ -387,6 +387,40 @@ def test_split_update_bit_identical():
     assert _probe_residual(A0, A1, p1) < 10 * checks.U64
 
 
+def test_timing_level_updates_only():
+    """LUPP_OPT_TIMING = 2 brackets the trailing updates only: the same update
+    intervals and flops as level 1, no column-block intervals, and the same
+    factors as an uninstrumented call."""
+    n = 4096
+    announce("timing levels n=%d fp64" % n)
+    g = torch.Generator(device="cuda").manual_seed(43)
+    A0 = torch.empty((n, n), dtype=torch.float64, device="cuda").t()
+    A0.uniform_(-1.0, 1.0, generator=g)
+    runs = []
+    for level in (0, 1, 2):
+        h = lupp.Handle()
+        h.set_option(3, level)
+        A = torch.empty_like(A0.t()).t()
+        A.copy_(A0)
+        ipiv = torch.empty(n, dtype=torch.int32, device="cuda")
+        info = torch.empty(1, dtype=torch.int32, device="cuda")
+        lupp.lupp_dgetrf(A, ipiv, info, handle=h)
+        h.sync()
+        counts = {ph: h.timing_summary(ph) for ph in ("panel", "panel_leaf", "laswp", "update", "update_big")}
+        h.close()
+        runs.append((A, ipiv, int(info.item()), counts))
+    (A0f, p0, i0, c0), (A1, p1, i1, c1), (A2, p2, i2, c2) = runs
+    assert i0 == i1 == i2 == 0
+    assert torch.equal(p0, p1) and torch.equal(p0, p2)
+    assert torch.equal(A0f, A1) and torch.equal(A0f, A2)
+    assert all(c[0] == 0 for c in c0.values())
+    assert c1["panel"][0] > 0 and c1["panel_leaf"][0] > 0 and c1["laswp"][0] > 0
+    assert c2["panel"][0] == 0 and c2["panel_leaf"][0] == 0 and c2["laswp"][0] == 0
+    for ph in ("update", "update_big"):
+        assert c2[ph][0] == c1[ph][0] > 0
+        assert c2[ph][2] == c1[ph][2] > 0
+
+
 def test_split_update_low_precision():
     """The same split with BF16 updates (each share scales its own blocks):
     a valid factorization within the update format's residual bound."""
