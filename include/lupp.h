@@ -85,11 +85,17 @@ enum {
                               of one per step; needs a workspace of about 2*m*n/nb bytes,
                               nb <= 512 and m - nb <= 32768 for FP64 or 65536 for FP32,
                               otherwise ignored); 0: at every step, as in LAPACK            */
-  LUPP_OPT_SPLIT_UPDATE = 7 /* 1 (default, with lookahead): once the next column block is
+  LUPP_OPT_SPLIT_UPDATE = 7, /* 1 (default, with lookahead): once the next column block is
                               factored, its CUs take the last columns of the remaining
                               update (sized from the measured panel time and GEMM rate, so
                               that both shares end together); 0: the bulk CUs take it all.
                               FP64/FP32 results are identical either way                 */
+  LUPP_OPT_LP_PACKED = 8    /* with a low-precision update format: 1 (default): each update
+                              scales and rounds A21 and U12 once into a handle workspace in
+                              the matrix cores' operand order (4 slots of about
+                              2*(m+n)*nb bytes, for updates that run concurrently), and the
+                              GEMM streams them; 0: every tile of the GEMM rounds its FP32
+                              operands while staging them.  Identical results either way  */
 };
 
 /* Operand formats of the trailing update (LUPP_OPT_UPDATE_PREC) and of the

@@ -168,11 +168,18 @@ hipError_t trsm_leaf(hipStream_t s, bool lower, int64_t w, int64_t ncols, const 
 // Number of int slots gemm_lp_sub needs as scale workspace for an M x N update.
 int64_t gemm_lp_scale_slots(int64_t M, int64_t N);
 
-// C (FP32) -= A * B with A and B rounded to a low format while staged:
-// mode 1 = BF16, 2 = FP16, 3 = FP8 e4m3 (2 and 3 scale each 128-row block of A
-// and 128-column block of B by a power of two first, using scale_ws).
+// Bytes of the packed-operand workspace of an M x N x K low-precision update.
+size_t gemm_lp_pack_bytes(int64_t M, int64_t N, int64_t K);
+
+// C (FP32) -= A * B with A and B rounded to a low format: mode 1 = BF16,
+// 2 = FP16, 3 = FP8 e4m3 (2 and 3 scale each 128-row block of A and 128-column
+// block of B by a power of two first, using scale_ws).  With a packing
+// workspace of at least gemm_lp_pack_bytes(M, N, K) bytes the operands are
+// rounded once into it; otherwise each tile rounds them while staging.  Both
+// give the same result bits.
 hipError_t gemm_lp_sub(hipStream_t s, int mode, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
-                       const float* B, int64_t ldb, float* C, int64_t ldc, int* scale_ws);
+                       const float* B, int64_t ldb, float* C, int64_t ldc, int* scale_ws, void* pack,
+                       size_t pack_bytes);
 
 // State of the one-launch triangular solve: per-block flags tagged with a
 // call epoch and a ticket counter that hands out blocks in dispatch order.

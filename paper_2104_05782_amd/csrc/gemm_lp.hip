@@ -17,6 +17,15 @@
 // it is never scaled, so no magnitude of C can overflow).  BF16 has FP32's exponent range
 // and uses no scaling.
 //
+// Two ways to stage the operands, with the same rounded values and the same
+// order of products (hence the same result bits):
+//  - packed (default): A and B are scaled and rounded once per update into
+//    a workspace laid out in MFMA fragment order (k_lp_pack_a, k_lp_pack_b);
+//    the GEMM (k_gemm_lpq) then loads each lane's 8-element operand with one
+//    coalesced load, with no LDS, no barrier and no per-tile conversion;
+//  - staged: each tile converts its FP32 operands while copying them into
+//    LDS (k_gemm_lp); used when no packing workspace fits the call.
+//
 // Lane layout of the 16x16x32 instructions (probed on gfx950): lane l supplies
 // A(l%16, 8*(l/16)+t) and B(8*(l/16)+t, l%16), t = 0..7.  The operands are
 // passed swapped (B as the first), so lane l receives C(l%16, 4*(l/16)+r):
@@ -266,34 +275,221 @@ __global__ __launch_bounds__(NT, 2) void k_gemm_lp(int64_t M, int64_t N, int64_t
   }
 }
 
+// Packed operands: for each 128-row block of A (128-column block of B) and
+// each 32-deep chunk of k, 128 rows of 32 rounded values, row-major (ROWB
+// bytes per row; the 8 values a lane supplies for k-group g sit at byte
+// offset g * kBytes of the row).  Rows, columns and k out of range are zero.
+template <int MODE>
+constexpr int lp_rowb() {
+  return 4 * Lp<MODE>::kBytes;
+}
+
+// A (FP32, column-major M x K) scaled by 2^ea[block] and rounded; one
+// workgroup per (128-row block, 32-deep chunk).  Thread c of 512 chunks takes
+// row c % 128 and k-group c / 128, so each of its 8 loads reads 64
+// consecutive rows of one column across the wavefront.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_lp_pack_a(int64_t M, int64_t K, const float* __restrict__ A, int64_t lda,
+                                                   const int* __restrict__ ea, int KC,
+                                                   unsigned char* __restrict__ out) {
+  typedef Lp<MODE> L;
+  constexpr int ROWB = lp_rowb<MODE>();
+  const int tm = blockIdx.x, kc = blockIdx.y;
+  const float f = ea ? ldexpf(1.0f, ea[tm]) : 1.0f;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = threadIdx.x + 256 * h;
+    const int row = c & 127, g = c >> 7;
+    const int64_t gr = (int64_t)tm * 128 + row;
+    const int64_t k0 = (int64_t)kc * 32 + 8 * g;
+    float v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t k = k0 + t;
+      v[t] = (gr < M && k < K) ? A[gr + k * lda] * f : 0.0f;
+    }
+    *(typename L::packed*)(out + ((size_t)((int64_t)tm * KC + kc) * 128 + row) * ROWB + g * L::kBytes) =
+        L::pack(v);
+  }
+}
+
+// B (FP32, column-major K x N) scaled by 2^eb[block] and rounded; one
+// workgroup per (128-column block, 32-deep chunk).  Four threads share a
+// column (k-groups 0..3), so a column's 32 values are read together.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_lp_pack_b(int64_t K, int64_t N, const float* __restrict__ B, int64_t ldb,
+                                                   const int* __restrict__ eb, int KC,
+                                                   unsigned char* __restrict__ out) {
+  typedef Lp<MODE> L;
+  constexpr int ROWB = lp_rowb<MODE>();
+  const int tn = blockIdx.x, kc = blockIdx.y;
+  const float f = eb ? ldexpf(1.0f, eb[tn]) : 1.0f;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = threadIdx.x + 256 * h;
+    const int g = c & 3, col = c >> 2;
+    const int64_t gc = (int64_t)tn * 128 + col;
+    const int64_t k0 = (int64_t)kc * 32 + 8 * g;
+    float v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t k = k0 + t;
+      v[t] = (gc < N && k < K) ? B[k + gc * ldb] * f : 0.0f;
+    }
+    *(typename L::packed*)(out + ((size_t)((int64_t)tn * KC + kc) * 128 + col) * ROWB + g * L::kBytes) =
+        L::pack(v);
+  }
+}
+
+// C (FP32) -= A * B from packed operands: 128 x 128 tiles, four wavefronts of
+// 64 x 64 (16 accumulators), each lane loading its own fragments straight
+// from the packed chunks (one 16-byte load per fragment for BF16/FP16, 8 for
+// FP8), two chunks in flight.  C is loaded at the start (its latency hides
+// behind the products) and stored once, unscaled: C - (acc 2^-ea) 2^-eb.
+template <int MODE>
+__global__ __launch_bounds__(NT, 2) void k_gemm_lpq(int64_t M, int64_t N, int KC,
+                                                    const unsigned char* __restrict__ Aq,
+                                                    const unsigned char* __restrict__ Bq, float* __restrict__ C,
+                                                    int64_t ldc, const int* __restrict__ ea,
+                                                    const int* __restrict__ eb, int tiles_m, int tiles_n) {
+  typedef Lp<MODE> L;
+  typedef typename L::packed P;
+  constexpr int ROWB = lp_rowb<MODE>();
+  constexpr int CH = 128 * ROWB;  // bytes of one 32-deep chunk of a 128-row block
+  constexpr int WGM = 2, WTM = BM / WGM, WTN = BN / 2, FM = WTM / 16, FN = WTN / 16;
+
+  const int total = tiles_m * tiles_n;
+  const int per_xcd = (total + kXcdsLp - 1) / kXcdsLp;
+  const int bid = blockIdx.x;
+  const int t = (bid % kXcdsLp) * per_xcd + bid / kXcdsLp;
+  if (t >= total) return;
+  const int group_size = kGroupMLp * tiles_n;
+  const int group = t / group_size;
+  const int first_m = group * kGroupMLp;
+  const int gm = min(tiles_m - first_m, kGroupMLp);
+  const int within = t - group * group_size;
+  const int tm = first_m + within % gm;
+  const int tn = within / gm;
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+
+  const int sea = ea ? ea[tm] : 0, seb = eb ? eb[tn] : 0;
+  const float fai = ldexpf(1.0f, -sea), fbi = ldexpf(1.0f, -seb);
+
+  const unsigned char* pa =
+      Aq + (size_t)tm * KC * CH + (wm * WTM + (lane & 15)) * ROWB + (lane >> 4) * L::kBytes;
+  const unsigned char* pb =
+      Bq + (size_t)tn * KC * CH + (wn * WTN + (lane & 15)) * ROWB + (lane >> 4) * L::kBytes;
+
+  f4 cpre[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    const int64_t row = m0 + wm * WTM + i * 16 + (lane & 15);
+    const int64_t rowc = row < M ? row : M - 1;
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t col = n0 + wn * WTN + j * 16 + 4 * (lane >> 4) + q;
+        const int64_t colc = col < N ? col : N - 1;
+        cpre[i][j][q] = C[rowc + colc * ldc];
+      }
+  }
+
+  f4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+
+  P a0[FM], b0[FN], a1[FM], b1[FN];
+  auto load = [&](int kc, P* a, P* b) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i) a[i] = *(const P*)(pa + (size_t)kc * CH + i * 16 * ROWB);
+#pragma unroll
+    for (int j = 0; j < FN; ++j) b[j] = *(const P*)(pb + (size_t)kc * CH + j * 16 * ROWB);
+  };
+  auto products = [&](const P* a, const P* b) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[i][j] = L::mma(b[j], a[i], acc[i][j]);
+  };
+
+  load(0, a0, b0);
+  int kc = 0;
+  for (; kc + 2 <= KC; kc += 2) {
+    load(kc + 1, a1, b1);
+    products(a0, b0);
+    if (kc + 2 < KC) load(kc + 2, a0, b0);
+    products(a1, b1);
+  }
+  if (kc < KC) products(a0, b0);
+
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    const int64_t row = m0 + wm * WTM + i * 16 + (lane & 15);
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t col = n0 + wn * WTN + j * 16 + 4 * (lane >> 4) + q;
+        if (row < M && col < N) C[row + col * ldc] = cpre[i][j][q] - (acc[i][j][q] * fai) * fbi;
+      }
+  }
+}
+
+// wavefront max of floats, the same value in every lane
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
 // exponent e of each 128-row block of A (dim = 0) or 128-column block of B
 // (dim = 1) such that 2^e * max|block| lies in [limit/2, limit]; 0 for a zero
-// block.  limit is the format's largest finite value.
-__global__ __launch_bounds__(256) void k_block_exp(int64_t rows, int64_t cols, const float* __restrict__ X,
-                                                   int64_t ldx, int dim, float limit, int* __restrict__ e) {
-  __shared__ float s_max[256];
-  const int blk = blockIdx.x, tid = threadIdx.x;
+// block.  limit is the format's largest finite value.  1024 threads per
+// block, each keeping four loads in flight; every load instruction reads 64
+// consecutive elements of a column.  (The maximum does not depend on the
+// order it is taken in: fmaxf is exact and skips NaN either way.)
+__global__ __launch_bounds__(1024) void k_block_exp(int64_t rows, int64_t cols, const float* __restrict__ X,
+                                                    int64_t ldx, int dim, float limit, int* __restrict__ e) {
+  __shared__ float s_max[16];
+  const int blk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   float m = 0.0f;
   if (dim == 0) {
+    // rows r0 + (tid & 127), columns tid >> 7, + 8, + 16, ...
     const int64_t r = (int64_t)blk * 128 + (tid & 127);
-    if (r < rows)
-      for (int64_t c = tid >> 7; c < cols; c += 2) m = fmaxf(m, fabsf(X[r + c * ldx]));
+    if (r < rows) {
+      const float* p = X + r;
+      int64_t c = tid >> 7;
+      for (; c + 24 < cols; c += 32) {
+        const float a0 = p[c * ldx], a1 = p[(c + 8) * ldx], a2 = p[(c + 16) * ldx], a3 = p[(c + 24) * ldx];
+        m = fmaxf(m, fmaxf(fmaxf(fabsf(a0), fabsf(a1)), fmaxf(fabsf(a2), fabsf(a3))));
+      }
+      for (; c < cols; c += 8) m = fmaxf(m, fabsf(p[c * ldx]));
+    }
   } else {
-    const int64_t c0 = (int64_t)blk * 128;
-    for (int64_t cc = tid >> 5; cc < 128; cc += 8) {
-      const int64_t c = c0 + cc;
+    // columns c0 + 8 * wave .. + 7, rows lane, lane + 64, ...
+    for (int cc = 0; cc < 8; ++cc) {
+      const int64_t c = (int64_t)blk * 128 + wave * 8 + cc;
       if (c >= cols) break;
-      for (int64_t r = tid & 31; r < rows; r += 32) m = fmaxf(m, fabsf(X[r + c * ldx]));
+      const float* p = X + c * ldx;
+      int64_t r = lane;
+      for (; r + 192 < rows; r += 256) {
+        const float a0 = p[r], a1 = p[r + 64], a2 = p[r + 128], a3 = p[r + 192];
+        m = fmaxf(m, fmaxf(fmaxf(fabsf(a0), fabsf(a1)), fmaxf(fabsf(a2), fabsf(a3))));
+      }
+      for (; r < rows; r += 64) m = fmaxf(m, fabsf(p[r]));
     }
   }
-  s_max[tid] = m;
+  m = wave_max(m);
+  if (lane == 0) s_max[wave] = m;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) s_max[tid] = fmaxf(s_max[tid], s_max[tid + s]);
-    __syncthreads();
-  }
   if (tid == 0) {
-    const float mx = s_max[0];
+    float mx = 0.0f;
+    for (int w = 0; w < 16; ++w) mx = fmaxf(mx, s_max[w]);
     int ex = 0;
     if (mx > 0.0f && mx < 3.0e38f) {
       (void)frexpf(limit / mx, &ex);  // limit/mx = f * 2^ex, f in [0.5, 1)
@@ -316,25 +512,59 @@ hipError_t launch_lp(hipStream_t s, int64_t M, int64_t N, int64_t K, const float
   return hipGetLastError();
 }
 
+// Packs A and B into `pack` (gemm_lp_pack_bytes(M, N, K) bytes) and runs the
+// packed GEMM.
+template <int MODE>
+hipError_t launch_lpq(hipStream_t s, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, const float* B,
+                      int64_t ldb, float* C, int64_t ldc, const int* ea, const int* eb, unsigned char* pack) {
+  const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN, kc = (K + 31) / 32;
+  if (tm * tn > (int64_t)1 << 30 || kc > 65535 || tm > 0x7fffffff || tn > 0x7fffffff) return hipErrorInvalidValue;
+  unsigned char* aq = pack;
+  unsigned char* bq = pack + (size_t)tm * kc * 128 * lp_rowb<MODE>();
+  hipLaunchKernelGGL(k_lp_pack_a<MODE>, dim3((unsigned)tm, (unsigned)kc), dim3(256), 0, s, M, K, A, lda, ea, (int)kc,
+                     aq);
+  hipLaunchKernelGGL(k_lp_pack_b<MODE>, dim3((unsigned)tn, (unsigned)kc), dim3(256), 0, s, K, N, B, ldb, eb, (int)kc,
+                     bq);
+  const int total = (int)(tm * tn);
+  const int per_xcd = (total + kXcdsLp - 1) / kXcdsLp;
+  hipLaunchKernelGGL((k_gemm_lpq<MODE>), dim3(per_xcd * kXcdsLp), dim3(NT), 0, s, M, N, (int)kc, aq, bq, C, ldc, ea,
+                     eb, (int)tm, (int)tn);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 int64_t gemm_lp_scale_slots(int64_t M, int64_t N) { return (M + BM - 1) / BM + (N + BN - 1) / BN; }
 
+size_t gemm_lp_pack_bytes(int64_t M, int64_t N, int64_t K) {
+  if (M <= 0 || N <= 0 || K <= 0) return 0;
+  const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN, kc = (K + 31) / 32;
+  return (size_t)(tm + tn) * (size_t)kc * 128 * (size_t)lp_rowb<1>();  // BF16/FP16 rows; FP8 uses half
+}
+
 hipError_t gemm_lp_sub(hipStream_t s, int mode, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
-                       const float* B, int64_t ldb, float* C, int64_t ldc, int* scale_ws) {
+                       const float* B, int64_t ldb, float* C, int64_t ldc, int* scale_ws, void* pack,
+                       size_t pack_bytes) {
   if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
-  if (mode == 1) return launch_lp<1>(s, M, N, K, A, lda, B, ldb, C, ldc, nullptr, nullptr);
-  if (mode != 2 && mode != 3) return hipErrorInvalidValue;
+  if (mode < 1 || mode > 3) return hipErrorInvalidValue;
+  const bool packed = pack && gemm_lp_pack_bytes(M, N, K) <= pack_bytes;
+  unsigned char* pk = (unsigned char*)pack;
+  if (mode == 1)
+    return packed ? launch_lpq<1>(s, M, N, K, A, lda, B, ldb, C, ldc, nullptr, nullptr, pk)
+                  : launch_lp<1>(s, M, N, K, A, lda, B, ldb, C, ldc, nullptr, nullptr);
   const float limit = (mode == 2) ? 65504.0f : 448.0f;
   const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
   int* ea = scale_ws;
   int* eb = scale_ws + tm;
-  hipLaunchKernelGGL(k_block_exp, dim3((unsigned)tm), dim3(256), 0, s, M, K, A, lda, 0, limit, ea);
-  hipLaunchKernelGGL(k_block_exp, dim3((unsigned)tn), dim3(256), 0, s, K, N, B, ldb, 1, limit, eb);
+  hipLaunchKernelGGL(k_block_exp, dim3((unsigned)tm), dim3(1024), 0, s, M, K, A, lda, 0, limit, ea);
+  hipLaunchKernelGGL(k_block_exp, dim3((unsigned)tn), dim3(1024), 0, s, K, N, B, ldb, 1, limit, eb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (mode == 2) return launch_lp<2>(s, M, N, K, A, lda, B, ldb, C, ldc, ea, eb);
-  return launch_lp<3>(s, M, N, K, A, lda, B, ldb, C, ldc, ea, eb);
+  if (mode == 2)
+    return packed ? launch_lpq<2>(s, M, N, K, A, lda, B, ldb, C, ldc, ea, eb, pk)
+                  : launch_lp<2>(s, M, N, K, A, lda, B, ldb, C, ldc, ea, eb);
+  return packed ? launch_lpq<3>(s, M, N, K, A, lda, B, ldb, C, ldc, ea, eb, pk)
+                : launch_lp<3>(s, M, N, K, A, lda, B, ldb, C, ldc, ea, eb);
 }
 
 }  // namespace lupp

@@ -69,8 +69,15 @@ struct lupp_handle_st {
   double est_panel_ms[2] = {-1.0, -1.0};  // measured column-block time (ms) per pair, < 0 before the first
   double est_rate = -1.0;           // measured bulk GEMM flops per ms per CU, < 0 before the first
   int update_prec = 0;              // LUPP_PREC_* of sgetrf's trailing update
-  int* lp_scale[3] = {nullptr, nullptr, nullptr};  // block exponents: next-block, bulk and side updates
-  int64_t lp_scale_cap = 0;         // ints in each of lp_scale[0..2]
+  // Workspace of the low-precision updates, one slot per update that may run
+  // concurrently: 0 the next block's (caller's stream), 1 the bulk update,
+  // 2 the bulk's share on the panel's CUs (loop) or the lookahead updates on
+  // the first lookahead stream (dataflow runtime), 3 those on the second.
+  int* lp_scale[4] = {nullptr, nullptr, nullptr, nullptr};  // block exponents
+  int64_t lp_scale_cap = 0;         // ints in each lp_scale slot
+  void* lp_pack[4] = {nullptr, nullptr, nullptr, nullptr};  // packed operands
+  size_t lp_pack_cap = 0;           // bytes in each lp_pack slot
+  int lp_packed = 1;                // LUPP_OPT_LP_PACKED
   std::vector<hipEvent_t> dag_events;  // task completion events of the dataflow runtime (reused)
   lupp::TrsvState trsv{};           // one-launch triangular solve state (flags on demand)
   lupp::MixedWs* mixed = nullptr;   // workspace of lupp_dgesv_mixed
@@ -98,7 +105,7 @@ hipError_t ensure_workspace(lupp_handle_t h);
 bool ensure_defer(lupp_handle_t h, int64_t m, int64_t n, size_t elem);
 // Streams of the dataflow runtime's lookahead updates (on first use).
 bool ensure_look_streams(lupp_handle_t h);
-hipError_t ensure_lp_scale(lupp_handle_t h, int64_t m, int64_t n);
+hipError_t ensure_lp_scale(lupp_handle_t h, int64_t m, int64_t n, int64_t nb);
 // Flags of the one-launch triangular solve for n rows.
 hipError_t ensure_trsv(lupp_handle_t h, int64_t n);
 // The factorization and the solve on the handle's stream (arguments checked).

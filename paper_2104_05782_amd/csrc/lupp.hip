@@ -132,16 +132,18 @@ hipError_t panel(lupp_handle_t h, hipStream_t s, int64_t m, int64_t k, int64_t w
 
 // Trailing update C -= A * B of the outer loop: FP64 and FP32 on the MFMA GEMM
 // of the working precision, or (FP32 factorization with a low-precision update
-// format) on the low-precision GEMM; `which` selects the scale workspace of
-// the updates that may run concurrently (0: next block, 1: bulk, 2: the
-// bulk's share on the panel's CUs).
+// format) on the low-precision GEMM; `which` selects the low-precision
+// workspace slot of the updates that may run concurrently (0: next block,
+// 1: bulk, 2: the bulk's share on the panel's CUs or the dataflow runtime's
+// first lookahead stream, 3: its second).
 template <typename T>
 hipError_t update(lupp_handle_t h, hipStream_t s, int which, int64_t M, int64_t N, int64_t K, const T* A,
                   int64_t lda, const T* B, int64_t ldb, T* C, int64_t ldc, int* tile = nullptr) {
   if constexpr (std::is_same<T, float>::value) {
     if (h->update_prec != LUPP_PREC_FP32) {
       if (tile) *tile = 1;
-      return gemm_lp_sub(s, h->update_prec, M, N, K, A, lda, B, ldb, C, ldc, h->lp_scale[which]);
+      return gemm_lp_sub(s, h->update_prec, M, N, K, A, lda, B, ldb, C, ldc, h->lp_scale[which],
+                         h->lp_packed ? h->lp_pack[which] : nullptr, h->lp_pack_cap);
     }
   }
   return gemm_sub<T>(s, M, N, K, A, lda, B, ldb, C, ldc, tile, which == 2 ? 1 : 0);
@@ -506,8 +508,10 @@ hipError_t getrf_dag(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, i
       if (mr > 0) {
         int tile = -1;
         tt = timer_begin(h, LUPP_PHASE_UPDATE, x.stream);
-        LUPP_TRY(update<T>(h, x.stream, x.stream == s ? 0 : 1, mr, nc, b, A + kn + k0 * lda, lda, A + k0 + c0 * lda,
-                           lda, A + kn + c0 * lda, lda, &tile));
+        // one workspace slot per stream: updates on different streams may overlap
+        const int slot = x.stream == s ? 0 : (x.stream == h->look ? 2 : (x.stream == h->look2 ? 3 : 1));
+        LUPP_TRY(update<T>(h, x.stream, slot, mr, nc, b, A + kn + k0 * lda, lda, A + k0 + c0 * lda, lda,
+                           A + kn + c0 * lda, lda, &tile));
         timer_end(h, tt, x.stream, 2.0 * (double)mr * (double)nc * (double)b, tile == 1, update_bytes<T>(mr, nc, b));
       }
     } else {
@@ -558,9 +562,10 @@ template hipError_t getrs<double>(lupp_handle_t, int64_t, int64_t, const double*
 template hipError_t getrs<float>(lupp_handle_t, int64_t, int64_t, const float*, int64_t, const int32_t*, float*,
                                  int64_t);
 
-hipError_t ensure_lp_scale(lupp_handle_t h, int64_t m, int64_t n) {
+hipError_t ensure_lp_scale(lupp_handle_t h, int64_t m, int64_t n, int64_t nb) {
   const int64_t need = gemm_lp_scale_slots(m, n);
-  if (need <= h->lp_scale_cap) return hipSuccess;
+  const size_t pneed = h->lp_packed ? gemm_lp_pack_bytes(m, n, nb) : 0;
+  if (need <= h->lp_scale_cap && pneed <= h->lp_pack_cap) return hipSuccess;
   LUPP_TRY(hipStreamSynchronize(h->stream));
   if (h->bulk) LUPP_TRY(hipStreamSynchronize(h->bulk));
   if (h->side) LUPP_TRY(hipStreamSynchronize(h->side));
@@ -568,15 +573,27 @@ hipError_t ensure_lp_scale(lupp_handle_t h, int64_t m, int64_t n) {
   if (h->look) LUPP_TRY(hipStreamSynchronize(h->look));
   if (h->look2) LUPP_TRY(hipStreamSynchronize(h->look2));
   if (h->side2) LUPP_TRY(hipStreamSynchronize(h->side2));
+  const int64_t ns = need > h->lp_scale_cap ? need : h->lp_scale_cap;
+  const size_t np = pneed > h->lp_pack_cap ? pneed : h->lp_pack_cap;
   if (h->lp_scale[0]) (void)hipFree(h->lp_scale[0]);
-  h->lp_scale[0] = h->lp_scale[1] = h->lp_scale[2] = nullptr;
+  if (h->lp_pack[0]) (void)hipFree(h->lp_pack[0]);
+  for (int i = 0; i < 4; ++i) {
+    h->lp_scale[i] = nullptr;
+    h->lp_pack[i] = nullptr;
+  }
   h->lp_scale_cap = 0;
+  h->lp_pack_cap = 0;
   void* p = nullptr;
-  LUPP_TRY(hipMalloc(&p, (size_t)need * 3 * sizeof(int)));
-  h->lp_scale[0] = (int*)p;
-  h->lp_scale[1] = (int*)p + need;
-  h->lp_scale[2] = (int*)p + 2 * need;
-  h->lp_scale_cap = need;
+  LUPP_TRY(hipMalloc(&p, (size_t)ns * 4 * sizeof(int)));
+  for (int i = 0; i < 4; ++i) h->lp_scale[i] = (int*)p + i * ns;
+  h->lp_scale_cap = ns;
+  if (np > 0) {
+    const size_t slot = (np + 255) / 256 * 256;
+    void* q = nullptr;
+    LUPP_TRY(hipMalloc(&q, slot * 4));
+    for (int i = 0; i < 4; ++i) h->lp_pack[i] = (char*)q + i * slot;
+    h->lp_pack_cap = slot;
+  }
   return hipSuccess;
 }
 
@@ -727,7 +744,10 @@ size_t getrf_workspace_bytes(lupp_handle_t h, int64_t m, int64_t n, size_t elem)
     const size_t d = (size_t)J * sizeof(SwapPairs) + sizeof(int32_t) * (size_t)(2 * m + left_map_entries(J, m, nb));
     if (d <= ((size_t)1 << 30)) bytes += d;
   }
-  if (elem == 4 && h->update_prec != LUPP_PREC_FP32) bytes += (size_t)gemm_lp_scale_slots(m, n) * 3 * sizeof(int);
+  if (elem == 4 && h->update_prec != LUPP_PREC_FP32) {
+    bytes += (size_t)gemm_lp_scale_slots(m, n) * 4 * sizeof(int);
+    if (h->lp_packed) bytes += (gemm_lp_pack_bytes(m, n, nb) + 255) / 256 * 256 * 4;
+  }
   return bytes;
 }
 
@@ -751,7 +771,7 @@ int getrf_entry(lupp_handle_t h, int64_t m, int64_t n, T* A, int64_t lda, int32_
   hipError_t e = ensure_workspace(h);
   if (e != hipSuccess) return LUPP_ERR_ALLOC;
   if (std::is_same<T, float>::value && h->update_prec != LUPP_PREC_FP32) {
-    e = ensure_lp_scale(h, m, n);
+    e = ensure_lp_scale(h, m, n, h->nb);
     if (e != hipSuccess) return LUPP_ERR_ALLOC;
   }
   return hip_status(getrf<T>(h, m, n, A, lda, ipiv, info));
@@ -828,6 +848,7 @@ int lupp_destroy(lupp_handle_t h) {
   if (h->slots) (void)hipFree(h->slots);
   if (h->defer_buf) (void)hipFree(h->defer_buf);
   if (h->lp_scale[0]) (void)hipFree(h->lp_scale[0]);
+  if (h->lp_pack[0]) (void)hipFree(h->lp_pack[0]);
   if (h->trsv.flags) (void)hipFree(h->trsv.flags);
   lupp::free_mixed(h);
   lupp::free_batched(h);
@@ -873,6 +894,10 @@ int lupp_set_option(lupp_handle_t h, int option, int64_t value) {
     case LUPP_OPT_SPLIT_UPDATE:
       if (value != 0 && value != 1) return -3;
       h->split = (int)value;
+      return LUPP_OK;
+    case LUPP_OPT_LP_PACKED:
+      if (value != 0 && value != 1) return -3;
+      h->lp_packed = (int)value;
       return LUPP_OK;
     default:
       return -2;

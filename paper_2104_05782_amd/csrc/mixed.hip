@@ -280,7 +280,7 @@ int gesv_mixed(lupp_handle_t h, int64_t n, int64_t nrhs, const double* A, int64_
   hipError_t e = ensure_workspace(h);
   if (e == hipSuccess) e = ensure_mixed(h, n, m);
   if (e == hipSuccess) e = ensure_trsv(h, n);
-  if (e == hipSuccess && o.factor_prec != LUPP_PREC_FP32) e = ensure_lp_scale(h, n, n);
+  if (e == hipSuccess && o.factor_prec != LUPP_PREC_FP32) e = ensure_lp_scale(h, n, n, o.nb > 0 ? o.nb : h->nb);
   if (e != hipSuccess) return LUPP_ERR_ALLOC;
   MixedWs* w = h->mixed;
   Ctx c{h, w, s, n, A, lda};

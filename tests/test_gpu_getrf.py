@@ -358,7 +358,7 @@ def _factor_dev(A0, **opts):
     h = lupp.Handle()
     for k, v in opts.items():
         h.set_option({"nb": 1, "timing": 3, "split": lupp._binding.OPT_SPLIT_UPDATE,
-                      "prec": lupp._binding.OPT_UPDATE_PREC}[k], v)
+                      "prec": lupp._binding.OPT_UPDATE_PREC, "packed": 8, "lookahead": 4}[k], v)
     A = torch.empty_like(A0.t()).t()
     A.copy_(A0)
     ipiv = torch.empty(A0.shape[0], dtype=torch.int32, device="cuda")
@@ -419,6 +419,40 @@ def test_timing_level_updates_only():
     for ph in ("update", "update_big"):
         assert c2[ph][0] == c1[ph][0] > 0
         assert c2[ph][2] == c1[ph][2] > 0
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16", "fp8"])
+@pytest.mark.parametrize("shape", [(4133, 4133), (5000, 3700), (2900, 4500)])
+def test_low_precision_packed_operands_bit_identical(fmt, shape):
+    """The update's operands rounded once into the packed workspace give the
+    same factors and pivots, bit for bit, as rounding them in every tile
+    (ragged row, column and k edges; FP16/FP8 with block scales)."""
+    m, n = shape
+    announce("packed vs staged %s updates %dx%d" % (fmt, m, n))
+    g = torch.Generator(device="cuda").manual_seed(44 + m + n)
+    A0 = torch.empty((n, m), dtype=torch.float32, device="cuda").t()
+    A0.uniform_(-1.0, 1.0, generator=g)
+    A1, p1, i1, _ = _factor_dev(A0, prec=lupp.PREC[fmt], packed=1)
+    A2, p2, i2, _ = _factor_dev(A0, prec=lupp.PREC[fmt], packed=0)
+    k = min(m, n)  # the pivot buffer holds m entries; the first min(m, n) are written
+    assert i1 == i2 == 0
+    assert torch.equal(p1[:k], p2[:k])
+    assert torch.equal(A1, A2)
+
+
+def test_dataflow_scaled_low_precision_bit_identical():
+    """Dataflow runtime with FP16 updates (per-block scales): each stream has
+    its own scale and packing slot, so overlapping update tasks give the
+    loop's bits exactly."""
+    n = 8192
+    announce("dataflow fp16 updates n=%d" % n)
+    g = torch.Generator(device="cuda").manual_seed(45)
+    A0 = torch.empty((n, n), dtype=torch.float32, device="cuda").t()
+    A0.uniform_(-1.0, 1.0, generator=g)
+    ref = _factor_dev(A0, prec=lupp.PREC["fp16"])
+    out = _factor_dev(A0, prec=lupp.PREC["fp16"], lookahead=4)
+    assert ref[2] == out[2] == 0
+    assert torch.equal(ref[1], out[1]) and torch.equal(ref[0], out[0])
 
 
 def test_split_update_low_precision():
