@@ -241,9 +241,15 @@ __global__ __launch_bounds__(NT) void k_qr_panel(int64_t r, int w, double* __res
 // (X is read once) and writes part[chunk] (column-major LDW x N per chunk).
 // Four wavefronts: for LDW = 128 each takes 32 rows x 64 columns (8 MFMA
 // accumulators of 16x16), for LDW = 32 each 16 rows x 32 columns (2).  LDS
-// tiles of 32 rows, double-buffered: the next tile's loads are in flight
-// while the current one is multiplied.
-constexpr int kTnCols = 64, kTnK = 32;
+// tiles of 16 rows, double-buffered: the next tile's loads are in flight
+// while the current one is multiplied (50 KB of LDS for LDW = 128, so that
+// three workgroups share a CU).
+constexpr int kTnCols = 64;
+constexpr int kTnTarget = 768;  // workgroups of one product (three per CU)
+template <int LDW>
+constexpr int tn_k() {
+  return LDW >= 64 ? 16 : 32;  // rows per LDS tile
+}
 template <int LDW>
 __global__ __launch_bounds__(256) void k_qr_tn(int64_t r, int64_t N, const double* __restrict__ V, int64_t ldv,
                                                const double* __restrict__ X, int64_t ldx, int64_t rows_per_chunk,
@@ -252,6 +258,7 @@ __global__ __launch_bounds__(256) void k_qr_tn(int64_t r, int64_t N, const doubl
   constexpr int WR = LDW >= 64 ? LDW / 4 : 16;  // rows of W per wavefront
   constexpr int WC = LDW >= 64 ? 64 : 32;       // columns per wavefront
   constexpr int FI = WR / 16, FJ = WC / 16;
+  constexpr int kTnK = tn_k<LDW>();
   constexpr int EV = kTnK * LDW / 256, EX = kTnK * kTnCols / 256;
   __shared__ double sV[2][kTnK][LDW + 1];
   __shared__ double sX[2][kTnK][kTnCols + 1];
@@ -344,24 +351,48 @@ __global__ void k_qr_reduce(int64_t N, int ldw, int nchunk, const double* __rest
   Wm[e] = t;
 }
 
+// t + sum_{l = lo}^{hi - 1} a[l * sa] * g[l] in increasing l (LDS operands):
+// eight pairs are loaded before their eight FMAs, so the chain waits for LDS
+// once per eight terms rather than once per term; the order of the sum is
+// that of the plain loop.
+__device__ __forceinline__ double ordered_dot(const double* a, int sa, const double* g, int lo, int hi) {
+  double t = 0.0;
+  int l = lo;
+  for (; l + 8 <= hi; l += 8) {
+    double x[8], y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      x[u] = a[(l + u) * sa];
+      y[u] = g[l + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t += x[u] * y[u];
+  }
+  for (; l < hi; ++l) t += a[l * sa] * g[l];
+  return t;
+}
+
 // -T^T of the compact WY form of up to 128 reflectors (the 128-column outer
 // block), from G = V^T V (128 x 128) and tau (b values): T[j][j] = tau_j,
 // T[:j, j] = -tau_j T[:j, :j] G[:j, j], one column after the other, then
 // written transposed and negated (128 x 128, column-major) for the product
-// W := T^T W = 0 - (-T^T) W on the GEMM.
+// W := T^T W = 0 - (-T^T) W on the GEMM.  Column j of G is staged in LDS
+// while column j - 1 is computed, so the dependent chain reads only LDS.
 __global__ __launch_bounds__(kQrNB) void k_qr_larft_big(int b, const double* __restrict__ Gm,
                                                         const double* __restrict__ tau, double* __restrict__ Tneg) {
   __shared__ double sT[kQrNB][kQrNB + 1];
+  __shared__ double sg[2][kQrNB];
   const int tid = threadIdx.x;
   for (int e = tid; e < kQrNB * kQrNB; e += kQrNB) sT[e % kQrNB][e / kQrNB] = 0.0;
+  if (b > 0) sg[0][tid] = Gm[tid];
   __syncthreads();
   for (int j = 0; j < b; ++j) {
+    // column j + 1 goes to the buffer read in column j - 1 (two barriers ago)
+    if (j + 1 < b) sg[(j + 1) & 1][tid] = Gm[tid + (j + 1) * kQrNB];
+    const double* g = sg[j & 1];
     const double tj = tau[j];
     double t = 0.0;
-    if (tid < j) {
-      for (int l = tid; l < j; ++l) t += sT[tid][l] * Gm[l + j * kQrNB];
-      t = -tj * t;
-    }
+    if (tid < j) t = -tj * ordered_dot(&sT[tid][0], 1, g, tid, j);
     __syncthreads();
     if (tid < j) sT[tid][j] = t;
     if (tid == j) sT[j][j] = tj;
@@ -380,21 +411,23 @@ __global__ void k_qr_zero(int64_t count, double* __restrict__ x) {
 }
 
 // T of the compact WY form from G = V^T V (32 x 32) and tau (b values, the
-// rest 0): one wavefront; column j after column j-1.
+// rest 0): one wavefront; column j after column j-1.  G is staged in LDS
+// first.
 __global__ __launch_bounds__(64) void k_qr_larft(int b, const double* __restrict__ Gm, const double* __restrict__ tau,
                                                  double* __restrict__ Tm) {
   __shared__ double sT[kQrW][kQrW];
+  __shared__ double sG[kQrW * kQrW];
   const int lane = threadIdx.x;
-  for (int e = lane; e < kQrW * kQrW; e += 64) sT[e % kQrW][e / kQrW] = 0.0;
+  for (int e = lane; e < kQrW * kQrW; e += 64) {
+    sT[e % kQrW][e / kQrW] = 0.0;
+    sG[e] = Gm[e];
+  }
   __syncthreads();
   for (int j = 0; j < b; ++j) {
     const double tj = tau[j];
     double t = 0.0;
-    if (lane < j) {
-      // (T[:j, :j] G[:j, j])[lane], T upper triangular
-      for (int l = lane; l < j; ++l) t += sT[lane][l] * Gm[l + j * kQrW];
-      t = -tj * t;
-    }
+    // (T[:j, :j] G[:j, j])[lane], T upper triangular
+    if (lane < j) t = -tj * ordered_dot(&sT[lane][0], 1, sG + j * kQrW, lane, j);
     __syncthreads();
     if (lane < j) sT[lane][j] = t;
     if (lane == j) sT[j][j] = tj;
@@ -436,7 +469,7 @@ namespace {
 
 int64_t tn_chunks(int64_t r, int64_t N) {
   const int64_t tiles = (N + kTnCols - 1) / kTnCols;
-  int64_t ch = (512 + tiles - 1) / tiles;  // about 512 workgroups in all
+  int64_t ch = (kTnTarget + tiles - 1) / tiles;  // about kTnTarget workgroups in all
   const int64_t maxch = (r + 1023) / 1024;  // at least 1024 rows per chunk
   if (ch > maxch) ch = maxch;
   return ch < 1 ? 1 : ch;
@@ -449,7 +482,7 @@ hipError_t qr_tn(hipStream_t s, int64_t r, int64_t N, const double* V, int64_t l
               int ldw, double* part, double* out) {
   const int64_t ch = tn_chunks(r, N);
   int64_t rpc = (r + ch - 1) / ch;
-  rpc = (rpc + kTnK - 1) / kTnK * kTnK;
+  rpc = (rpc + 31) / 32 * 32;  // a multiple of every tile depth
   const int64_t nch = (r + rpc - 1) / rpc;
   const dim3 grid((unsigned)((N + kTnCols - 1) / kTnCols), (unsigned)nch);
   if (ldw == kQrNB)
@@ -476,12 +509,12 @@ void free_qr(lupp_handle_t h) {
 }
 
 // Vbig (m x 128), G and -T^T (128 x 128 each), G32 and T32, W and W2
-// (128 x n each), the chunk partials (at most 512 / tiles + 1 chunks of
-// ldw x N with tiles = N / 64, so at most 128 x (32768 + n) values).
+// (128 x n each), the chunk partials (at most kTnTarget / tiles + 1 chunks
+// of ldw x N with tiles = N / 64, so at most 128 x (64 kTnTarget + n) values).
 size_t qr_workspace_bytes(int64_t m, int64_t n) {
   const int64_t nn = n > kQrNB ? n : kQrNB;
   return sizeof(QrSlots) + sizeof(double) * (size_t)((int64_t)kQrNB * m + 2 * kQrNB * kQrNB + 2 * kQrW * kQrW +
-                                                     2 * kQrNB * nn + kQrNB * (32768 + nn) + 256);
+                                                     2 * kQrNB * nn + kQrNB * (kTnCols * kTnTarget + nn) + 256);
 }
 
 namespace {
