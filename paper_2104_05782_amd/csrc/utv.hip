@@ -73,16 +73,26 @@ __global__ void k_utv_set_diag(int w, const double* __restrict__ sigma, double* 
   }
 }
 
-__device__ __forceinline__ double xsum(double v, int lane) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    const uint64_t u = (uint64_t)__double_as_longlong(v);
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)u, m, 64);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(u >> 32), m, 64);
-    v += __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-  }
-  (void)lane;
-  return v;
+// Sum over the 64 lanes, the same value in every lane: pairs, quads, 8- and
+// 16-lane mirrors by DPP (ALU latency, no LDS crossbar), then the four row
+// sums read as scalars.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  v += dpp_f64<0x141>(v);
+  v += dpp_f64<0x140>(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// Jacobi rotation of the pair with squared norms al, be and product ga:
+// false when the pair is orthogonal to working accuracy.
+__device__ __forceinline__ bool jacobi_rotation(double al, double be, double ga, double& c, double& sn) {
+  if (ga == 0.0 || !(fabs(ga) > 1e-15 * sqrt(al * be))) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  c = 1.0 / sqrt(1.0 + t * t);
+  sn = c * t;
+  return true;
 }
 
 // SVD of a w x w block M (w <= 64, ld) by one-sided Jacobi (Hestenes): the
@@ -117,35 +127,51 @@ __global__ __launch_bounds__(kSvdThreads) void k_utv_svd(int w, const double* __
     if (tid == 0) s_rot = 0;
     __syncthreads();
     for (int round = 0; round < B - 1; ++round) {
+      // the wavefront's two pairs of this round (disjoint: every column is in
+      // one pair of a round), all their columns read before any is written
+      int p[2], q[2];
+#pragma unroll
       for (int kk = 0; kk < 2; ++kk) {
         const int k = wave * 2 + kk;
-        int p, q;
         if (k == 0) {
-          p = round;
-          q = B - 1;
+          p[kk] = round;
+          q[kk] = B - 1;
         } else {
-          p = (round + k) % (B - 1);
-          q = (round - k + (B - 1)) % (B - 1);
+          p[kk] = (round + k) % (B - 1);
+          q[kk] = (round - k + (B - 1)) % (B - 1);
         }
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
-        const double ap = sA[p][lane], aq = sA[q][lane];
-        const double al = xsum(ap * ap, lane), be = xsum(aq * aq, lane), ga = xsum(ap * aq, lane);
-        if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-          sA[p][lane] = c * ap - sn * aq;
-          sA[q][lane] = sn * ap + c * aq;
-          const double vp = sV[p][lane], vq = sV[q][lane];
-          sV[p][lane] = c * vp - sn * vq;
-          sV[q][lane] = sn * vp + c * vq;
-          if (lane == 0) s_rot = 1;
+        if (p[kk] > q[kk]) {
+          const int t = p[kk];
+          p[kk] = q[kk];
+          q[kk] = t;
         }
       }
+      double ap[2], aq[2], vp[2], vq[2], al[2], be[2], ga[2], c[2], sn[2];
+      bool rot[2];
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {
+        ap[kk] = sA[p[kk]][lane];
+        aq[kk] = sA[q[kk]][lane];
+        vp[kk] = sV[p[kk]][lane];
+        vq[kk] = sV[q[kk]][lane];
+      }
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {
+        al[kk] = wave_sum(ap[kk] * ap[kk]);
+        be[kk] = wave_sum(aq[kk] * aq[kk]);
+        ga[kk] = wave_sum(ap[kk] * aq[kk]);
+      }
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) rot[kk] = jacobi_rotation(al[kk], be[kk], ga[kk], c[kk], sn[kk]);
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {
+        if (!rot[kk]) continue;
+        sA[p[kk]][lane] = c[kk] * ap[kk] - sn[kk] * aq[kk];
+        sA[q[kk]][lane] = sn[kk] * ap[kk] + c[kk] * aq[kk];
+        sV[p[kk]][lane] = c[kk] * vp[kk] - sn[kk] * vq[kk];
+        sV[q[kk]][lane] = sn[kk] * vp[kk] + c[kk] * vq[kk];
+      }
+      if ((rot[0] || rot[1]) && lane == 0) s_rot = 1;
       __syncthreads();
     }
     const int rot = s_rot;
@@ -194,19 +220,22 @@ inline unsigned grid_for(int64_t count) {
 struct UtvWs {
   double* buf = nullptr;
   size_t bytes = 0;
+  hipStream_t side = nullptr;  // each step's SVD and the products that use it
+  hipEvent_t pre = nullptr;    // main stream: the step's diagonal block is final
+  hipEvent_t done = nullptr;   // side stream: the step's block row and column are final
 };
 
 namespace {
 
 struct UtvBufs {
-  double *Y, *P, *Z, *XV, *M, *Vt, *Tp, *sig, *Us, *Vs, *NUsT, *tmp, *tau;
+  double *Y, *P, *Z, *XV, *M, *Vt, *Tp, *sig, *Us, *Vs, *NUsT, *tmp, *tau, *NY;
   int* sweeps;
 };
 
 hipError_t ensure_utv(lupp_handle_t h, int64_t n, UtvBufs* b) {
   const int64_t B = kUtvB;
   const size_t need = sizeof(double) * (size_t)(2 * n * B + B * n + 2 * n * 128 + 128 * n + 128 * 128 + B +
-                                                3 * B * B + n * B + 128 + 64);
+                                                4 * B * B + n * B + 128 + 64);
   if (!h->utv) {
     h->utv = new (std::nothrow) UtvWs();
     if (!h->utv) return hipErrorOutOfMemory;
@@ -244,11 +273,19 @@ hipError_t ensure_utv(lupp_handle_t h, int64_t n, UtvBufs* b) {
   x += B * B;
   b->NUsT = x;
   x += B * B;
+  b->NY = x;
+  x += B * B;
   b->tmp = x;
   x += n * B;
   b->tau = x;
   x += 128;
   b->sweeps = (int*)x;
+  UtvWs* w = h->utv;
+  if (!w->side) {
+    LUPP_TRY(hipStreamCreateWithFlags(&w->side, hipStreamNonBlocking));
+    LUPP_TRY(hipEventCreateWithFlags(&w->pre, hipEventDisableTiming));
+    LUPP_TRY(hipEventCreateWithFlags(&w->done, hipEventDisableTiming));
+  }
   return hipSuccess;
 }
 
@@ -279,6 +316,12 @@ hipError_t right_apply(lupp_handle_t h, const UtvBufs& b, int64_t rows, int64_t 
 
 void free_utv(lupp_handle_t h) {
   if (!h->utv) return;
+  if (h->utv->side) {
+    (void)hipStreamSynchronize(h->utv->side);
+    (void)hipStreamDestroy(h->utv->side);
+  }
+  if (h->utv->pre) (void)hipEventDestroy(h->utv->pre);
+  if (h->utv->done) (void)hipEventDestroy(h->utv->done);
   if (h->utv->buf) (void)hipFree(h->utv->buf);
   delete h->utv;
   h->utv = nullptr;
@@ -300,14 +343,22 @@ hipError_t randutv(lupp_handle_t h, int64_t n, double* A, int64_t lda, int q, co
   };
   if (U) LUPP_TRY(identity(U, ldu));
   if (V) LUPP_TRY(identity(V, ldv));
+  // Each step's SVD and the products that use it run on the side stream, so
+  // that they overlap the next step's sketch and QR: they write only the
+  // step's diagonal block, block row (rows k0 .. k0+w of the columns to the
+  // right), block column above it and columns k0 .. k0+w of U and V, which
+  // the next step does not touch before its right-application to T (it waits
+  // there).  The side stream's buffers (sig, Us, Vs, NUsT, NY, tmp) are its own.
+  hipStream_t ss = h->utv->side;
+  bool side_pending = false;
   // X (rows x w) := X Y (Y w x w, ld 64) through the GEMM: tmp = 0 - X (-Y)
   auto times = [&](double* X, int64_t ldx, int64_t rows, int w, const double* Ysmall) -> hipError_t {
     if (rows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_utv_scale_copy, dim3(grid_for(B * B)), dim3(256), 0, s, B, B, Ysmall, B, b.XV, B, -1.0);
-    hipLaunchKernelGGL(k_utv_fill, dim3(grid_for(rows * w)), dim3(256), 0, s, rows, (int64_t)w, b.tmp, rows, 0.0);
+    hipLaunchKernelGGL(k_utv_scale_copy, dim3(grid_for(B * B)), dim3(256), 0, ss, B, B, Ysmall, B, b.NY, B, -1.0);
+    hipLaunchKernelGGL(k_utv_fill, dim3(grid_for(rows * w)), dim3(256), 0, ss, rows, (int64_t)w, b.tmp, rows, 0.0);
     LUPP_TRY(hipGetLastError());
-    LUPP_TRY(gemm_sub<double>(s, rows, w, w, X, ldx, b.XV, B, b.tmp, rows, nullptr, 2));
-    hipLaunchKernelGGL(k_utv_scale_copy, dim3(grid_for(rows * w)), dim3(256), 0, s, rows, (int64_t)w, b.tmp, rows, X,
+    LUPP_TRY(gemm_sub<double>(ss, rows, w, w, X, ldx, b.NY, B, b.tmp, rows, nullptr, 2));
+    hipLaunchKernelGGL(k_utv_scale_copy, dim3(grid_for(rows * w)), dim3(256), 0, ss, rows, (int64_t)w, b.tmp, rows, X,
                        ldx, 1.0);
     return hipGetLastError();
   };
@@ -330,8 +381,10 @@ hipError_t randutv(lupp_handle_t h, int64_t n, double* A, int64_t lda, int q, co
                            nr, -1.0);  // Y = -Z^T = T22^T T22 Y
         LUPP_TRY(hipGetLastError());
       }
-      // Householder QR of Y; T[:, k0:] and V[:, k0:] times its Q
+      // Householder QR of Y; T[:, k0:] and V[:, k0:] times its Q (after the
+      // previous step's block row is final)
       LUPP_TRY(qr_outer(h, nr, B, b.Y, nr, b.tau, B, true));
+      if (side_pending) LUPP_TRY(hipStreamWaitEvent(s, h->utv->done, 0));
       LUPP_TRY(right_apply(h, b, n, nr, A + k0 * lda, lda, 64, false));
       if (V) LUPP_TRY(right_apply(h, b, n, nr, V + k0 * ldv, ldv, 64, true));
       // ---- U_alpha: Householder QR of T22's first 64 columns, applied to
@@ -344,25 +397,32 @@ hipError_t randutv(lupp_handle_t h, int64_t n, double* A, int64_t lda, int q, co
     } else {
       w = (int)nr;
     }
-    // ---- U_beta, V_beta: SVD of the w x w diagonal block
-    hipLaunchKernelGGL(k_utv_svd, dim3(1), dim3(kSvdThreads), 0, s, w, T22, lda, b.sig, b.Us, b.Vs, b.sweeps);
-    hipLaunchKernelGGL(k_utv_transpose, dim3(2, 2), dim3(256), 0, s, B, B, b.Us, B, b.NUsT, B, -1.0);  // -Us^T
-    hipLaunchKernelGGL(k_utv_set_diag, dim3(1), dim3(256), 0, s, w, b.sig, T22, lda);
+    // ---- U_beta, V_beta: SVD of the w x w diagonal block (side stream)
+    LUPP_TRY(hipEventRecord(h->utv->pre, s));
+    LUPP_TRY(hipStreamWaitEvent(ss, h->utv->pre, 0));
+    hipLaunchKernelGGL(k_utv_svd, dim3(1), dim3(kSvdThreads), 0, ss, w, T22, lda, b.sig, b.Us, b.Vs, b.sweeps);
+    hipLaunchKernelGGL(k_utv_transpose, dim3(2, 2), dim3(256), 0, ss, B, B, b.Us, B, b.NUsT, B, -1.0);  // -Us^T
+    hipLaunchKernelGGL(k_utv_set_diag, dim3(1), dim3(256), 0, ss, w, b.sig, T22, lda);
     LUPP_TRY(hipGetLastError());
     const int64_t nright = n - k0 - w;
     if (nright > 0) {  // T[k0:k0+w, k0+w:] := Us^T T[k0:k0+w, k0+w:]
       double* X = T22 + w * lda;
-      hipLaunchKernelGGL(k_utv_fill, dim3(grid_for(w * nright)), dim3(256), 0, s, (int64_t)w, nright, b.tmp, B, 0.0);
+      hipLaunchKernelGGL(k_utv_fill, dim3(grid_for(w * nright)), dim3(256), 0, ss, (int64_t)w, nright, b.tmp, B,
+                         0.0);
       LUPP_TRY(hipGetLastError());
-      LUPP_TRY(gemm_sub<double>(s, w, nright, w, b.NUsT, B, X, lda, b.tmp, B, nullptr, 2));  // tmp = Us^T X
-      hipLaunchKernelGGL(k_utv_scale_copy, dim3(grid_for(w * nright)), dim3(256), 0, s, (int64_t)w, nright, b.tmp, B,
-                         X, lda, 1.0);
+      LUPP_TRY(gemm_sub<double>(ss, w, nright, w, b.NUsT, B, X, lda, b.tmp, B, nullptr, 2));  // tmp = Us^T X
+      hipLaunchKernelGGL(k_utv_scale_copy, dim3(grid_for(w * nright)), dim3(256), 0, ss, (int64_t)w, nright, b.tmp,
+                         B, X, lda, 1.0);
       LUPP_TRY(hipGetLastError());
     }
     LUPP_TRY(times(A + k0 * lda, lda, k0, w, b.Vs));       // T[:k0, k0:k0+w] := T[:k0, k0:k0+w] Vs
     if (U) LUPP_TRY(times(U + k0 * ldu, ldu, n, w, b.Us));  // U[:, k0:k0+w] := U[:, k0:k0+w] Us
     if (V) LUPP_TRY(times(V + k0 * ldv, ldv, n, w, b.Vs));  // V[:, k0:k0+w] := V[:, k0:k0+w] Vs
+    LUPP_TRY(hipEventRecord(h->utv->done, ss));
+    side_pending = true;
   }
+  // the caller's stream carries the end of the factorization
+  if (side_pending) LUPP_TRY(hipStreamWaitEvent(s, h->utv->done, 0));
   return hipSuccess;
 }
 
