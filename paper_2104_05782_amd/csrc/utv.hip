@@ -85,11 +85,13 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Jacobi rotation of the pair with squared norms al, be and product ga:
-// false when the pair is orthogonal to working accuracy.
-__device__ __forceinline__ bool jacobi_rotation(double al, double be, double ga, double& c, double& sn) {
+// false when the pair is orthogonal to working accuracy.  t = tan(theta)
+// makes the rotated pair orthogonal; the squared norms become al - t ga and
+// be + t ga.
+__device__ __forceinline__ bool jacobi_rotation(double al, double be, double ga, double& c, double& sn, double& t) {
   if (ga == 0.0 || !(fabs(ga) > 1e-15 * sqrt(al * be))) return false;
   const double zeta = (be - al) / (2.0 * ga);
-  const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   c = 1.0 / sqrt(1.0 + t * t);
   sn = c * t;
   return true;
@@ -113,6 +115,7 @@ __global__ __launch_bounds__(kSvdThreads) void k_utv_svd(int w, const double* __
   __shared__ double sA[B][B + 1];  // [column][row]
   __shared__ double sV[B][B + 1];
   __shared__ double s_norm[B];
+  __shared__ double s_n2[B];  // squared column norms, exact at each sweep's start
   __shared__ int s_perm[B];
   __shared__ int s_rot;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -125,6 +128,13 @@ __global__ __launch_bounds__(kSvdThreads) void k_utv_svd(int w, const double* __
   int sweep = 0;
   for (; sweep < kUtvMaxSweeps; ++sweep) {
     if (tid == 0) s_rot = 0;
+#pragma unroll
+    for (int u = 0; u < B / 16; ++u) {  // 16 wavefronts, 4 columns each
+      const int col = wave * (B / 16) + u;
+      const double x = sA[col][lane];
+      const double n2 = wave_sum(x * x);
+      if (lane == 0) s_n2[col] = n2;
+    }
     __syncthreads();
     for (int round = 0; round < B - 1; ++round) {
       // the wavefront's two pairs of this round (disjoint: every column is in
@@ -146,23 +156,32 @@ __global__ __launch_bounds__(kSvdThreads) void k_utv_svd(int w, const double* __
           q[kk] = t;
         }
       }
-      double ap[2], aq[2], vp[2], vq[2], al[2], be[2], ga[2], c[2], sn[2];
-      bool rot[2];
+      double ap[2], aq[2], vp[2], vq[2], al[2], be[2], ga[2];
 #pragma unroll
       for (int kk = 0; kk < 2; ++kk) {
         ap[kk] = sA[p[kk]][lane];
         aq[kk] = sA[q[kk]][lane];
         vp[kk] = sV[p[kk]][lane];
         vq[kk] = sV[q[kk]][lane];
+        al[kk] = s_n2[p[kk]];
+        be[kk] = s_n2[q[kk]];
       }
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) ga[kk] = wave_sum(ap[kk] * aq[kk]);
+      // both pairs' rotations in one pass over the lanes (even lanes: the
+      // first pair, odd lanes: the second), then read back as scalars
+      const int sel = lane & 1;
+      double cl = 1.0, sl = 0.0, tl = 0.0;
+      const bool rl = jacobi_rotation(sel ? al[1] : al[0], sel ? be[1] : be[0], sel ? ga[1] : ga[0], cl, sl, tl);
+      double c[2], sn[2], t[2];
+      bool rot[2];
 #pragma unroll
       for (int kk = 0; kk < 2; ++kk) {
-        al[kk] = wave_sum(ap[kk] * ap[kk]);
-        be[kk] = wave_sum(aq[kk] * aq[kk]);
-        ga[kk] = wave_sum(ap[kk] * aq[kk]);
+        rot[kk] = __builtin_amdgcn_readlane((int)rl, kk) != 0;
+        c[kk] = readlane_d(cl, kk);
+        sn[kk] = readlane_d(sl, kk);
+        t[kk] = readlane_d(tl, kk);
       }
-#pragma unroll
-      for (int kk = 0; kk < 2; ++kk) rot[kk] = jacobi_rotation(al[kk], be[kk], ga[kk], c[kk], sn[kk]);
 #pragma unroll
       for (int kk = 0; kk < 2; ++kk) {
         if (!rot[kk]) continue;
@@ -170,6 +189,10 @@ __global__ __launch_bounds__(kSvdThreads) void k_utv_svd(int w, const double* __
         sA[q[kk]][lane] = sn[kk] * ap[kk] + c[kk] * aq[kk];
         sV[p[kk]][lane] = c[kk] * vp[kk] - sn[kk] * vq[kk];
         sV[q[kk]][lane] = sn[kk] * vp[kk] + c[kk] * vq[kk];
+        if (lane == 0) {
+          s_n2[p[kk]] = al[kk] - t[kk] * ga[kk];
+          s_n2[q[kk]] = be[kk] + t[kk] * ga[kk];
+        }
       }
       if ((rot[0] || rot[1]) && lane == 0) s_rot = 1;
       __syncthreads();
