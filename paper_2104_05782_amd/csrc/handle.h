@@ -24,6 +24,10 @@ struct QrWs {
   double* buf = nullptr;
   size_t bytes = 0;
   int64_t m = 0, n = 0;  // the shape the buffer layout is set for (last ensure_qr)
+  // lookahead: the second V / G / -T^T and the per-stream scratch
+  double* la = nullptr;
+  size_t la_bytes = 0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // factored, T ready, next block, rest
 };
 }  // namespace lupp
 
@@ -129,7 +133,7 @@ hipError_t qr_outer(lupp_handle_t h, int64_t r, int64_t ncols, double* A, int64_
                     bool keep_wy);
 // out (ldw x N) = V^T X, V r x ldw (ldw 32, 64 or 128); part: chunk partials.
 hipError_t qr_tn(hipStream_t s, int64_t r, int64_t N, const double* V, int64_t ldv, const double* X, int64_t ldx,
-                 int ldw, double* part, double* out);
+                 int ldw, double* part, double* out, int64_t chunk_width = 0);
 inline double* qr_v(lupp_handle_t h);
 inline double* qr_tneg(lupp_handle_t h);
 inline double* qr_part(lupp_handle_t h);

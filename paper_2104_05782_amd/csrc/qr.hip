@@ -37,6 +37,7 @@ namespace {
 
 constexpr int kQrW = 32;         // block width (columns per panel launch)
 constexpr int kQrNB = 128;       // outer block width (columns per trailing update)
+constexpr int64_t kQrOverlapMin = (int64_t)1 << 26;  // rows x columns of a rest update worth overlapping
 constexpr int kQrThreads = 512;  // rows per workgroup of the panel kernel
 constexpr long kQrSpin = 1L << 22;
 
@@ -376,19 +377,28 @@ __device__ __forceinline__ double ordered_dot(const double* a, int sa, const dou
 // block), from G = V^T V (128 x 128) and tau (b values): T[j][j] = tau_j,
 // T[:j, j] = -tau_j T[:j, :j] G[:j, j], one column after the other, then
 // written transposed and negated (128 x 128, column-major) for the product
-// W := T^T W = 0 - (-T^T) W on the GEMM.  Column j of G is staged in LDS
-// while column j - 1 is computed, so the dependent chain reads only LDS.
+// W := T^T W = 0 - (-T^T) W on the GEMM.  The dependent chain reads only
+// LDS: each thread keeps its element of the next seven columns of G in
+// registers (loads in flight), and column j + 1 is stored to LDS while
+// column j is computed.
 __global__ __launch_bounds__(kQrNB) void k_qr_larft_big(int b, const double* __restrict__ Gm,
                                                         const double* __restrict__ tau, double* __restrict__ Tneg) {
+  constexpr int kAhead = 7;
   __shared__ double sT[kQrNB][kQrNB + 1];
   __shared__ double sg[2][kQrNB];
   const int tid = threadIdx.x;
   for (int e = tid; e < kQrNB * kQrNB; e += kQrNB) sT[e % kQrNB][e / kQrNB] = 0.0;
   if (b > 0) sg[0][tid] = Gm[tid];
+  double gq[kAhead];  // columns j + 1 .. j + kAhead of G, element tid
+#pragma unroll
+  for (int u = 0; u < kAhead; ++u) gq[u] = (u + 1 < b) ? Gm[tid + (u + 1) * kQrNB] : 0.0;
   __syncthreads();
   for (int j = 0; j < b; ++j) {
     // column j + 1 goes to the buffer read in column j - 1 (two barriers ago)
-    if (j + 1 < b) sg[(j + 1) & 1][tid] = Gm[tid + (j + 1) * kQrNB];
+    if (j + 1 < b) sg[(j + 1) & 1][tid] = gq[0];
+#pragma unroll
+    for (int u = 0; u + 1 < kAhead; ++u) gq[u] = gq[u + 1];
+    gq[kAhead - 1] = (j + 1 + kAhead < b) ? Gm[tid + (j + 1 + kAhead) * kQrNB] : 0.0;
     const double* g = sg[j & 1];
     const double tj = tau[j];
     double t = 0.0;
@@ -477,10 +487,13 @@ int64_t tn_chunks(int64_t r, int64_t N) {
 
 }  // namespace
 
-// out (ldw x N) = V^T X for V of ldw (32, 64 or 128) columns.
+// out (ldw x N) = V^T X for V of ldw (32, 64 or 128) columns.  The rows are
+// split into chunks as for a product of chunk_width columns (default N), so
+// that products over parts of the same columns add their row chunks in the
+// same order.
 hipError_t qr_tn(hipStream_t s, int64_t r, int64_t N, const double* V, int64_t ldv, const double* X, int64_t ldx,
-              int ldw, double* part, double* out) {
-  const int64_t ch = tn_chunks(r, N);
+                 int ldw, double* part, double* out, int64_t chunk_width) {
+  const int64_t ch = tn_chunks(r, chunk_width > N ? chunk_width : N);
   int64_t rpc = (r + ch - 1) / ch;
   rpc = (rpc + 31) / 32 * 32;  // a multiple of every tile depth
   const int64_t nch = (r + rpc - 1) / rpc;
@@ -504,6 +517,9 @@ void free_qr(lupp_handle_t h) {
   if (!h->qr) return;
   if (h->qr->slots) (void)hipFree(h->qr->slots);
   if (h->qr->buf) (void)hipFree(h->qr->buf);
+  if (h->qr->la) (void)hipFree(h->qr->la);
+  for (int e = 0; e < 4; ++e)
+    if (h->qr->ev[e]) (void)hipEventDestroy(h->qr->ev[e]);
   delete h->qr;
   h->qr = nullptr;
 }
@@ -547,33 +563,45 @@ hipError_t ensure_qr(lupp_handle_t h, int64_t m, int64_t n) {
 }
 
 
-// One outer block: factor the first B <= 128 columns of the r x ncols
-// matrix A (32-column blocks with their compact WY updates inside the outer
-// block) and apply Q^T to the columns B .. ncols-1 with one 128-column
-// compact WY update.  Leaves in the workspace the outer block's V (r x 128,
-// explicit: unit diagonal, zeros above, zero columns beyond B) and -T^T of
-// its compact WY form (128 x 128) whenever there are trailing columns or
-// keep_wy is set.
-hipError_t qr_outer(lupp_handle_t h, int64_t r, int64_t ncols, double* A, int64_t lda, double* tau, int64_t B,
-                    bool keep_wy) {
+// Buffers of one outer block's work: its V (r x 128, explicit: unit
+// diagonal, zeros above, zero columns beyond B; ld r), G = V^T V and -T^T
+// (128 x 128 each); the column blocks' G32, T32, W (32 x up to n) and chunk
+// partials; the trailing update's W, W2 (128 x its columns) and partials.
+struct QrBufs {
+  double *V, *G, *Tn;
+  double *G32, *T32, *Wf, *partf;
+  double *W, *W2, *part;
+};
+
+QrBufs qr_default_bufs(lupp_handle_t h) {
   QrWs* q = h->qr;
-  hipStream_t s = h->stream;
   const int64_t m = q->m, n = q->n;
   const int64_t nn = n > kQrNB ? n : kQrNB;
-  double* Vb = q->buf;                        // m x 128 (ld r of the outer block)
-  double* Gb = Vb + (int64_t)kQrNB * m;       // 128 x 128
-  double* Tn = Gb + kQrNB * kQrNB;            // 128 x 128: -T^T
-  double* G32 = Tn + kQrNB * kQrNB;           // 32 x 32
-  double* T32 = G32 + kQrW * kQrW;            // 32 x 32
-  double* Wm = T32 + kQrW * kQrW;             // 128 x n
-  double* W2 = Wm + (int64_t)kQrNB * nn;      // 128 x n
-  double* part = W2 + (int64_t)kQrNB * nn;
-  const int64_t n2 = ncols - B;
-  const bool wy = n2 > 0 || keep_wy;
+  QrBufs w;
+  w.V = q->buf;                          // m x 128
+  w.G = w.V + (int64_t)kQrNB * m;        // 128 x 128
+  w.Tn = w.G + kQrNB * kQrNB;            // 128 x 128: -T^T
+  w.G32 = w.Tn + kQrNB * kQrNB;          // 32 x 32
+  w.T32 = w.G32 + kQrW * kQrW;           // 32 x 32
+  w.W = w.T32 + kQrW * kQrW;             // 128 x n
+  w.W2 = w.W + (int64_t)kQrNB * nn;      // 128 x n
+  w.part = w.W2 + (int64_t)kQrNB * nn;
+  w.Wf = w.W;
+  w.partf = w.part;
+  return w;
+}
+
+// The column blocks of an outer block: factor its first B <= 128 columns of
+// the r x ncols matrix A (32-column panels on stream s) and apply each
+// panel's compact WY form to the columns right of it up to column ce.  With
+// wy, V is written out explicitly for the outer block's own update.
+hipError_t qr_factor(lupp_handle_t h, hipStream_t s, int64_t r, int64_t ce, double* A, int64_t lda, double* tau,
+                     int64_t B, bool wy, const QrBufs& w) {
+  QrWs* q = h->qr;
   if (wy) {  // the outer block's V, zero above each panel's rows
     const int64_t cnt = r * kQrNB;
     hipLaunchKernelGGL(k_qr_zero, dim3((unsigned)((cnt + 255) / 256 < 4096 ? (cnt + 255) / 256 : 4096)), dim3(256), 0,
-                       s, cnt, Vb);
+                       s, cnt, w.V);
     LUPP_TRY(hipGetLastError());
   }
   for (int64_t p0 = 0; p0 < B; p0 += kQrW) {
@@ -586,44 +614,225 @@ hipError_t qr_outer(lupp_handle_t h, int64_t r, int64_t ncols, double* A, int64_
       LUPP_TRY(hipGetLastError());
       q->epoch = 0;
     }
-    double* Vp = Vb + p0 + p0 * r;  // this panel's V: rows p0.., columns p0.. of the outer block's V (ld r)
+    double* Vp = w.V + p0 + p0 * r;  // this panel's V: rows p0.., columns p0.. of the outer block's V (ld r)
     const int t = timer_begin(h, LUPP_PHASE_PANEL, s);
     hipLaunchKernelGGL(k_qr_panel<kQrThreads>, dim3(G), dim3(kQrThreads), 0, s, rp, b, A + p0 + p0 * lda, lda,
                        tau + p0, Vp, r, q->slots, q->epoch);
     LUPP_TRY(hipGetLastError());
     timer_end(h, t, s, 0.0);
     q->epoch += (uint32_t)b + 1u;
-    // the outer block's remaining columns (or, for an outer block with no
-    // trailing columns, every column right of the panel)
-    const int64_t ce = (n2 > 0) ? B : ncols;
     const int64_t nb2 = ce - p0 - b;
     if (nb2 <= 0) continue;
     double* Ab = A + p0 + (p0 + b) * lda;
     const int tu = timer_begin(h, LUPP_PHASE_PANEL_GEMM, s);
-    LUPP_TRY(qr_tn(s, rp, kQrW, Vp, r, Vp, r, kQrW, part, G32));
-    hipLaunchKernelGGL(k_qr_larft, dim3(1), dim3(64), 0, s, b, G32, tau + p0, T32);
-    LUPP_TRY(qr_tn(s, rp, nb2, Vp, r, Ab, lda, kQrW, part, Wm));
-    hipLaunchKernelGGL(k_qr_trmm, dim3((unsigned)((nb2 + 255) / 256)), dim3(256), 0, s, nb2, T32, Wm);
+    LUPP_TRY(qr_tn(s, rp, kQrW, Vp, r, Vp, r, kQrW, w.partf, w.G32));
+    hipLaunchKernelGGL(k_qr_larft, dim3(1), dim3(64), 0, s, b, w.G32, tau + p0, w.T32);
+    LUPP_TRY(qr_tn(s, rp, nb2, Vp, r, Ab, lda, kQrW, w.partf, w.Wf));
+    hipLaunchKernelGGL(k_qr_trmm, dim3((unsigned)((nb2 + 255) / 256)), dim3(256), 0, s, nb2, w.T32, w.Wf);
     LUPP_TRY(hipGetLastError());
-    LUPP_TRY(gemm_sub<double>(s, rp, nb2, kQrW, Vp, r, Wm, kQrW, Ab, lda, nullptr, 2));
+    LUPP_TRY(gemm_sub<double>(s, rp, nb2, kQrW, Vp, r, w.Wf, kQrW, Ab, lda, nullptr, 2));
     timer_end(h, tu, s, 4.0 * (double)rp * (double)nb2 * (double)b);
   }
-  if (!wy) return hipSuccess;
+  return hipSuccess;
+}
+
+// G = V^T V and -T^T of the outer block's B reflectors (stream s; w.part),
+// timed as part of the trailing update.
+hipError_t qr_make_t(lupp_handle_t h, hipStream_t s, int64_t r, int64_t B, const double* tau, const QrBufs& w) {
   const int tu = timer_begin(h, LUPP_PHASE_UPDATE, s);
-  LUPP_TRY(qr_tn(s, r, kQrNB, Vb, r, Vb, r, kQrNB, part, Gb));
-  hipLaunchKernelGGL(k_qr_larft_big, dim3(1), dim3(kQrNB), 0, s, (int)B, Gb, tau, Tn);
+  LUPP_TRY(qr_tn(s, r, kQrNB, w.V, r, w.V, r, kQrNB, w.part, w.G));
+  hipLaunchKernelGGL(k_qr_larft_big, dim3(1), dim3(kQrNB), 0, s, (int)B, w.G, tau, w.Tn);
   LUPP_TRY(hipGetLastError());
-  if (n2 > 0) {
-    double* A2 = A + B * lda;
-    LUPP_TRY(qr_tn(s, r, n2, Vb, r, A2, lda, kQrNB, part, Wm));
-    const int64_t cnt = (int64_t)kQrNB * n2;
-    hipLaunchKernelGGL(k_qr_zero, dim3((unsigned)((cnt + 255) / 256 < 4096 ? (cnt + 255) / 256 : 4096)), dim3(256), 0, s,
-                       cnt, W2);
-    LUPP_TRY(hipGetLastError());
-    LUPP_TRY(gemm_sub<double>(s, kQrNB, n2, kQrNB, Tn, kQrNB, Wm, kQrNB, W2, kQrNB, nullptr, 2));  // W2 = T^T W
-    LUPP_TRY(gemm_sub<double>(s, r, n2, kQrNB, Vb, r, W2, kQrNB, A2, lda, nullptr, 0));           // A2 -= V W2
+  timer_end(h, tu, s, 0.0);
+  return hipSuccess;
+}
+
+// A2 := Q^T A2 = A2 - V (T^T (V^T A2)) for the N columns of A2 (r rows) on
+// stream s; the row chunks of V^T A2 are those of a product of chunk_width
+// columns.
+hipError_t qr_apply(lupp_handle_t h, hipStream_t s, int64_t r, int64_t N, double* A2, int64_t lda, int64_t B,
+                    int64_t chunk_width, const QrBufs& w) {
+  if (N <= 0) return hipSuccess;
+  const int tu = timer_begin(h, LUPP_PHASE_UPDATE, s);
+  LUPP_TRY(qr_tn(s, r, N, w.V, r, A2, lda, kQrNB, w.part, w.W, chunk_width));
+  const int64_t cnt = (int64_t)kQrNB * N;
+  hipLaunchKernelGGL(k_qr_zero, dim3((unsigned)((cnt + 255) / 256 < 4096 ? (cnt + 255) / 256 : 4096)), dim3(256), 0, s,
+                     cnt, w.W2);
+  LUPP_TRY(hipGetLastError());
+  LUPP_TRY(gemm_sub<double>(s, kQrNB, N, kQrNB, w.Tn, kQrNB, w.W, kQrNB, w.W2, kQrNB, nullptr, 2));  // W2 = T^T W
+  LUPP_TRY(gemm_sub<double>(s, r, N, kQrNB, w.V, r, w.W2, kQrNB, A2, lda, nullptr, 0));             // A2 -= V W2
+  timer_end(h, tu, s, 4.0 * (double)r * (double)N * (double)B);
+  return hipSuccess;
+}
+
+// One outer block on the handle's stream: factor the first B <= 128 columns
+// of the r x ncols matrix A (32-column blocks with their compact WY updates
+// inside the outer block) and apply Q^T to the columns B .. ncols-1 with one
+// 128-column compact WY update.  Leaves in the workspace the outer block's V
+// (r x 128, explicit: unit diagonal, zeros above, zero columns beyond B) and
+// -T^T of its compact WY form (128 x 128) whenever there are trailing columns
+// or keep_wy is set.
+hipError_t qr_outer(lupp_handle_t h, int64_t r, int64_t ncols, double* A, int64_t lda, double* tau, int64_t B,
+                    bool keep_wy) {
+  hipStream_t s = h->stream;
+  const QrBufs w = qr_default_bufs(h);
+  const int64_t n2 = ncols - B;
+  const bool wy = n2 > 0 || keep_wy;
+  // the outer block's remaining columns (or, for an outer block with no
+  // trailing columns, every column right of each panel)
+  LUPP_TRY(qr_factor(h, s, r, n2 > 0 ? B : ncols, A, lda, tau, B, wy, w));
+  if (!wy) return hipSuccess;
+  LUPP_TRY(qr_make_t(h, s, r, B, tau, w));
+  return qr_apply(h, s, r, n2, A + B * lda, lda, B, n2, w);
+}
+
+namespace {
+
+// Bytes of the lookahead buffers beyond the default layout: the second V, G
+// and -T^T; W, W2 and partials for the next block's update (128 columns) and
+// for the rest (up to n columns).
+size_t qr_la_bytes(int64_t m, int64_t n) {
+  const int64_t nn = n > kQrNB ? n : kQrNB;
+  const int64_t part = (int64_t)kQrNB * (kTnCols * kTnTarget + nn);
+  return sizeof(double) * (size_t)((int64_t)kQrNB * m + 2 * kQrNB * kQrNB + 2 * kQrNB * kQrNB + part +
+                                   2 * (int64_t)kQrNB * nn + part + 256);
+}
+
+hipError_t ensure_qr_la(lupp_handle_t h, int64_t m, int64_t n) {
+  QrWs* q = h->qr;
+  for (int e = 0; e < 4; ++e)
+    if (!q->ev[e]) LUPP_TRY(hipEventCreateWithFlags(&q->ev[e], hipEventDisableTiming));
+  const size_t need = qr_la_bytes(m, n);
+  if (need > q->la_bytes) {
+    LUPP_TRY(hipStreamSynchronize(h->stream));
+    if (q->la) (void)hipFree(q->la);
+    q->la = nullptr;
+    q->la_bytes = 0;
+    void* p = nullptr;
+    LUPP_TRY(hipMalloc(&p, need));
+    q->la = (double*)p;
+    q->la_bytes = need;
   }
-  timer_end(h, tu, s, 4.0 * (double)r * (double)n2 * (double)B);
+  return hipSuccess;
+}
+
+// Side and bulk streams for a column block whose first panel has G
+// workgroups: the CU partition whose panel CUs hold all of them.
+bool qr_pair(lupp_handle_t h, int G, hipStream_t* side, hipStream_t* bulk) {
+  if (h->side && h->bulk && G <= h->panel_cus) {
+    *side = h->side;
+    *bulk = h->bulk;
+    return true;
+  }
+  if (h->side2 && h->bulk2 && G <= h->panel_cus2) {
+    *side = h->side2;
+    *bulk = h->bulk2;
+    return true;
+  }
+  return false;
+}
+
+}  // namespace
+
+// Lookahead: while block j's compact WY form is applied to the columns beyond
+// block j + 1 on the bulk CUs, block j + 1 (updated first, on the handle's
+// stream) is factored on the panel's CUs.  V, G and -T^T alternate between two
+// buffers by block parity; the next block's update, the rest and the column
+// blocks each have their own scratch.  Every product splits its rows as the
+// whole trailing update would, so the result is the loop's, bit for bit.
+hipError_t geqrf_la(lupp_handle_t h, int64_t m, int64_t n, double* A, int64_t lda, double* tau) {
+  QrWs* q = h->qr;
+  hipStream_t s = h->stream;
+  const int64_t k = m < n ? m : n;
+  const int64_t J = (k + kQrNB - 1) / kQrNB;
+  const int64_t nn = n > kQrNB ? n : kQrNB;
+  const int64_t part = (int64_t)kQrNB * (kTnCols * kTnTarget + nn);
+  QrBufs w[2];
+  w[0] = qr_default_bufs(h);
+  w[1] = w[0];
+  double* x = q->la;
+  w[1].V = x;
+  x += (int64_t)kQrNB * m;
+  w[1].G = x;
+  x += kQrNB * kQrNB;
+  w[1].Tn = x;
+  x += kQrNB * kQrNB;
+  // the next block's update on the handle's stream (both parities)
+  double* Wn = x;
+  x += kQrNB * kQrNB;
+  double* W2n = x;
+  x += kQrNB * kQrNB;
+  double* partn = x;
+  x += part;
+  // the rest on the bulk stream
+  double* Wr = x;
+  x += (int64_t)kQrNB * nn;
+  double* W2r = x;
+  x += (int64_t)kQrNB * nn;
+  double* partr = x;
+  hipEvent_t ev_f = q->ev[0], ev_rest = q->ev[3];
+  bool rest_pending = false, f_side = false;
+  // block 0 on the handle's stream
+  {
+    const int64_t B = k < kQrNB ? k : kQrNB;
+    LUPP_TRY(qr_factor(h, s, m, n - B > 0 ? B : n, A, lda, tau, B, n - B > 0, w[0]));
+  }
+  for (int64_t j = 0; j < J; ++j) {
+    const int64_t j0 = j * kQrNB, r = m - j0, B = (k - j0 < kQrNB) ? (k - j0) : kQrNB;
+    const int64_t n2 = n - j0 - B;
+    double* Aj = A + j0 + j0 * lda;
+    const QrBufs& wj = w[j & 1];
+    if (f_side) LUPP_TRY(hipStreamWaitEvent(s, ev_f, 0));
+    if (rest_pending) LUPP_TRY(hipStreamWaitEvent(s, ev_rest, 0));
+    f_side = rest_pending = false;
+    if (n2 <= 0) break;  // the last block, factored with its columns
+    LUPP_TRY(qr_make_t(h, s, r, B, tau + j0, QrBufs{wj.V, wj.G, wj.Tn, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                                 nullptr, partn}));
+    const int64_t jn0 = j0 + kQrNB;
+    const int64_t Bn = (j + 1 < J) ? ((k - jn0 < kQrNB) ? (k - jn0) : kQrNB) : 0;
+    const int64_t nxt = Bn;  // columns the next block's factorization needs first
+    hipStream_t side = nullptr, bulk = nullptr;
+    const int Gn = Bn > 0 ? (int)((m - jn0 + kQrThreads - 1) / kQrThreads) : 0;
+    // overlap only while the rest of the update outlasts the next block's
+    // factorization on the panel's CUs (about 8192 x 8192 and up); smaller
+    // steps run in order on all CUs
+    const bool overlap = Bn > 0 && n2 - nxt > 0 && r * (n2 - nxt) >= kQrOverlapMin && qr_pair(h, Gn, &side, &bulk);
+    QrBufs wn = wj, wr = wj;
+    wn.W = Wn;
+    wn.W2 = W2n;
+    wn.part = partn;
+    wr.W = Wr;
+    wr.W2 = W2r;
+    wr.part = partr;
+    double* A2 = Aj + B * lda;
+    if (!overlap) {
+      LUPP_TRY(qr_apply(h, s, r, n2, A2, lda, B, n2, wr));
+    } else {
+      LUPP_TRY(hipEventRecord(q->ev[1], s));  // T ready
+      LUPP_TRY(qr_apply(h, s, r, nxt, A2, lda, B, n2, wn));
+      LUPP_TRY(hipEventRecord(q->ev[2], s));  // next block updated
+      LUPP_TRY(hipStreamWaitEvent(bulk, q->ev[1], 0));
+      LUPP_TRY(qr_apply(h, bulk, r, n2 - nxt, A2 + nxt * lda, lda, B, n2, wr));
+      LUPP_TRY(hipEventRecord(ev_rest, bulk));
+      rest_pending = true;
+    }
+    if (Bn > 0) {
+      const int64_t n2n = n - jn0 - Bn;
+      double* An = A + jn0 + jn0 * lda;
+      hipStream_t fs = s;
+      if (overlap) {
+        LUPP_TRY(hipStreamWaitEvent(side, q->ev[2], 0));
+        fs = side;
+      }
+      LUPP_TRY(qr_factor(h, fs, m - jn0, n2n > 0 ? Bn : n - jn0, An, lda, tau + jn0, Bn, n2n > 0, w[(j + 1) & 1]));
+      if (overlap) {
+        LUPP_TRY(hipEventRecord(ev_f, side));
+        f_side = true;
+      }
+    }
+  }
+  if (f_side) LUPP_TRY(hipStreamWaitEvent(s, ev_f, 0));
+  if (rest_pending) LUPP_TRY(hipStreamWaitEvent(s, ev_rest, 0));
   return hipSuccess;
 }
 
@@ -631,11 +840,18 @@ hipError_t qr_outer(lupp_handle_t h, int64_t r, int64_t ncols, double* A, int64_
 // vectors below it, tau[min(m, n)].  Outer blocks of 128 columns: each is
 // factored as four 32-column blocks (the panel kernel, and the compact WY
 // update of the block's remaining columns), then the trailing columns get one
-// 128-column compact WY update: W = V^T A2, W := T^T W, A2 -= V W.
+// 128-column compact WY update: W = V^T A2, W := T^T W, A2 -= V W.  With
+// lookahead (the handle's default) the next outer block is factored on the
+// panel's CUs while the rest of the update runs on the others.
 hipError_t geqrf(lupp_handle_t h, int64_t m, int64_t n, double* A, int64_t lda, double* tau) {
   const int64_t k = m < n ? m : n;
   if (k == 0) return hipSuccess;
   LUPP_TRY(ensure_qr(h, m, n));
+  if (h->lookahead >= 1 && k > kQrNB && ensure_workspace(h) == hipSuccess && h->lookahead >= 1 && h->side &&
+      h->bulk) {
+    LUPP_TRY(ensure_qr_la(h, m, n));
+    return geqrf_la(h, m, n, A, lda, tau);
+  }
   for (int64_t j0 = 0; j0 < k; j0 += kQrNB) {
     const int64_t B = (k - j0 < kQrNB) ? (k - j0) : kQrNB;
     LUPP_TRY(qr_outer(h, m - j0, n - j0, A + j0 + j0 * lda, lda, tau + j0, B, false));

@@ -97,6 +97,34 @@ def test_geqrf_deterministic_and_empty():
     h.close()
 
 
+@pytest.mark.parametrize("shape", [(9000, 9000), (12288, 6000), (6000, 12288), (20000, 4000), (33000, 2300),
+                                   (2600, 1000)])
+def test_geqrf_lookahead_bit_identical(shape):
+    """Lookahead (the next outer block factored on the panel's CUs while the
+    rest of the update runs on the others, for steps whose rest has at least
+    2^26 rows x columns) gives the in-order factors and tau bit for bit: every
+    product splits its rows as the whole update would.  m = 20000 uses the
+    64-CU partition; m = 33000 exceeds both partitions for its first blocks,
+    which then run in order; 2600 x 1000 never reaches the overlap size."""
+    m, n = shape
+    announce("geqrf lookahead %dx%d" % shape)
+    g = torch.Generator(device="cuda").manual_seed(m + 7 * n)
+    A0 = torch.empty((n, m), dtype=torch.float64, device="cuda").t()
+    A0.uniform_(-1.0, 1.0, generator=g)
+    out = []
+    for depth in (1, 0):
+        h = lupp.Handle()
+        h.set_option(4, depth)
+        A = torch.empty_like(A0.t()).t()
+        A.copy_(A0)
+        tau = lupp.geqrf(A, h)
+        h.sync()
+        h.close()
+        out.append((A, tau))
+    assert torch.equal(out[0][1], out[1][1])
+    assert torch.equal(out[0][0], out[1][0])
+
+
 def test_geqrf_argument_errors():
     h = lupp.Handle()
     A = to_dev(np.eye(4))
