@@ -373,45 +373,85 @@ __device__ __forceinline__ double ordered_dot(const double* a, int sa, const dou
   return t;
 }
 
-// -T^T of the compact WY form of up to 128 reflectors (the 128-column outer
-// block), from G = V^T V (128 x 128) and tau (b values): T[j][j] = tau_j,
-// T[:j, j] = -tau_j T[:j, :j] G[:j, j], one column after the other, then
-// written transposed and negated (128 x 128, column-major) for the product
-// W := T^T W = 0 - (-T^T) W on the GEMM.  The dependent chain reads only
-// LDS: each thread keeps its element of the next seven columns of G in
-// registers (loads in flight), and column j + 1 is stored to LDS while
-// column j is computed.
-__global__ __launch_bounds__(kQrNB) void k_qr_larft_big(int b, const double* __restrict__ Gm,
-                                                        const double* __restrict__ tau, double* __restrict__ Tneg) {
-  constexpr int kAhead = 7;
-  __shared__ double sT[kQrNB][kQrNB + 1];
-  __shared__ double sg[2][kQrNB];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kQrNB * kQrNB; e += kQrNB) sT[e % kQrNB][e / kQrNB] = 0.0;
-  if (b > 0) sg[0][tid] = Gm[tid];
-  double gq[kAhead];  // columns j + 1 .. j + kAhead of G, element tid
+// One level of block merges in k_qr_larft_big: the 128 / (2 W) pairs of
+// W-column blocks, 64 rows in all, four threads per row, each with W / 4
+// columns in registers.  Sums run in increasing l (one G load per term of a
+// row, feeding W / 4 columns; the next load is in flight during the FMAs).
+template <int W>
+__device__ __forceinline__ void larft_merge(double (*sT)[kQrNB + 1], const double* __restrict__ Gm, int tid) {
+  constexpr int CR = W / 4;
+  const int R = tid >> 2, cq = tid & 3;
+  const int pr = R / W, ii = R % W, o = 2 * W * pr, c0 = cq * CR;
+  double acc[CR];
 #pragma unroll
-  for (int u = 0; u < kAhead; ++u) gq[u] = (u + 1 < b) ? Gm[tid + (u + 1) * kQrNB] : 0.0;
-  __syncthreads();
-  for (int j = 0; j < b; ++j) {
-    // column j + 1 goes to the buffer read in column j - 1 (two barriers ago)
-    if (j + 1 < b) sg[(j + 1) & 1][tid] = gq[0];
+  for (int u = 0; u < CR; ++u) acc[u] = 0.0;
+  // X[ii][c] = sum_{l <= c} G[o + ii][o + W + l] T2[l][c]
+  const int lend = c0 + CR;  // l <= c < c0 + CR
+  double g = Gm[(o + ii) + (o + W) * kQrNB];
+  for (int l = 0; l < lend; ++l) {
+    const double gn = (l + 1 < lend) ? Gm[(o + ii) + (o + W + l + 1) * kQrNB] : 0.0;
 #pragma unroll
-    for (int u = 0; u + 1 < kAhead; ++u) gq[u] = gq[u + 1];
-    gq[kAhead - 1] = (j + 1 + kAhead < b) ? Gm[tid + (j + 1 + kAhead) * kQrNB] : 0.0;
-    const double* g = sg[j & 1];
-    const double tj = tau[j];
-    double t = 0.0;
-    if (tid < j) t = -tj * ordered_dot(&sT[tid][0], 1, g, tid, j);
-    __syncthreads();
-    if (tid < j) sT[tid][j] = t;
-    if (tid == j) sT[j][j] = tj;
-    __syncthreads();
+    for (int u = 0; u < CR; ++u)
+      if (l <= c0 + u) acc[u] += g * sT[o + W + l][o + W + c0 + u];
+    g = gn;
   }
-  // Tneg[i][l] = -T[l][i]
-  for (int e = tid; e < kQrNB * kQrNB; e += kQrNB) {
+#pragma unroll
+  for (int u = 0; u < CR; ++u) sT[o + W + c0 + u][o + ii] = acc[u];
+  __syncthreads();
+  // T12[ii][c] = -sum_{l >= ii} T1[ii][l] X[l][c]
+#pragma unroll
+  for (int u = 0; u < CR; ++u) acc[u] = 0.0;
+  for (int l = ii; l < W; ++l) {
+    const double t1 = sT[o + ii][o + l];
+#pragma unroll
+    for (int u = 0; u < CR; ++u) acc[u] += t1 * sT[o + W + c0 + u][o + l];
+  }
+#pragma unroll
+  for (int u = 0; u < CR; ++u) sT[o + ii][o + W + c0 + u] = -acc[u];
+  __syncthreads();
+}
+
+// -T^T of the compact WY form of up to 128 reflectors (the 128-column outer
+// block), from G = V^T V (128 x 128) and tau (b values), written transposed
+// and negated (128 x 128, column-major) for the product W := T^T W =
+// 0 - (-T^T) W on the GEMM.  T is built by blocks, with the column recurrence
+// T[:j, j] = -tau_j T[:j, :j] G[:j, j] only inside 32-column blocks: for
+// V = [V1 V2], Q = (I - V1 T1 V1^T)(I - V2 T2 V2^T) = I - V T V^T with
+// T = [T1, -T1 G12 T2; 0, T2], G12 = V1^T V2.  The four 32-column blocks run
+// at once (one wavefront each), then two 32 + 32 merges, then one 64 + 64
+// merge.  G's pieces are staged in T's strictly lower triangle, which T does
+// not use.
+__global__ __launch_bounds__(256) void k_qr_larft_big(int b, const double* __restrict__ Gm,
+                                                      const double* __restrict__ tau, double* __restrict__ Tneg) {
+  __shared__ double sT[kQrNB][kQrNB + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < kQrNB * (kQrNB + 1); e += 256) (&sT[0][0])[e] = 0.0;
+  __syncthreads();
+  // 32-column diagonal blocks: G[c0 + l][c0 + j] (l < j) staged at
+  // sT[c0 + j][c0 + l]; lane i < j forms T[c0 + i][c0 + j] from its own row
+  {
+    const int c0 = 32 * wave;
+    for (int e = lane; e < 32 * 32; e += 64) {
+      const int l = e % 32, jj = e / 32;
+      if (l < jj) sT[c0 + jj][c0 + l] = Gm[(c0 + l) + (c0 + jj) * kQrNB];
+    }
+    __syncthreads();
+    for (int jj = 0; jj < 32 && c0 + jj < b; ++jj) {
+      const double tj = tau[c0 + jj];
+      if (lane < jj) sT[c0 + lane][c0 + jj] = -tj * ordered_dot(&sT[c0 + lane][c0], 1, &sT[c0 + jj][c0], lane, jj);
+      if (lane == jj) sT[c0 + jj][c0 + jj] = tj;
+    }
+  }
+  __syncthreads();
+  // merges of width 32, then 64: block pairs at o = 2 W p.  X = G12 T2 goes
+  // to the strictly lower block sT[o + W + c][o + i] (transposed), then
+  // T12 = -T1 X to sT[o + i][o + W + c]
+  larft_merge<32>(sT, Gm, tid);
+  larft_merge<64>(sT, Gm, tid);
+  // Tneg[i][l] = -T[l][i] (T upper triangular; the lower triangle holds G)
+  for (int e = tid; e < kQrNB * kQrNB; e += 256) {
     const int i = e % kQrNB, l = e / kQrNB;
-    Tneg[e] = -sT[l][i];
+    Tneg[e] = (l <= i) ? -sT[l][i] : 0.0;
   }
 }
 
@@ -641,7 +681,7 @@ hipError_t qr_factor(lupp_handle_t h, hipStream_t s, int64_t r, int64_t ce, doub
 hipError_t qr_make_t(lupp_handle_t h, hipStream_t s, int64_t r, int64_t B, const double* tau, const QrBufs& w) {
   const int tu = timer_begin(h, LUPP_PHASE_UPDATE, s);
   LUPP_TRY(qr_tn(s, r, kQrNB, w.V, r, w.V, r, kQrNB, w.part, w.G));
-  hipLaunchKernelGGL(k_qr_larft_big, dim3(1), dim3(kQrNB), 0, s, (int)B, w.G, tau, w.Tn);
+  hipLaunchKernelGGL(k_qr_larft_big, dim3(1), dim3(256), 0, s, (int)B, w.G, tau, w.Tn);
   LUPP_TRY(hipGetLastError());
   timer_end(h, tu, s, 0.0);
   return hipSuccess;
