@@ -848,7 +848,7 @@ def main():
                 "traffic_note": ("bytes per launch: %.3f x the algorithmic bytes (C read and written, A and B read once; "
                                  "%.4g per launch here), the ratio measured at n = 24576" %
                                  (TRAFFIC_RATIO_FP64_GEMM, alg_bytes / max(1, c))) if traffic else None,
-                "kernel": ("k_dgemm_sub_16<128,128,8,2,4,4,0>" if args.dtype == "f64" else "k_gemm_sub<float,128,128,16,2,2,2>"),
+                "kernel": ("k_dgemm_sub_16<128,128,8,2,4,4,0>" if args.dtype == "f64" else "k_sgemm_sub_16<128,128,16,2,2,2,0>"),
                 "launches_per_step": c // max(1, args.steps),
                 "avg_launch_ms": round(ms / max(1, c), 4),
                 "flops_per_launch": fl / max(1, c)}

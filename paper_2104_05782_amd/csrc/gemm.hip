@@ -171,28 +171,27 @@ __global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_gemm_sub(int64_t M, int
 // accumulators for the 64x32 tile of the 8-wavefront 128x128 launch, four
 // wavefronts per SIMD).  The operands are passed swapped (B first), so each
 // lane holds 16 consecutive rows of a column of C and the stores coalesce.
-// V = 2: interior tiles of 16-byte aligned operands stage A and B with
-// 16-byte loads (two rows of A, two k of B per thread); the k order of the
-// products, hence every result bit, is the same for V = 1 and V = 2.
-template <int BM, int BN, int BK, int WGM, int WGN, bool EDGE, int V = 1>
-__device__ __forceinline__ void dgemm16_body(int64_t M, int64_t N, int64_t K, const double* __restrict__ A,
-                                             int64_t lda, const double* __restrict__ B, int64_t ldb,
-                                             double* __restrict__ C, int64_t ldc, int64_t m0, int64_t n0,
-                                             double* sA, double* sB) {
-  typedef double T;
-  typedef Mfma<double> MF;
+// V > 1: interior tiles of 16-byte aligned operands stage A and B with
+// 16-byte loads (V rows of A, V k of B per thread: V = 2 for FP64, 4 for
+// FP32); the k order of the products, hence every result bit, is the same
+// for V = 1 and V > 1.  The same body serves FP32 on v_mfma_f32_16x16x4f32.
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, bool EDGE, int V = 1>
+__device__ __forceinline__ void gemm16_body(int64_t M, int64_t N, int64_t K, const T* __restrict__ A, int64_t lda,
+                                            const T* __restrict__ B, int64_t ldb, T* __restrict__ C, int64_t ldc,
+                                            int64_t m0, int64_t n0, T* sA, T* sB) {
+  typedef Mfma<T> MF;
   constexpr int NT = 64 * WGM * WGN;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int FM = WTM / 16, FN = WTN / 16;
   constexpr int PAD = 16;  // 128-byte k-row runs, 1152 B apart: two bank passes, no extra conflict
   constexpr int LDSA = BM + PAD, LDSB = BN + PAD;
   constexpr int SA = BK * LDSA, SB = BK * LDSB;
-  static_assert(V == 1 || (V == 2 && !EDGE), "16-byte staging on interior tiles only");
+  static_assert(V == 1 || (V * sizeof(T) == 16 && !EDGE), "16-byte staging on interior tiles only");
   constexpr int TA = BM / V, TB = BK / V;  // threads per k-row of A, per column of B
   constexpr int KA = NT / TA, NB_ = NT / TB;
   constexpr int EA = BK / KA, EB = BN / NB_;
   static_assert(KA * TA == NT && EA * KA == BK && NB_ * TB == NT && EB * NB_ == BN, "thread layout");
-  typedef double V2 __attribute__((ext_vector_type(2)));
+  typedef T VT __attribute__((ext_vector_type(V)));
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
@@ -213,19 +212,19 @@ __device__ __forceinline__ void dgemm16_body(int64_t M, int64_t N, int64_t K, co
 
   T ra[EA * V], rb[EB * V];
   auto gload = [&](int64_t k0) {
-    if (V == 2) {
+    if (V > 1) {
       const T* q = pa + k0 * lda;
 #pragma unroll
       for (int s = 0; s < EA; ++s) {
-        const V2 v = *reinterpret_cast<const V2*>(q + s * astep);
-        ra[2 * s] = v[0];
-        ra[2 * s + 1] = v[1];
+        const VT v = *reinterpret_cast<const VT*>(q + s * astep);
+#pragma unroll
+        for (int e = 0; e < V; ++e) ra[V * s + e] = v[e];
       }
 #pragma unroll
       for (int s = 0; s < EB; ++s) {
-        const V2 v = *reinterpret_cast<const V2*>(pb[s] + k0);
-        rb[2 * s] = v[0];
-        rb[2 * s + 1] = v[1];
+        const VT v = *reinterpret_cast<const VT*>(pb[s] + k0);
+#pragma unroll
+        for (int e = 0; e < V; ++e) rb[V * s + e] = v[e];
       }
     } else if (!EDGE) {
       const T* q = pa + k0 * lda;
@@ -254,19 +253,18 @@ __device__ __forceinline__ void dgemm16_body(int64_t M, int64_t N, int64_t K, co
   auto sstore = [&](int buf) {
     T* a = sA + buf * SA + ak0 * LDSA + ai;
     T* b = sB + buf * SB + bk * LDSB + bn0;
-    if (V == 2) {
+    if (V > 1) {
 #pragma unroll
       for (int s = 0; s < EA; ++s) {
-        V2 v;
-        v[0] = ra[2 * s];
-        v[1] = ra[2 * s + 1];
-        *reinterpret_cast<V2*>(a + s * KA * LDSA) = v;
+        VT v;
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[e] = ra[V * s + e];
+        *reinterpret_cast<VT*>(a + s * KA * LDSA) = v;
       }
 #pragma unroll
-      for (int s = 0; s < EB; ++s) {
-        b[s * NB_] = rb[2 * s];
-        b[s * NB_ + LDSB] = rb[2 * s + 1];
-      }
+      for (int s = 0; s < EB; ++s)
+#pragma unroll
+        for (int e = 0; e < V; ++e) b[s * NB_ + e * LDSB] = rb[V * s + e];
     } else {
 #pragma unroll
       for (int s = 0; s < EA; ++s) a[s * KA * LDSA] = ra[s];
@@ -335,19 +333,13 @@ __device__ __forceinline__ void dgemm16_body(int64_t M, int64_t N, int64_t K, co
   }
 }
 
-// ROLE only names the launch: 0 for the trailing updates on the main and bulk
-// streams, 1 for the share of the remaining-columns update run on the panel's
-// CUs, 2 for the products inside the column-block and triangular-solve
-// recursions.
-template <int BM, int BN, int BK, int WGM, int WGN, int MINB, int ROLE, int GM = kGroupM>
-__global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_dgemm_sub_16(int64_t M, int64_t N, int64_t K,
-                                                                      const double* __restrict__ A, int64_t lda,
-                                                                      const double* __restrict__ B, int64_t ldb,
-                                                                      double* __restrict__ C, int64_t ldc,
-                                                                      int tiles_m, int tiles_n) {
-  constexpr int PAD = 16;
-  __shared__ __attribute__((aligned(16))) double sA[2 * BK * (BM + PAD)];
-  __shared__ double sB[2 * BK * (BN + PAD)];
+// Tile placement and the interior / edge / aligned dispatch of the gemm16
+// kernels.
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int GM>
+__device__ __forceinline__ void gemm16_tile(int64_t M, int64_t N, int64_t K, const T* __restrict__ A, int64_t lda,
+                                            const T* __restrict__ B, int64_t ldb, T* __restrict__ C, int64_t ldc,
+                                            int tiles_m, int tiles_n, T* sA, T* sB) {
+  constexpr int V = 16 / (int)sizeof(T);
   const int total = tiles_m * tiles_n;
   const int per_xcd = (total + kXcds - 1) / kXcds;
   const int bid = blockIdx.x;
@@ -361,14 +353,46 @@ __global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_dgemm_sub_16(int64_t M,
   const int tm = first_m + within % gm;
   const int tn = within / gm;
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
-  const bool vec = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0 && ((lda | ldb) & 1) == 0;
+  const bool vec = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0 && lda % V == 0 &&
+                   ldb % V == 0;
   if (m0 + BM <= M && n0 + BN <= N && K % BK == 0) {
     if (vec)
-      dgemm16_body<BM, BN, BK, WGM, WGN, false, 2>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sA, sB);
+      gemm16_body<T, BM, BN, BK, WGM, WGN, false, V>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sA, sB);
     else
-      dgemm16_body<BM, BN, BK, WGM, WGN, false, 1>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sA, sB);
-  } else
-    dgemm16_body<BM, BN, BK, WGM, WGN, true>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sA, sB);
+      gemm16_body<T, BM, BN, BK, WGM, WGN, false, 1>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sA, sB);
+  } else {
+    gemm16_body<T, BM, BN, BK, WGM, WGN, true, 1>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sA, sB);
+  }
+}
+
+// ROLE only names the launch: 0 for the trailing updates on the main and bulk
+// streams, 1 for the share of the remaining-columns update run on the panel's
+// CUs, 2 for the products inside the column-block and triangular-solve
+// recursions.
+template <int BM, int BN, int BK, int WGM, int WGN, int MINB, int ROLE, int GM = kGroupM>
+__global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_dgemm_sub_16(int64_t M, int64_t N, int64_t K,
+                                                                      const double* __restrict__ A, int64_t lda,
+                                                                      const double* __restrict__ B, int64_t ldb,
+                                                                      double* __restrict__ C, int64_t ldc,
+                                                                      int tiles_m, int tiles_n) {
+  constexpr int PAD = 16;
+  __shared__ __attribute__((aligned(16))) double sA[2 * BK * (BM + PAD)];
+  __shared__ double sB[2 * BK * (BN + PAD)];
+  gemm16_tile<double, BM, BN, BK, WGM, WGN, GM>(M, N, K, A, lda, B, ldb, C, ldc, tiles_m, tiles_n, sA, sB);
+}
+
+// FP32 C -= A * B on v_mfma_f32_16x16x4f32 with the same body (16-byte
+// staging: four rows of A, four k of B per thread on interior tiles).
+template <int BM, int BN, int BK, int WGM, int WGN, int MINB, int ROLE, int GM = kGroupM>
+__global__ __launch_bounds__(64 * WGM* WGN, MINB) void k_sgemm_sub_16(int64_t M, int64_t N, int64_t K,
+                                                                      const float* __restrict__ A, int64_t lda,
+                                                                      const float* __restrict__ B, int64_t ldb,
+                                                                      float* __restrict__ C, int64_t ldc,
+                                                                      int tiles_m, int tiles_n) {
+  constexpr int PAD = 16;
+  __shared__ __attribute__((aligned(16))) float sA[2 * BK * (BM + PAD)];
+  __shared__ float sB[2 * BK * (BN + PAD)];
+  gemm16_tile<float, BM, BN, BK, WGM, WGN, GM>(M, N, K, A, lda, B, ldb, C, ldc, tiles_m, tiles_n, sA, sB);
 }
 
 namespace {
@@ -397,6 +421,18 @@ hipError_t launch_d16(hipStream_t s, int64_t M, int64_t N, int64_t K, const doub
   return hipGetLastError();
 }
 
+template <int BM, int BN, int BK, int WGM, int WGN, int MINB, int ROLE = 0, int GM = kGroupM>
+hipError_t launch_s16(hipStream_t s, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, const float* B,
+                      int64_t ldb, float* C, int64_t ldc) {
+  const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
+  if (tm * tn > (int64_t)1 << 30) return hipErrorInvalidValue;
+  const int total = (int)(tm * tn);
+  const int per_xcd = (total + kXcds - 1) / kXcds;
+  hipLaunchKernelGGL((k_sgemm_sub_16<BM, BN, BK, WGM, WGN, MINB, ROLE, GM>), dim3(per_xcd * kXcds),
+                     dim3(64 * WGM * WGN), 0, s, M, N, K, A, lda, B, ldb, C, ldc, (int)tm, (int)tn);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 template <typename T>
@@ -421,9 +457,11 @@ hipError_t gemm_sub(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, 
     tile = 2;
     return launch_d16<64, 64, 8, 2, 2, 4>(s, M, N, K, A, lda, B, ldb, C, ldc);
   } else {
-    if (big_tiles >= 512) {
+    if (big_tiles >= 512 || (role == 1 && big_tiles >= 32)) {
       tile = 1;
-      return launch<T, 128, 128, 16, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
+      if (role == 1) return launch_s16<128, 128, 16, 2, 2, 2, 1>(s, M, N, K, A, lda, B, ldb, C, ldc);
+      if (role == 2) return launch_s16<128, 128, 16, 2, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
+      return launch_s16<128, 128, 16, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
     }
     tile = 2;
     return launch<T, 64, 64, 16, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
