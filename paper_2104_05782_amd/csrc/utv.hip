@@ -244,8 +244,12 @@ struct UtvWs {
   double* buf = nullptr;
   size_t bytes = 0;
   hipStream_t side = nullptr;  // each step's SVD and the products that use it
+  hipStream_t uv = nullptr;    // the products of U and V with the Householder factors
   hipEvent_t pre = nullptr;    // main stream: the step's diagonal block is final
   hipEvent_t done = nullptr;   // side stream: the step's block row and column are final
+  hipEvent_t snap[2] = {nullptr, nullptr};     // main stream: a copy set of the factors is written
+  hipEvent_t uv_done[2] = {nullptr, nullptr};  // uv stream: a copy set has been used
+  hipEvent_t tail = nullptr;                   // side stream: the step's U and V columns are final
 };
 
 namespace {
@@ -253,12 +257,16 @@ namespace {
 struct UtvBufs {
   double *Y, *P, *Z, *XV, *M, *Vt, *Tp, *sig, *Us, *Vs, *NUsT, *tmp, *tau, *NY;
   int* sweeps;
+  // the uv stream's copies of a step's two compact WY forms (V: r x 64,
+  // T: 128 x 128, V^T: 64 x r), by step parity, and its XV, M (n x 64)
+  double *SVa[2], *STa[2], *SVta[2], *SVu[2], *STu[2], *SVtu[2], *SXV, *SM;
 };
 
 hipError_t ensure_utv(lupp_handle_t h, int64_t n, UtvBufs* b) {
   const int64_t B = kUtvB;
   const size_t need = sizeof(double) * (size_t)(2 * n * B + B * n + 2 * n * 128 + 128 * n + 128 * 128 + B +
-                                                4 * B * B + n * B + 128 + 64);
+                                                4 * B * B + n * B + 128 + 64 + 2 * (4 * n * B + 2 * 128 * 128) +
+                                                2 * n * B);
   if (!h->utv) {
     h->utv = new (std::nothrow) UtvWs();
     if (!h->utv) return hipErrorOutOfMemory;
@@ -303,35 +311,60 @@ hipError_t ensure_utv(lupp_handle_t h, int64_t n, UtvBufs* b) {
   b->tau = x;
   x += 128;
   b->sweeps = (int*)x;
+  x += 64;
+  for (int p = 0; p < 2; ++p) {
+    b->SVa[p] = x;
+    x += n * B;
+    b->SVta[p] = x;
+    x += n * B;
+    b->SVu[p] = x;
+    x += n * B;
+    b->SVtu[p] = x;
+    x += n * B;
+    b->STa[p] = x;
+    x += 128 * 128;
+    b->STu[p] = x;
+    x += 128 * 128;
+  }
+  b->SXV = x;
+  x += n * B;
+  b->SM = x;
   UtvWs* w = h->utv;
   if (!w->side) {
     LUPP_TRY(hipStreamCreateWithFlags(&w->side, hipStreamNonBlocking));
+    LUPP_TRY(hipStreamCreateWithFlags(&w->uv, hipStreamNonBlocking));
     LUPP_TRY(hipEventCreateWithFlags(&w->pre, hipEventDisableTiming));
     LUPP_TRY(hipEventCreateWithFlags(&w->done, hipEventDisableTiming));
+    LUPP_TRY(hipEventCreateWithFlags(&w->tail, hipEventDisableTiming));
+    for (int p = 0; p < 2; ++p) {
+      LUPP_TRY(hipEventCreateWithFlags(&w->snap[p], hipEventDisableTiming));
+      LUPP_TRY(hipEventCreateWithFlags(&w->uv_done[p], hipEventDisableTiming));
+    }
   }
   return hipSuccess;
 }
 
-// X (rows x r, ldx) := X Q with Q = I - V T V^T the compact WY form left by
-// qr_outer (V: r x kb at qr_v, ld r; -T^T at qr_tneg, ld 128), kb = 64 or 128:
-// X V, then (X V) T, then X -= ((X V) T) V^T.
-hipError_t right_apply(lupp_handle_t h, const UtvBufs& b, int64_t rows, int64_t r, double* X, int64_t ldx, int kb,
-                       bool prepared) {
-  hipStream_t s = h->stream;
-  const double* V = qr_v(h);
-  if (!prepared) {  // T = -(-T^T)^T and V^T, once per Q
-    hipLaunchKernelGGL(k_utv_transpose, dim3(4, 4), dim3(256), 0, s, (int64_t)128, (int64_t)128, qr_tneg(h),
-                       (int64_t)128, b.Tp, (int64_t)128, -1.0);
-    hipLaunchKernelGGL(k_utv_transpose, dim3((unsigned)((r + 31) / 32), (unsigned)((kb + 31) / 32)), dim3(256), 0, s,
-                       r, (int64_t)kb, V, r, b.Vt, (int64_t)kb, 1.0);
-    LUPP_TRY(hipGetLastError());
-  }
-  hipLaunchKernelGGL(k_utv_fill, dim3(grid_for(rows * kb)), dim3(256), 0, s, rows, (int64_t)kb, b.XV, rows, 0.0);
-  hipLaunchKernelGGL(k_utv_fill, dim3(grid_for(rows * kb)), dim3(256), 0, s, rows, (int64_t)kb, b.M, rows, 0.0);
+// T = -(-T^T)^T and V^T of the compact WY form left by qr_outer (V: r x kb
+// at qr_v, ld r; -T^T at qr_tneg, ld 128) into Tp (128 x 128) and Vt (kb x r).
+hipError_t prepare_wy(lupp_handle_t h, hipStream_t s, int64_t r, int kb, double* Tp, double* Vt) {
+  hipLaunchKernelGGL(k_utv_transpose, dim3(4, 4), dim3(256), 0, s, (int64_t)128, (int64_t)128, qr_tneg(h),
+                     (int64_t)128, Tp, (int64_t)128, -1.0);
+  hipLaunchKernelGGL(k_utv_transpose, dim3((unsigned)((r + 31) / 32), (unsigned)((kb + 31) / 32)), dim3(256), 0, s, r,
+                     (int64_t)kb, qr_v(h), r, Vt, (int64_t)kb, 1.0);
+  return hipGetLastError();
+}
+
+// X (rows x r, ldx) := X Q with Q = I - V T V^T (V: r x kb, ld r; T: Tp,
+// ld 128; V^T: Vt, ld kb), kb = 64 or 128, on stream s: X V, then (X V) T,
+// then X -= ((X V) T) V^T (XV and M: rows x kb each).
+hipError_t right_apply(hipStream_t s, const double* V, const double* Tp, const double* Vt, double* XV, double* M,
+                       int64_t rows, int64_t r, double* X, int64_t ldx, int kb) {
+  hipLaunchKernelGGL(k_utv_fill, dim3(grid_for(rows * kb)), dim3(256), 0, s, rows, (int64_t)kb, XV, rows, 0.0);
+  hipLaunchKernelGGL(k_utv_fill, dim3(grid_for(rows * kb)), dim3(256), 0, s, rows, (int64_t)kb, M, rows, 0.0);
   LUPP_TRY(hipGetLastError());
-  LUPP_TRY(gemm_sub<double>(s, rows, kb, r, X, ldx, V, r, b.XV, rows, nullptr, 2));      // XV = -X V
-  LUPP_TRY(gemm_sub<double>(s, rows, kb, kb, b.XV, rows, b.Tp, 128, b.M, rows, nullptr, 2));  // M = X V T
-  LUPP_TRY(gemm_sub<double>(s, rows, r, kb, b.M, rows, b.Vt, kb, X, ldx, nullptr, 2));  // X -= M V^T
+  LUPP_TRY(gemm_sub<double>(s, rows, kb, r, X, ldx, V, r, XV, rows, nullptr, 2));      // XV = -X V
+  LUPP_TRY(gemm_sub<double>(s, rows, kb, kb, XV, rows, Tp, 128, M, rows, nullptr, 2));  // M = X V T
+  LUPP_TRY(gemm_sub<double>(s, rows, r, kb, M, rows, Vt, kb, X, ldx, nullptr, 2));     // X -= M V^T
   return hipSuccess;
 }
 
@@ -339,12 +372,14 @@ hipError_t right_apply(lupp_handle_t h, const UtvBufs& b, int64_t rows, int64_t 
 
 void free_utv(lupp_handle_t h) {
   if (!h->utv) return;
-  if (h->utv->side) {
-    (void)hipStreamSynchronize(h->utv->side);
-    (void)hipStreamDestroy(h->utv->side);
-  }
-  if (h->utv->pre) (void)hipEventDestroy(h->utv->pre);
-  if (h->utv->done) (void)hipEventDestroy(h->utv->done);
+  UtvWs* w = h->utv;
+  for (hipStream_t st : {w->side, w->uv})
+    if (st) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
+  for (hipEvent_t e : {w->pre, w->done, w->tail, w->snap[0], w->snap[1], w->uv_done[0], w->uv_done[1]})
+    if (e) (void)hipEventDestroy(e);
   if (h->utv->buf) (void)hipFree(h->utv->buf);
   delete h->utv;
   h->utv = nullptr;
@@ -369,11 +404,19 @@ hipError_t randutv(lupp_handle_t h, int64_t n, double* A, int64_t lda, int q, co
   // Each step's SVD and the products that use it run on the side stream, so
   // that they overlap the next step's sketch and QR: they write only the
   // step's diagonal block, block row (rows k0 .. k0+w of the columns to the
-  // right), block column above it and columns k0 .. k0+w of U and V, which
-  // the next step does not touch before its right-application to T (it waits
-  // there).  The side stream's buffers (sig, Us, Vs, NUsT, NY, tmp) are its own.
-  hipStream_t ss = h->utv->side;
+  // right), block column above it and columns k0 .. of U and V, which the
+  // next step does not touch before its right-application to T (it waits
+  // there).  The step's products of U and V with its two orthogonal factors
+  // also run there, from copies of their compact WY forms (SVa .. SVtu) that
+  // the main stream writes after that wait.  The side stream's other buffers
+  // (sig, Us, Vs, NUsT, NY, tmp) are its own; XV and M are shared, used by
+  // the main stream only before the step's hand-off and after the wait.
+  hipStream_t ss = h->utv->side, su = h->utv->uv;
+  UtvWs* uw = h->utv;
   bool side_pending = false;
+  int uv_last = -1;         // parity of the uv stream's last recorded step, -1 before any
+  bool uv_used[2] = {false, false};
+  int step = 0;
   // X (rows x w) := X Y (Y w x w, ld 64) through the GEMM: tmp = 0 - X (-Y)
   auto times = [&](double* X, int64_t ldx, int64_t rows, int w, const double* Ysmall) -> hipError_t {
     if (rows <= 0) return hipSuccess;
@@ -408,21 +451,49 @@ hipError_t randutv(lupp_handle_t h, int64_t n, double* A, int64_t lda, int q, co
       // previous step's block row is final)
       LUPP_TRY(qr_outer(h, nr, B, b.Y, nr, b.tau, B, true));
       if (side_pending) LUPP_TRY(hipStreamWaitEvent(s, h->utv->done, 0));
-      LUPP_TRY(right_apply(h, b, n, nr, A + k0 * lda, lda, 64, false));
-      if (V) LUPP_TRY(right_apply(h, b, n, nr, V + k0 * ldv, ldv, 64, true));
+      LUPP_TRY(prepare_wy(h, s, nr, 64, b.Tp, b.Vt));
+      LUPP_TRY(right_apply(s, qr_v(h), b.Tp, b.Vt, b.XV, b.M, n, nr, A + k0 * lda, lda, 64));
+      const int par = step & 1;
+      // the copy set of this parity was last read by the uv stream two steps ago
+      if ((U || V) && uv_used[par]) LUPP_TRY(hipStreamWaitEvent(s, uw->uv_done[par], 0));
+      if (V) {  // V[:, k0:] times this Q on the uv stream: copy the form
+        hipLaunchKernelGGL(k_utv_scale_copy, dim3(grid_for(nr * B)), dim3(256), 0, s, nr, B, qr_v(h), nr,
+                           b.SVa[par], nr, 1.0);
+        hipLaunchKernelGGL(k_utv_scale_copy, dim3(grid_for(128 * 128)), dim3(256), 0, s, (int64_t)128, (int64_t)128,
+                           b.Tp, (int64_t)128, b.STa[par], (int64_t)128, 1.0);
+        hipLaunchKernelGGL(k_utv_scale_copy, dim3(grid_for(nr * B)), dim3(256), 0, s, B, nr, b.Vt, B, b.SVta[par], B,
+                           1.0);
+        LUPP_TRY(hipGetLastError());
+      }
       // ---- U_alpha: Householder QR of T22's first 64 columns, applied to
-      // the rest of T22; U[:, k0:] times its Q; the block column below the
-      // diagonal (the reflectors) becomes 0
+      // the rest of T22; U[:, k0:] times its Q (side stream, from a copy of
+      // its form); the block column below the diagonal (the reflectors) becomes 0
       LUPP_TRY(qr_outer(h, nr, nr, T22, lda, b.tau, B, true));
-      if (U) LUPP_TRY(right_apply(h, b, n, nr, U + k0 * ldu, ldu, 64, false));
+      if (U) {
+        LUPP_TRY(prepare_wy(h, s, nr, 64, b.STu[par], b.SVtu[par]));
+        hipLaunchKernelGGL(k_utv_scale_copy, dim3(grid_for(nr * B)), dim3(256), 0, s, nr, B, qr_v(h), nr,
+                           b.SVu[par], nr, 1.0);
+        LUPP_TRY(hipGetLastError());
+      }
       hipLaunchKernelGGL(k_utv_zero_lower, dim3(grid_for(nr * B)), dim3(256), 0, s, nr, (int)B, T22, lda);
       LUPP_TRY(hipGetLastError());
+      if (U || V) {  // the uv stream: V[:, k0:] and U[:, k0:] times the step's two factors
+        LUPP_TRY(hipEventRecord(uw->snap[par], s));
+        LUPP_TRY(hipStreamWaitEvent(su, uw->snap[par], 0));
+        if (V) LUPP_TRY(right_apply(su, b.SVa[par], b.STa[par], b.SVta[par], b.SXV, b.SM, n, nr, V + k0 * ldv, ldv, 64));
+        if (U) LUPP_TRY(right_apply(su, b.SVu[par], b.STu[par], b.SVtu[par], b.SXV, b.SM, n, nr, U + k0 * ldu, ldu, 64));
+        LUPP_TRY(hipEventRecord(uw->uv_done[par], su));
+        uv_used[par] = true;
+        uv_last = par;
+      }
     } else {
       w = (int)nr;
     }
-    // ---- U_beta, V_beta: SVD of the w x w diagonal block (side stream)
+    // ---- U_beta, V_beta: SVD of the w x w diagonal block (side stream),
+    // after the step's products of V and U with its two Householder factors
     LUPP_TRY(hipEventRecord(h->utv->pre, s));
     LUPP_TRY(hipStreamWaitEvent(ss, h->utv->pre, 0));
+
     hipLaunchKernelGGL(k_utv_svd, dim3(1), dim3(kSvdThreads), 0, ss, w, T22, lda, b.sig, b.Us, b.Vs, b.sweeps);
     hipLaunchKernelGGL(k_utv_transpose, dim3(2, 2), dim3(256), 0, ss, B, B, b.Us, B, b.NUsT, B, -1.0);  // -Us^T
     hipLaunchKernelGGL(k_utv_set_diag, dim3(1), dim3(256), 0, ss, w, b.sig, T22, lda);
@@ -439,13 +510,20 @@ hipError_t randutv(lupp_handle_t h, int64_t n, double* A, int64_t lda, int q, co
       LUPP_TRY(hipGetLastError());
     }
     LUPP_TRY(times(A + k0 * lda, lda, k0, w, b.Vs));       // T[:k0, k0:k0+w] := T[:k0, k0:k0+w] Vs
-    if (U) LUPP_TRY(times(U + k0 * ldu, ldu, n, w, b.Us));  // U[:, k0:k0+w] := U[:, k0:k0+w] Us
-    if (V) LUPP_TRY(times(V + k0 * ldv, ldv, n, w, b.Vs));  // V[:, k0:k0+w] := V[:, k0:k0+w] Vs
-    LUPP_TRY(hipEventRecord(h->utv->done, ss));
+    LUPP_TRY(hipEventRecord(uw->done, ss));
     side_pending = true;
+    if (U || V) {  // after the uv stream's products over these columns
+      if (uv_last >= 0) LUPP_TRY(hipStreamWaitEvent(ss, uw->uv_done[uv_last], 0));
+      if (U) LUPP_TRY(times(U + k0 * ldu, ldu, n, w, b.Us));  // U[:, k0:k0+w] := U[:, k0:k0+w] Us
+      if (V) LUPP_TRY(times(V + k0 * ldv, ldv, n, w, b.Vs));  // V[:, k0:k0+w] := V[:, k0:k0+w] Vs
+      LUPP_TRY(hipEventRecord(uw->tail, ss));
+    }
+    ++step;
   }
   // the caller's stream carries the end of the factorization
-  if (side_pending) LUPP_TRY(hipStreamWaitEvent(s, h->utv->done, 0));
+  if (side_pending) LUPP_TRY(hipStreamWaitEvent(s, uw->done, 0));
+  if ((U || V) && side_pending) LUPP_TRY(hipStreamWaitEvent(s, uw->tail, 0));
+  if (uv_last >= 0) LUPP_TRY(hipStreamWaitEvent(s, uw->uv_done[uv_last], 0));
   return hipSuccess;
 }
 
