@@ -464,7 +464,9 @@ hipError_t gemm_sub(hipStream_t s, int64_t M, int64_t N, int64_t K, const T* A, 
       return launch_s16<128, 128, 16, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
     }
     tile = 2;
-    return launch<T, 64, 64, 16, 2, 2, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
+    if (role == 1) return launch_s16<64, 64, 16, 2, 2, 4, 1>(s, M, N, K, A, lda, B, ldb, C, ldc);
+    if (role == 2) return launch_s16<64, 64, 16, 2, 2, 4, 2>(s, M, N, K, A, lda, B, ldb, C, ldc);
+    return launch_s16<64, 64, 16, 2, 2, 4>(s, M, N, K, A, lda, B, ldb, C, ldc);
   }
 }
 
