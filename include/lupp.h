@@ -58,7 +58,7 @@ enum {
 enum {
   LUPP_OPT_NB = 1,         /* outer block size b of the right-looking loop (default 512)  */
   LUPP_OPT_PANEL_LEAF = 2, /* widest column block factored in one cooperative launch
-                              (16 .. 256, a multiple of 16; default 128); wider blocks
+                              (16 .. 256, a multiple of 16; default 64); wider blocks
                               split recursively with a triangular solve and a GEMM      */
   LUPP_OPT_TIMING = 3,     /* 1: record HIP events around every phase of xGETRF (below);
                               2: around the trailing updates only (LUPP_PHASE_UPDATE and

@@ -35,7 +35,7 @@ struct lupp_handle_st {
   int device = 0;
   hipStream_t stream = nullptr;
   int64_t nb = 512;
-  int block = 128;                  // widest column block factored in one cooperative launch
+  int block = 64;                   // widest column block factored in one cooperative launch
   lupp::LeafSlots* slots = nullptr;
   lupp::SwapPairs* pairs = nullptr;
   // deferred interchanges of the finished columns: per-step pairs, the gather
