@@ -80,7 +80,7 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
-TRAFFIC_RATIO_FP64_GEMM = 1.797  # HBM bytes / algorithmic bytes, k_dgemm_sub_16 role 0, n = 24576 counters
+TRAFFIC_RATIO_FP64_GEMM = 1.808  # HBM bytes / algorithmic bytes, k_dgemm_sub_16 role 0, n = 24576 counters
 
 
 def log(msg):
@@ -837,7 +837,7 @@ def main():
     peak = FP64_PEAK_TFLOPS if args.dtype == "f64" else FP32_PEAK_TFLOPS
     achieved = (fl / (ms * 1e-3) / 1e12) if ms > 0 else 0.0
     # HBM traffic of this kernel: the calibrated FETCH_SIZE + WRITE_SIZE of its
-    # launches over their algorithmic bytes, 1.797 at n = 24576 (the largest
+    # launches over their algorithmic bytes, 1.808 at n = 24576 (the largest
     # size at which the profiler's counter mode has run; profiles/
     # lupp_n24576_counters.md), applied to this run's algorithmic bytes per launch
     traffic = None
