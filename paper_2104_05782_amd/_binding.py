@@ -39,6 +39,7 @@ OPT_LOOKAHEAD = 4
 OPT_UPDATE_PREC = 5
 OPT_DEFER_SWAPS = 6
 OPT_SPLIT_UPDATE = 7
+OPT_LP_PACKED = 8
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "fp8": 3}
 IR_SOLVER = {"classical": 0, "gmres": 1}
 IR_STATUS = {0: "converged", 1: "stagnated", 2: "diverged", 3: "singular", 4: "maxiter"}

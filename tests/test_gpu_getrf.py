@@ -455,6 +455,46 @@ def test_dataflow_scaled_low_precision_bit_identical():
     assert torch.equal(ref[1], out[1]) and torch.equal(ref[0], out[0])
 
 
+def test_option_ranges():
+    """lupp_set_option accepts each option's documented range and rejects the
+    rest with -3 (value) or -2 (unknown option), leaving the handle usable."""
+    b = lupp._binding
+    h = lupp.Handle()
+    lib = b._lib
+    cases = {b.OPT_NB: ([1, 512, 1024], [0, 1025]),
+             b.OPT_PANEL_LEAF: ([16, 64, 256], [0, 8, 24, 272]),
+             b.OPT_TIMING: ([0, 1, 2], [-1, 3]),
+             b.OPT_LOOKAHEAD: ([0, 1, 2, 16], [-1, 17]),
+             b.OPT_UPDATE_PREC: ([0, 1, 2, 3], [-1, 4]),
+             b.OPT_DEFER_SWAPS: ([0, 1], [2]),
+             b.OPT_SPLIT_UPDATE: ([0, 1], [-1, 2]),
+             b.OPT_LP_PACKED: ([0, 1], [2])}
+    for opt, (good, bad) in cases.items():
+        for v in good:
+            assert lib.lupp_set_option(h.ptr, opt, v) == 0, (opt, v)
+        for v in bad:
+            assert lib.lupp_set_option(h.ptr, opt, v) == -3, (opt, v)
+    for opt in (0, 9, 100):
+        assert lib.lupp_set_option(h.ptr, opt, 1) == -2, opt
+    # restore the defaults and factor once
+    for opt, v in ((b.OPT_NB, 512), (b.OPT_PANEL_LEAF, 64), (b.OPT_TIMING, 0), (b.OPT_LOOKAHEAD, 1),
+                   (b.OPT_UPDATE_PREC, 0), (b.OPT_DEFER_SWAPS, 1), (b.OPT_SPLIT_UPDATE, 1), (b.OPT_LP_PACKED, 1)):
+        h.set_option(opt, v)
+    n = 1000
+    g = torch.Generator(device="cuda").manual_seed(46)
+    A0 = torch.empty((n, n), dtype=torch.float64, device="cuda").t()
+    A0.uniform_(-1.0, 1.0, generator=g)
+    A = torch.empty_like(A0.t()).t()
+    A.copy_(A0)
+    ipiv = torch.empty(n, dtype=torch.int32, device="cuda")
+    info = torch.empty(1, dtype=torch.int32, device="cuda")
+    lupp.lupp_dgetrf(A, ipiv, info, handle=h)
+    h.sync()
+    h.close()
+    assert int(info.item()) == 0
+    assert _probe_residual(A0, A, ipiv) < 10 * checks.U64
+
+
 def test_split_update_low_precision():
     """The same split with BF16 updates (each share scales its own blocks):
     a valid factorization within the update format's residual bound."""
