@@ -447,10 +447,16 @@ int lupp_sgetrf_batched(lupp_handle_t h, int32_t batch, const int32_t* dn, const
  * Per block of 32 columns: the block's reflectors (one cooperative launch,
  * one exchange between workgroups per column), T with H_1 ... H_b =
  * I - V T V^T, and the trailing columns A2 := A2 - V (T^T (V^T A2)) as matrix
- * products.  Sums of squares are formed without scaling: entries whose
- * squares overflow are outside the contract.  Asynchronous on the handle's
- * stream; the column-block kernel's workgroups wait for each other (bounded
- * waits, an expiry reported by lupp_sync as LUPP_ERR_INTERNAL).
+ * products; the columns right of each 128-column outer block get one such
+ * update with its 128 reflectors.  With LUPP_OPT_LOOKAHEAD >= 1 (default),
+ * large steps factor the next outer block on the handle's CU-partitioned
+ * streams while the rest of the update runs beside it (same result, bit for
+ * bit); that work is joined back into the handle's stream before the call's
+ * last operation, so ordering on the handle's stream and lupp_sync cover it.
+ * Sums of squares are formed without scaling: entries whose squares
+ * overflow are outside the contract.  Asynchronous on the handle's stream;
+ * the column-block kernel's workgroups wait for each other (bounded waits, an
+ * expiry reported by lupp_sync as LUPP_ERR_INTERNAL).
  * Size limit: m <= 131072 (LUPP_ERR_UNSUPPORTED beyond).
  * Errors: -2 m, -3 n, -4 dA, -5 lda, -6 dtau.
  */
@@ -481,8 +487,12 @@ int lupp_dgeqrf(lupp_handle_t h, int64_t m, int64_t n, double* dA, int64_t lda, 
  *           (that factor is then not formed)
  * Singular vectors of each small SVD are fixed up to sign, so T's rows and
  * columns and U's and V's columns are determined up to sign.  Asynchronous on
- * the handle's stream; workspace in the handle (about 8 n x 64 + n x 128
- * values beside the QR path's).  Size limit: n <= 131072.
+ * the handle's stream.  Each step's SVD and the products with it run on a
+ * second stream of the handle, and the products of U and V with the
+ * Householder factors on a third; both are joined back into the handle's
+ * stream before the call's last operation, so ordering on the handle's stream
+ * and lupp_sync cover them.  Workspace in the handle: about 14 n x 64 + 3 n x 128
+ * values beside the QR path's.  Size limit: n <= 131072.
  * Errors: -2 n, -3 dA, -4 lda, -5 q, -6 dG, -7 ldg, -9 ldu, -11 ldv.
  */
 int lupp_drandutv(lupp_handle_t h, int64_t n, double* dA, int64_t lda, int32_t q, const double* dG, int64_t ldg,
