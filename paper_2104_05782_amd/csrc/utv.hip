@@ -84,15 +84,37 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
+// 1/x and 1/sqrt(x) from the hardware's seeds, each refined by two Newton
+// steps (y' = y (2 - x y) and y' = y (3/2 - x y^2 / 2)): accurate to a few
+// units in the last place, not correctly rounded, and much shorter than the
+// division and square-root sequences.  x > 0, finite and normal.
+__device__ __forceinline__ double rcp_newton(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double rsqrt_newton(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
+}
+
 // Jacobi rotation of the pair with squared norms al, be and product ga:
-// false when the pair is orthogonal to working accuracy.  t = tan(theta)
-// makes the rotated pair orthogonal; the squared norms become al - t ga and
-// be + t ga.
+// false when the pair is orthogonal to working accuracy (ga^2 <= 1e-30 al be).
+// t = tan(theta) makes the rotated pair orthogonal: the smaller root of
+// t^2 + 2 zeta t - 1 = 0, zeta = (be - al) / (2 ga), written without zeta as
+// t = 2 ga sgn(be - al) / (|be - al| + sqrt((be - al)^2 + 4 ga^2)), so its
+// chain has one square root and one reciprocal; c = 1/sqrt(1 + t^2), s = c t.
+// The squared norms become al - t ga and be + t ga.
 __device__ __forceinline__ bool jacobi_rotation(double al, double be, double ga, double& c, double& sn, double& t) {
-  if (ga == 0.0 || !(fabs(ga) > 1e-15 * sqrt(al * be))) return false;
-  const double zeta = (be - al) / (2.0 * ga);
-  t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  c = 1.0 / sqrt(1.0 + t * t);
+  if (!(ga * ga > 1e-30 * (al * be))) return false;
+  const double d = be - al;
+  const double r = sqrt(fma(d, d, 4.0 * ga * ga));  // >= 2 |ga| > 0
+  t = (d >= 0.0 ? 2.0 * ga : -2.0 * ga) * rcp_newton(fabs(d) + r);
+  c = rsqrt_newton(fma(t, t, 1.0));  // 1 + t^2 in [1, 2]
   sn = c * t;
   return true;
 }
@@ -102,7 +124,7 @@ __device__ __forceinline__ bool jacobi_rotation(double al, double be, double ga,
 // M Vs = Us diag(sigma); the same rotations accumulate Vs.  Pairs follow a
 // round-robin tournament (32 disjoint pairs per round, 63 rounds per sweep;
 // columns beyond w are zero and never rotated with another); a pair is rotated
-// when |a_p . a_q| > 1e-15 sqrt(|a_p|^2 |a_q|^2), with tan(theta) from
+// when (a_p . a_q)^2 > 1e-30 |a_p|^2 |a_q|^2, with tan(theta) from
 // zeta = (|a_q|^2 - |a_p|^2) / (2 a_p . a_q).  Sweeps stop when no pair was
 // rotated (at most 40).  Then sigma_j = |a_j|, sorted decreasing (ties by
 // index), Us[:, j] = a_j / sigma_j (0 when sigma_j = 0).  One workgroup of 1024
