@@ -84,6 +84,43 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
+// Sums over the 64 lanes of a and b together.  After one exchange of each
+// (lane pairs), even lanes carry a's partial sums and odd lanes b's, so the
+// rest of the butterfly runs once for both: quads and the two row rotations
+// (DPP, they keep a lane's parity), then the row pairs and the wave halves by
+// the permlane swaps (v_permlane16_swap exchanges the odd rows of its first
+// operand with the even rows of its second, v_permlane32_swap the upper half
+// of the first with the lower half of the second: with both operands x, the
+// two results add up to the sum of partners 16, resp. 32, apart).  a's sum is
+// then in lane 0, b's in lane 1; both are returned to every lane.
+__device__ __forceinline__ double join_u32(uint32_t lo, uint32_t hi) {
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ double swap16_sum(double x) {
+  const uint64_t u = (uint64_t)__double_as_longlong(x);
+  const auto lo = __builtin_amdgcn_permlane16_swap((int)(uint32_t)u, (int)(uint32_t)u, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((int)(uint32_t)(u >> 32), (int)(uint32_t)(u >> 32), false, false);
+  return join_u32((uint32_t)lo[0], (uint32_t)hi[0]) + join_u32((uint32_t)lo[1], (uint32_t)hi[1]);
+}
+__device__ __forceinline__ double swap32_sum(double x) {
+  const uint64_t u = (uint64_t)__double_as_longlong(x);
+  const auto lo = __builtin_amdgcn_permlane32_swap((int)(uint32_t)u, (int)(uint32_t)u, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((int)(uint32_t)(u >> 32), (int)(uint32_t)(u >> 32), false, false);
+  return join_u32((uint32_t)lo[0], (uint32_t)hi[0]) + join_u32((uint32_t)lo[1], (uint32_t)hi[1]);
+}
+__device__ __forceinline__ void wave_sum2(double a, double b, int lane, double& sa, double& sb) {
+  a += dpp_f64<0xB1>(a);  // lane ^ 1
+  b += dpp_f64<0xB1>(b);
+  double x = (lane & 1) ? b : a;
+  x += dpp_f64<0x4E>(x);   // lane ^ 2
+  x += dpp_f64<0x124>(x);  // row rotation by 4
+  x += dpp_f64<0x128>(x);  // row rotation by 8
+  x = swap16_sum(x);
+  x = swap32_sum(x);
+  sa = readlane_d(x, 0);
+  sb = readlane_d(x, 1);
+}
+
 // 1/x and 1/sqrt(x) from the hardware's seeds, each refined by two Newton
 // steps (y' = y (2 - x y) and y' = y (3/2 - x y^2 / 2)): accurate to a few
 // units in the last place, not correctly rounded, and much shorter than the
@@ -188,8 +225,7 @@ __global__ __launch_bounds__(kSvdThreads) void k_utv_svd(int w, const double* __
         al[kk] = s_n2[p[kk]];
         be[kk] = s_n2[q[kk]];
       }
-#pragma unroll
-      for (int kk = 0; kk < 2; ++kk) ga[kk] = wave_sum(ap[kk] * aq[kk]);
+      wave_sum2(ap[0] * aq[0], ap[1] * aq[1], lane, ga[0], ga[1]);
       // both pairs' rotations in one pass over the lanes (even lanes: the
       // first pair, odd lanes: the second), then read back as scalars
       const int sel = lane & 1;
