@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_trsm_leaf(int w, int64_t ncols, const T
 // sent content into it.  The chains of C are resolved by pointer jumping.
 __global__ __launch_bounds__(kMaxSwaps) void k_swap_pairs(const int32_t* __restrict__ ipiv, int64_t k1, int64_t k2,
                                                           int64_t m, SwapPairs* __restrict__ out) {
-  __shared__ int32_t s_p[kMaxSwaps];
+  __shared__ __attribute__((aligned(16))) int32_t s_p[kMaxSwaps];
   __shared__ int32_t s_root[kMaxSwaps];
   __shared__ int32_t s_wext[kMaxSwaps / 64];
   const int i = threadIdx.x;
@@ -115,15 +115,21 @@ __global__ __launch_bounds__(kMaxSwaps) void k_swap_pairs(const int32_t* __restr
     s_p[i] = p;
   }
   __syncthreads();
+  // scan of every interchange, four per 16-byte LDS read and without
+  // branches (a branch per entry puts an LDS round trip on each one)
   int prev_b = -1, last_p = -1;
   bool later_p = false;
-  for (int j = 0; j < S; ++j) {
-    const int32_t q = s_p[j];
-    if (j < i) {
-      if (q == self) prev_b = j;
-      if (q == p) last_p = j;
-    } else if (j > i && q == p) {
-      later_p = true;
+#pragma unroll 4
+  for (int j0 = 0; j0 < S; j0 += 4) {
+    const int4 q4 = *reinterpret_cast<const int4*>(&s_p[j0]);
+    const int32_t qv[4] = {q4.x, q4.y, q4.z, q4.w};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + u;
+      const bool before = j < i && j < S, after = j > i && j < S;
+      prev_b = (before && qv[u] == self) ? j : prev_b;
+      last_p = (before && qv[u] == p) ? j : last_p;
+      later_p = later_p || (after && qv[u] == p);
     }
   }
   if (act) s_root[i] = prev_b < 0 ? i : prev_b;
