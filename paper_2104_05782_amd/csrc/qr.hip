@@ -139,38 +139,53 @@ __global__ __launch_bounds__(NT) void k_qr_panel(int64_t r, int w, double* __res
         lds_barrier();  // s_wp is reused below
         // 3. every wavefront adds the records of workgroups wave, wave + NW, ...
         //    (lane = word); wavefront 0 also reads row j
-        // (all of a wavefront's records loaded together, then tag-checked)
-        constexpr int RPW = kQrMaxGroups / NW;
-        uint64_t u[RPW];
-        {
-          long spins = 0;
-          for (;;) {
-            bool ok = true;
-#pragma unroll
-            for (int t = 0; t < RPW; ++t) {
-              const int q = wave + NW * t;
-              if (q < G) {
-                u[t] = qld(&ws->rec[par][q][lane]);
-                ok &= (uint32_t)(u[t] >> 32) == tag;
-              }
-            }
-            if (__all(ok)) break;
-            if (++spins > kQrSpin || s_broken) {
-              if (lane == 0) {
-                __hip_atomic_store(&ws->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                s_broken = 1;
-              }
-              break;
-            }
-          }
-        }
+        // Records in chunks of RC: a chunk's loads are issued together, then
+        // tag-checked (a check inside each load's block would make every load
+        // wait for the one before), then its exchanges, then the sum in record
+        // order.  A chunk wholly past the last workgroup is skipped.
+        constexpr int RC = 8, RPW = kQrMaxGroups / NW;
+        static_assert(RPW % RC == 0, "record chunks");
         double acc = 0.0;
+        long spins = 0;
 #pragma unroll
-        for (int t = 0; t < RPW; ++t) {
-          const int q = wave + NW * t;
-          if (q < G) {  // uniform in the wavefront
-            const uint32_t lo = (uint32_t)__shfl_down((int)(uint32_t)u[t], 1, 64);
-            acc += __longlong_as_double((long long)(((uint64_t)(uint32_t)u[t] << 32) | lo));
+        for (int t0 = 0; t0 < RPW; t0 += RC) {
+          if (wave + NW * t0 < G) {  // uniform in the wavefront
+            uint64_t u[RC];
+#pragma unroll
+            for (int t = 0; t < RC; ++t) u[t] = 0;
+            for (;;) {
+#pragma unroll
+              for (int t = 0; t < RC; ++t) {
+                const int q = wave + NW * (t0 + t);
+                if (q < G) u[t] = qld(&ws->rec[par][q][lane]);
+              }
+              bool ok = true;
+#pragma unroll
+              for (int t = 0; t < RC; ++t) {
+                const int q = wave + NW * (t0 + t);
+                if (q < G) ok &= (uint32_t)(u[t] >> 32) == tag;
+              }
+              if (__all(ok)) break;
+              if (++spins > kQrSpin || s_broken) {
+                if (lane == 0) {
+                  __hip_atomic_store(&ws->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                  s_broken = 1;
+                }
+                break;
+              }
+            }
+            uint32_t lo[RC];
+#pragma unroll
+            for (int t = 0; t < RC; ++t) {
+              const int q = wave + NW * (t0 + t);
+              lo[t] = 0;
+              if (q < G) lo[t] = (uint32_t)__shfl_down((int)(uint32_t)u[t], 1, 64);
+            }
+#pragma unroll
+            for (int t = 0; t < RC; ++t) {
+              const int q = wave + NW * (t0 + t);
+              if (q < G) acc += __longlong_as_double((long long)(((uint64_t)(uint32_t)u[t] << 32) | lo[t]));
+            }
           }
         }
         if ((lane & 1) == 0) s_wp[wave][lane >> 1] = acc;
