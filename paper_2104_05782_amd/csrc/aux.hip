@@ -323,12 +323,17 @@ __global__ __launch_bounds__(kLeftGatherThreads) void k_left_gather(T* __restric
   T* col = A + c * lda;
   T* dst = col + r0;
   const int tid = threadIdx.x;
-  T v[R];
+  // all map entries, then all values, at indices clamped into the column
+  // (a guarded load per element would wait for the one before it)
+  int32_t src[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = tid + r * kLeftGatherThreads;
-    if (i < len) v[r] = col[(uint32_t)map[i]];
+    src[r] = map[i < len ? i : len - 1];
   }
+  T v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = col[(uint32_t)src[r]];
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < R; ++r) {

@@ -302,12 +302,17 @@ __global__ __launch_bounds__(256) void k_lp_pack_a(int64_t M, int64_t K, const f
     const int row = c & 127, g = c >> 7;
     const int64_t gr = (int64_t)tm * 128 + row;
     const int64_t k0 = (int64_t)kc * 32 + 8 * g;
+    // loads at indices clamped into A, then the selects (a guarded load per
+    // value would wait for the one before it)
+    const int64_t grc = gr < M ? gr : M - 1;
     float v[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int64_t k = k0 + t;
-      v[t] = (gr < M && k < K) ? A[gr + k * lda] * f : 0.0f;
+      v[t] = A[grc + (k < K ? k : K - 1) * lda];
     }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = (gr < M && k0 + t < K) ? v[t] * f : 0.0f;
     *(typename L::packed*)(out + ((size_t)((int64_t)tm * KC + kc) * 128 + row) * ROWB + g * L::kBytes) =
         L::pack(v);
   }
@@ -330,12 +335,15 @@ __global__ __launch_bounds__(256) void k_lp_pack_b(int64_t K, int64_t N, const f
     const int g = c & 3, col = c >> 2;
     const int64_t gc = (int64_t)tn * 128 + col;
     const int64_t k0 = (int64_t)kc * 32 + 8 * g;
+    const int64_t gcc = gc < N ? gc : N - 1;
     float v[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int64_t k = k0 + t;
-      v[t] = (gc < N && k < K) ? B[k + gc * ldb] * f : 0.0f;
+      v[t] = B[(k < K ? k : K - 1) + gcc * ldb];
     }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = (gc < N && k0 + t < K) ? v[t] * f : 0.0f;
     *(typename L::packed*)(out + ((size_t)((int64_t)tn * KC + kc) * 128 + col) * ROWB + g * L::kBytes) =
         L::pack(v);
   }
