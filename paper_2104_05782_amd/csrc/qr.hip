@@ -405,9 +405,14 @@ __device__ __forceinline__ void larft_merge(double (*sT)[kQrNB + 1], const doubl
   double g = Gm[(o + ii) + (o + W) * kQrNB];
   for (int l = 0; l < lend; ++l) {
     const double gn = (l + 1 < lend) ? Gm[(o + ii) + (o + W + l + 1) * kQrNB] : 0.0;
+    // every column's value read, the terms with l > c selected away (adding
+    // +0.0 leaves a sum that started at +0.0 unchanged; a guarded read per
+    // column would wait for the one before it)
+    double tv[CR];
 #pragma unroll
-    for (int u = 0; u < CR; ++u)
-      if (l <= c0 + u) acc[u] += g * sT[o + W + l][o + W + c0 + u];
+    for (int u = 0; u < CR; ++u) tv[u] = sT[o + W + l][o + W + c0 + u];
+#pragma unroll
+    for (int u = 0; u < CR; ++u) acc[u] += (l <= c0 + u) ? g * tv[u] : 0.0;
     g = gn;
   }
 #pragma unroll
