@@ -492,11 +492,25 @@ __global__ __launch_bounds__(NT) void k_panel_block(int64_t r, int wt, T* __rest
             for (int c = 0; c < W; ++c) a[c] = prow[c];
           }
           if (rok && i > jg) {
-            const T l = a[j] / pv;
-            a[j] = l;
+            if constexpr (sizeof(T) == 4) {
+              // the pivot row's values read before the division, so the reads
+              // are in flight during it (FP32 only: in FP64 the values do
+              // not fit the registers beside the row)
+              T pr[W];
 #pragma unroll
-            for (int c = 0; c < W; ++c)
-              if (c > j) a[c] = a[c] - l * prow[c];
+              for (int c = 0; c < W; ++c) pr[c] = (c > j) ? prow[c] : T(0);
+              const T l = a[j] / pv;
+              a[j] = l;
+#pragma unroll
+              for (int c = 0; c < W; ++c)
+                if (c > j) a[c] = a[c] - l * pr[c];
+            } else {
+              const T l = a[j] / pv;
+              a[j] = l;
+#pragma unroll
+              for (int c = 0; c < W; ++c)
+                if (c > j) a[c] = a[c] - l * prow[c];
+            }
           }
         }
       }
